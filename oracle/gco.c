@@ -1,0 +1,868 @@
+/*
+ * gco.c -- plain, slow FP64 CPU oracle for Newtonian ray tracing of the
+ * grating cloak (Halimeh, Schmied, Wegener, Opt. Express 2010).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the GPU library: every quantity
+ * here is written out again from the paper's equations.
+ *
+ * What is computed, in the paper's order:
+ *   - the index profile, eq. (1), with the principal Lambert function W0 of
+ *     eq. (13) evaluated by Halley iteration from a cold start;
+ *   - its gradient, eq. (12), and the ray acceleration used for integration,
+ *     grad(n^2)/2 = n grad n (Sec. 3);
+ *   - the trochoid grating of eq. (2) (height S(x) by solving the Kepler-type
+ *     equation x = xi - A sin(k xi)), and its normal;
+ *   - straight rays in air, Snell refraction at the cloak/air interface, and
+ *     mirror reflection at the metal grating (Sec. 3 and Sec. 4);
+ *   - Newton-type ray equation inside the cloak (Sec. 3, eq. (11)), written in
+ *     the equivalent parameter tau with dr/dtau = p, dp/dtau = grad(n^2)/2 and
+ *     |p| = n (dt = n^2 dtau turns it into eq. (11));
+ *   - pinhole camera, procedural sky, image averaging;
+ *   - mean subtraction and zero-shift cross-correlation, eqs. (14), (15).
+ *
+ * Readings where the paper is silent (integrator, event rules, camera, sky,
+ * colour handling) follow the project's design notes; each is restated at the
+ * function that implements it.
+ *
+ * Parameter blocks are flat arrays so that this file needs no header shared
+ * with anything else:
+ *   scene[8]  = { Lambda, A, half_width, y_top, cloak, mirror, sky_K, unused }
+ *               cloak: 0 -> n = 1 everywhere, 1 -> eq. (1) inside the box
+ *               mirror: 0 -> trochoid eq. (2), 1 -> flat mirror y = 0
+ *   opts[10]  = { integrator (0 RK4, 1 DOPRI5), h, rtol, atol, h_max,
+ *                 max_events, max_steps, h0, h_min, diagnostics }
+ *   camera[12]= { eye xyz, target xyz, fov_y_deg, width, height, spp,
+ *                 jitter, scene_index }  (seed passed separately)
+ */
+#include <complex.h>
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define ORC_PI 3.14159265358979323846
+
+enum { RAY_OK = 0, RAY_MAX_STEPS = 1, RAY_MAX_EVENTS = 2, RAY_NONFINITE = 3,
+       RAY_STEP_UNDERFLOW = 4 };
+
+typedef struct {
+    double L, A, hw, ytop, K;
+    int cloak, mirror;
+    double k, e;   /* k = 2 pi / Lambda, e = A k */
+} oscene;
+
+typedef struct {
+    int integ;
+    double h, rtol, atol, hmax, h0, hmin;
+    long max_events;
+    long max_steps;
+    int diag;      /* 1: record the drift of |p|^2 - n^2 at every accepted step */
+} oopts;
+
+static void load_scene(const double* s, oscene* o)
+{
+    o->L = s[0]; o->A = s[1]; o->hw = s[2]; o->ytop = s[3];
+    o->cloak = (int)s[4]; o->mirror = (int)s[5]; o->K = s[6];
+    o->k = 2.0 * ORC_PI / o->L;
+    o->e = o->A * o->k;
+}
+
+static void load_opts(const double* p, oopts* o)
+{
+    o->integ = (int)p[0]; o->h = p[1]; o->rtol = p[2]; o->atol = p[3];
+    o->hmax = p[4]; o->max_events = (long)p[5]; o->max_steps = (long)p[6];
+    o->h0 = p[7]; o->hmin = p[8]; o->diag = (int)p[9];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lambert W, principal branch (eq. (13) names it; Sec. 2).                  */
+/* Halley's iteration for w e^w = z (Corless, Gonnet, Hare, Jeffrey, Knuth,  */
+/* Adv. Comput. Math. 5 (1996)), tried from these starts in turn:            */
+/*   |z| < 1/4           : Taylor series  z - z^2 + 3 z^3 / 2                */
+/*   |z + 1/e| < 0.3     : branch-point series -1 + p - p^2/3 + 11 p^3 / 72, */
+/*                         p = sqrt(2 (e z + 1)), principal square root     */
+/*   always              : log(1 + z), then the asymptotic form              */
+/*                         L1 - L2 + L2 / L1 with L1 = log z, L2 = log L1    */
+/* The cut is z in (-inf, -1/e]; on it the value continuous from above is    */
+/* taken (complex.h's log/sqrt follow the sign of a zero imaginary part).    */
+/* Returns 0 when converged with |w e^w - z| <= 1e-14 max(|z|, 1e-300) and w */
+/* inside the image of the principal branch, 1 otherwise.                    */
+/* ------------------------------------------------------------------------ */
+static int w0_in_principal_range(cplx w)
+{
+    double a = creal(w), b = cimag(w);
+    if (fabs(b) >= ORC_PI) return 0;
+    if (b == 0.0) return a >= -1.0 - 1e-12;
+    /* boundary of the principal range: a = -b cot b */
+    return a > -b * cos(b) / sin(b) - 1e-10;
+}
+
+static int w0_halley(cplx z, cplx w, cplx* out)
+{
+    for (int it = 0; it < 64; ++it) {
+        cplx ew = cexp(w);
+        cplx f = w * ew - z;
+        cplx wp1 = w + 1.0;
+        if (wp1 == 0.0) break;   /* exactly at the branch point */
+        cplx d = f / (ew * wp1 - (w + 2.0) * f / (2.0 * wp1));
+        w -= d;
+        if (!(cabs(d) > 4.0 * DBL_EPSILON * fmax(1.0, cabs(w)))) break;
+    }
+    *out = w;
+    double res = cabs(w * cexp(w) - z);
+    int ok = isfinite(creal(w)) && isfinite(cimag(w)) &&
+             res <= 1e-14 * fmax(cabs(z), 1e-300) && w0_in_principal_range(w);
+    return ok ? 0 : 1;
+}
+
+static int orc_w0(cplx z, cplx* out)
+{
+    const double E = 2.71828182845904523536;
+    /* e split into a double plus a small correction so that e z + 1 keeps
+       its low bits near the branch point */
+    const double E_LO = 1.4456468917292502e-16;
+    double az = cabs(z);
+    if (az == 0.0) { *out = 0.0; return 0; }
+    cplx ezp1 = (E * z + 1.0) + E_LO * z;
+    cplx p = csqrt(2.0 * ezp1);
+    cplx L1 = clog(z), L2 = clog(L1);
+    cplx guess[4];
+    int ng = 0;
+    if (az < 0.25) guess[ng++] = z - z * z + 1.5 * z * z * z;
+    if (cabs(z + 1.0 / E) < 0.3) guess[ng++] = -1.0 + p - p * p / 3.0 + 11.0 / 72.0 * p * p * p;
+    guess[ng++] = clog(1.0 + z);
+    guess[ng++] = L1 - L2 + L2 / L1;
+    /* the first start whose Halley limit passes the residual and the
+       principal-range checks wins; otherwise the first limit is returned */
+    cplx first = 0.0;
+    for (int g = 0; g < ng; ++g) {
+        cplx w;
+        if (w0_halley(z, guess[g], &w) == 0) { *out = w; return 0; }
+        if (g == 0) first = w;
+    }
+    *out = first;
+    return 1;
+}
+
+/* Argument of W0 in eq. (1): i c k e^{ik(x+iy)} with c = iA, i.e.
+   Z = -A k e^{-k y} (cos kx + i sin kx).  x is reduced modulo Lambda first
+   (the profile is Lambda-periodic in x). */
+static cplx orc_Z(const oscene* s, double x, double y)
+{
+    double xr = x - s->L * floor(x / s->L + 0.5);
+    double ph = s->k * xr;
+    double m = -s->e * exp(-s->k * y);
+    return m * cos(ph) + I * (m * sin(ph));
+}
+
+/* eq. (1): n = 1 / |1 + W0(Z)| (untruncated profile). */
+static double orc_index_raw(const oscene* s, double x, double y, int* bad)
+{
+    cplx w;
+    int r = orc_w0(orc_Z(s, x, y), &w);
+    if (bad) *bad |= r;
+    return 1.0 / cabs(1.0 + w);
+}
+
+/* Ray acceleration grad(n^2)/2 = n grad n for eq. (1).  With W = W0(Z):
+   a_x + i a_y = i k conj(W) (1 + W)^2 / |1 + W|^6.  (eq. (12) times n; the
+   test-suite checks the two against each other and against differences.) */
+static void orc_accel(const oscene* s, double x, double y, double* ax, double* ay, int* bad)
+{
+    cplx w;
+    int r = orc_w0(orc_Z(s, x, y), &w);
+    if (bad) *bad |= r;
+    cplx d = 1.0 + w;
+    double d2 = creal(d) * creal(d) + cimag(d) * cimag(d);
+    cplx a = I * s->k * conj(w) * d * d / (d2 * d2 * d2);
+    *ax = creal(a);
+    *ay = cimag(a);
+}
+
+/* eq. (12), literally: grad n in terms of W0. */
+static void orc_grad_n_eq12(const oscene* s, double x, double y, double* gx, double* gy)
+{
+    cplx w;
+    orc_w0(orc_Z(s, x, y), &w);
+    double re1 = 1.0 + creal(w), im = cimag(w);
+    double m2 = re1 * re1 + im * im;
+    double m3 = m2 * sqrt(m2);
+    *gx = (2.0 * re1 * im / m2 - im) * s->k / m3;
+    *gy = ((im * im - re1 * re1) / m2 + re1) * s->k / m3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trochoid grating, eq. (2): x = xi - A sin(k xi), y = A cos(k xi).         */
+/* For given x, xi solves Kepler's equation M = E - e sin E with M = k x,    */
+/* E = k xi, eccentricity e = A k < 1 (unique root in [M - e, M + e]).       */
+/* Safeguarded Newton (bisection when Newton leaves the bracket).            */
+/* Returns the height S(x) = A cos(k xi); *Eout = k xi reduced to [-pi,pi).  */
+/* ------------------------------------------------------------------------ */
+static double orc_surface(const oscene* s, double x, double* Eout)
+{
+    if (s->mirror == 1) { if (Eout) *Eout = 0.0; return 0.0; }
+    double N = floor(x / s->L + 0.5);
+    double M = s->k * (x - N * s->L);
+    double e = s->e;
+    double lo = M - e, hi = M + e;
+    double E = M + e * sin(M);
+    if (E < lo || E > hi) E = M;
+    for (int it = 0; it < 200; ++it) {
+        double f = E - e * sin(E) - M;
+        if (f > 0) hi = E; else lo = E;
+        double fp = 1.0 - e * cos(E);
+        double En = E - f / fp;
+        if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
+        double dE = En - E;
+        E = En;
+        if (fabs(dE) <= 1e-15 * fmax(1.0, fabs(E)) || hi - lo <= 1e-15) break;
+    }
+    if (Eout) *Eout = E;
+    return s->A * cos(E);
+}
+
+/* Upward unit normal of the grating at parameter E = k xi (points out of the
+   metal, +y side).  From eq. (2): tangent (1 - e cos E, -e sin E). */
+static void orc_grating_normal(const oscene* s, double E, double* nx, double* ny)
+{
+    if (s->mirror == 1) { *nx = 0.0; *ny = 1.0; return; }
+    double a = s->e * sin(E), b = 1.0 - s->e * cos(E);
+    double r = sqrt(a * a + b * b);
+    *nx = a / r;
+    *ny = b / r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray state and integrators.                                                */
+/* Only (x, y, px, py) evolve non-trivially: n does not depend on z, so p_z  */
+/* is constant and z advances by p_z per unit tau.                           */
+/* ------------------------------------------------------------------------ */
+typedef struct { double v[4]; } st4;   /* x, y, px, py */
+
+static void rhs(const oscene* s, const st4* u, st4* du, int* bad)
+{
+    double ax, ay;
+    orc_accel(s, u->v[0], u->v[1], &ax, &ay, bad);
+    du->v[0] = u->v[2];
+    du->v[1] = u->v[3];
+    du->v[2] = ax;
+    du->v[3] = ay;
+}
+
+static void axpy(st4* out, const st4* u, double h, const st4* k)
+{
+    for (int i = 0; i < 4; ++i) out->v[i] = u->v[i] + h * k->v[i];
+}
+
+/* Classical 4-stage Runge-Kutta step of size h. */
+static void rk4_step(const oscene* s, const st4* u, double h, st4* out, int* bad)
+{
+    st4 k1, k2, k3, k4, t;
+    rhs(s, u, &k1, bad);
+    axpy(&t, u, 0.5 * h, &k1); rhs(s, &t, &k2, bad);
+    axpy(&t, u, 0.5 * h, &k2); rhs(s, &t, &k3, bad);
+    axpy(&t, u, h, &k3);       rhs(s, &t, &k4, bad);
+    for (int i = 0; i < 4; ++i)
+        out->v[i] = u->v[i] + (h / 6.0) * (k1.v[i] + 2.0 * k2.v[i] + 2.0 * k3.v[i] + k4.v[i]);
+}
+
+/* Dormand-Prince 5(4) tableau (Dormand & Prince, J. Comput. Appl. Math. 6
+   (1980) 19-26): 5th-order solution propagated, 4th-order embedded for the
+   error estimate, first-same-as-last. */
+static const double DP_A[7][6] = {
+    { 0 },
+    { 1.0 / 5 },
+    { 3.0 / 40, 9.0 / 40 },
+    { 44.0 / 45, -56.0 / 15, 32.0 / 9 },
+    { 19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729 },
+    { 9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656 },
+    { 35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84 },
+};
+static const double DP_B5[7] = { 35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0.0 };
+static const double DP_B4[7] = { 5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
+                                 -92097.0 / 339200, 187.0 / 2100, 1.0 / 40 };
+
+/* One DOPRI5 step of size h from u with k1 = f(u) given.  Writes the 5th
+   order result, the 4th order result and k7 = f(result). */
+static void dp5_step(const oscene* s, const st4* u, const st4* k1, double h,
+                     st4* y5, st4* y4, st4* k7, int* bad)
+{
+    st4 K[7];
+    K[0] = *k1;
+    for (int st = 1; st < 7; ++st) {
+        st4 t = *u;
+        for (int j = 0; j < st; ++j)
+            for (int i = 0; i < 4; ++i) t.v[i] += h * DP_A[st][j] * K[j].v[i];
+        if (st == 6) *y5 = t;
+        rhs(s, &t, &K[st], bad);
+    }
+    for (int i = 0; i < 4; ++i) {
+        double a5 = 0.0, a4 = 0.0;
+        for (int j = 0; j < 7; ++j) { a5 += DP_B5[j] * K[j].v[i]; a4 += DP_B4[j] * K[j].v[i]; }
+        y5->v[i] = u->v[i] + h * a5;
+        y4->v[i] = u->v[i] + h * a4;
+    }
+    *k7 = K[6];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Box B = { |x| <= hw, y <= y_top, y above the grating } (cloak = 1).       */
+/* Event functions, all >= 0 inside B.                                       */
+/* ------------------------------------------------------------------------ */
+enum { EV_NONE = -1, EV_TOP = 0, EV_RIGHT = 1, EV_LEFT = 2, EV_GRATING = 3 };
+
+static double event_value(const oscene* s, int ev, const st4* u)
+{
+    switch (ev) {
+    case EV_TOP:   return s->ytop - u->v[1];
+    case EV_RIGHT: return s->hw - u->v[0];
+    case EV_LEFT:  return s->hw + u->v[0];
+    default:       return u->v[1] - orc_surface(s, u->v[0], NULL);
+    }
+}
+
+/* Snell's law at a planar face with unit normal nf (pointing from medium 1
+   into medium 2): the tangential part of p is kept and the normal part is
+   chosen so that |p'| = n2.  Total internal reflection when n2^2 < |p_t|^2:
+   mirror reflection about the face.  Returns 1 if transmitted. */
+static int snell(double p[3], const double nf[3], double n2)
+{
+    double pn = p[0] * nf[0] + p[1] * nf[1] + p[2] * nf[2];
+    double pt[3] = { p[0] - pn * nf[0], p[1] - pn * nf[1], p[2] - pn * nf[2] };
+    double pt2 = pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2];
+    double q = n2 * n2 - pt2;
+    if (q < 0.0) {
+        for (int i = 0; i < 3; ++i) p[i] -= 2.0 * pn * nf[i];
+        return 0;
+    }
+    double pnn = (pn >= 0.0 ? 1.0 : -1.0) * sqrt(q);
+    for (int i = 0; i < 3; ++i) p[i] = pt[i] + pnn * nf[i];
+    return 1;
+}
+
+static void reflect(double p[3], double nx, double ny)
+{
+    double pn = p[0] * nx + p[1] * ny;
+    p[0] -= 2.0 * pn * nx;
+    p[1] -= 2.0 * pn * ny;
+}
+
+/* First contact of the straight line r + t d (t > 0, d in the xy-plane
+   projection) with the metal surface.  Returns +inf if none.
+   g(t) = y(t) - S(x(t)) >= 0 above the metal.  |S'(x)| <= e / sqrt(1 - e^2)
+   (maximum slope of the trochoid), so |g'| <= L with
+   L = |d_y| + |d_x| e / sqrt(1 - e^2): marching with steps g/L never steps
+   over a crossing.  A minimum step of 1e-9 guarantees progress near
+   tangency.  The bracket is then refined by bisection to 1e-15. */
+static double air_contact(const oscene* s, const double r[3], const double d[3])
+{
+    double x0 = r[0], y0 = r[1], dx = d[0], dy = d[1];
+    if (s->mirror == 1 || s->A == 0.0) {
+        if (dy < 0.0 && y0 > 0.0) return -y0 / dy;
+        if (dy < 0.0 && y0 >= 0.0) return 0.0;
+        return INFINITY;
+    }
+    double A = s->A;
+    double t0 = 0.0, t1;
+    if (dy < 0.0) {
+        if (y0 > A) t0 = (A - y0) / dy;
+        t1 = (-A - y0) / dy * (1.0 + 1e-12);   /* just below the troughs */
+    } else if (dy > 0.0) {
+        if (y0 >= A) return INFINITY;
+        t1 = (A - y0) / dy;
+    } else {
+        if (y0 > A || y0 < -A || dx == 0.0) return INFINITY;
+        t1 = s->L / fabs(dx);
+    }
+    double L = fabs(dy) + fabs(dx) * s->e / sqrt(1.0 - s->e * s->e);
+    double t = t0, tprev = t0;
+    /* a ray that starts on the surface (just reflected) is not in contact */
+    int at_origin = (t0 == 0.0);
+    for (long it = 0; it < 100000000L; ++it) {
+        double g = y0 + t * dy - orc_surface(s, x0 + t * dx, NULL);
+        if (g <= 0.0 && !(at_origin && t == t0)) {
+            if (t == t0) return t0;   /* touches the surface where it enters the band */
+            double lo = tprev, hi = t;
+            for (int b = 0; b < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++b) {
+                double mid = 0.5 * (lo + hi);
+                double gm = y0 + mid * dy - orc_surface(s, x0 + mid * dx, NULL);
+                if (gm <= 0.0) hi = mid; else lo = mid;
+            }
+            return hi;
+        }
+        if (t >= t1) return INFINITY;
+        tprev = t;
+        double step = (g > 0.0 ? g : 0.0) / L;
+        if (step < 1e-9) step = 1e-9;
+        t += step;
+        if (t > t1) t = t1;
+    }
+    return INFINITY;
+}
+
+/* Entry of the straight line into the cloak box from air.  Faces: top
+   (y = y_top, |x| <= hw), right (x = hw) and left (x = -hw), the side faces
+   spanning from the grating height at that x up to y_top. */
+static double air_box_entry(const oscene* s, const double r[3], const double d[3], int* face)
+{
+    double best = INFINITY;
+    *face = EV_NONE;
+    if (!s->cloak) return best;
+    if (d[1] < 0.0 && r[1] > s->ytop) {
+        double t = (s->ytop - r[1]) / d[1];
+        double xe = r[0] + t * d[0];
+        if (fabs(xe) <= s->hw && t < best) { best = t; *face = EV_TOP; }
+    }
+    if (d[0] < 0.0 && r[0] > s->hw) {
+        double t = (s->hw - r[0]) / d[0];
+        double ye = r[1] + t * d[1];
+        if (ye <= s->ytop && ye >= orc_surface(s, s->hw, NULL) && t < best) { best = t; *face = EV_RIGHT; }
+    }
+    if (d[0] > 0.0 && r[0] < -s->hw) {
+        double t = (-s->hw - r[0]) / d[0];
+        double ye = r[1] + t * d[1];
+        if (ye <= s->ytop && ye >= orc_surface(s, -s->hw, NULL) && t < best) { best = t; *face = EV_LEFT; }
+    }
+    return best;
+}
+
+static void face_normal(int face, double nf[3])
+{
+    nf[0] = nf[1] = nf[2] = 0.0;
+    if (face == EV_TOP) nf[1] = 1.0;
+    else if (face == EV_RIGHT) nf[0] = 1.0;
+    else nf[0] = -1.0;
+}
+
+typedef struct {
+    long steps;       /* accepted integrator steps inside the box */
+    long rejected;    /* rejected DOPRI5 attempts */
+    long events;      /* box entries, exits, internal reflections, grating contacts */
+    long contacts;    /* grating reflections */
+    double min_cos;   /* smallest |p_hat . N| over all contacts and face crossings */
+    long bad_w;       /* Lambert-W evaluations that failed their check */
+    double max_H;     /* diagnostics: max | |p|^2 - n^2 | / n^2 at step ends */
+} trace_info;
+
+static int all_finite(const double* a, int n)
+{
+    for (int i = 0; i < n; ++i) if (!isfinite(a[i])) return 0;
+    return 1;
+}
+
+/* Integration inside the box from (r, p) on entry until the ray leaves B
+   through a face into air.  Grating contacts and total internal reflections
+   at faces are handled inside.  Returns a ray status; on RAY_OK, r and p hold
+   the exit point and the refracted momentum (|p| = 1). */
+static int integrate_box(const oscene* s, const oopts* o, double r[3], double p[3],
+                         trace_info* ti)
+{
+    st4 u = { { r[0], r[1], p[0], p[1] } };
+    double z = r[2], pz = p[2];
+    double h = (o->integ == 0) ? o->h : o->h0;
+    int last_rej = 0;
+    int bad = 0;
+    st4 k1;
+    int have_k1 = 0;
+    for (;;) {
+        if (ti->steps >= o->max_steps) return RAY_MAX_STEPS;
+        st4 y5, y4, k7;
+        double hs = h, hnext = h;
+        if (o->integ == 0) {
+            rk4_step(s, &u, h, &y5, &bad);
+        } else {
+            if (!have_k1) { rhs(s, &u, &k1, &bad); have_k1 = 1; }
+            dp5_step(s, &u, &k1, h, &y5, &y4, &k7, &bad);
+            double acc = 0.0;
+            for (int i = 0; i < 4; ++i) {
+                double sc = o->atol + o->rtol * fmax(fabs(u.v[i]), fabs(y5.v[i]));
+                double q = (y5.v[i] - y4.v[i]) / sc;
+                acc += q * q;
+            }
+            double err = sqrt(acc / 4.0);
+            if (!isfinite(err)) return RAY_NONFINITE;
+            if (err > 1.0) {
+                double fac = 0.9 * pow(err, -0.2);
+                if (fac < 0.2) fac = 0.2;
+                h *= fac;
+                last_rej = 1;
+                ti->rejected++;
+                if (h < o->hmin) return RAY_STEP_UNDERFLOW;
+                continue;
+            }
+            double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+            if (fac > 5.0) fac = 5.0;
+            if (fac < 0.2) fac = 0.2;
+            if (last_rej && fac > 1.0) fac = 1.0;
+            last_rej = 0;
+            hnext = h * fac;
+            if (hnext > o->hmax) hnext = o->hmax;
+        }
+        ti->steps++;
+        if (!all_finite(y5.v, 4)) return RAY_NONFINITE;
+        /* events at the end of the step */
+        int hit = EV_NONE;
+        double theta = 2.0;
+        for (int ev = 0; ev < 4; ++ev) {
+            if (event_value(s, ev, &y5) >= 0.0) continue;
+            /* smallest theta in (0, 1] with the event function of the partial
+               step crossing zero: bisection over the partial step size. */
+            double lo = 0.0, hi = 1.0;
+            while (hi - lo > 1e-14) {
+                double mid = 0.5 * (lo + hi);
+                st4 ym, y4m, k7m;
+                if (o->integ == 0) rk4_step(s, &u, mid * hs, &ym, &bad);
+                else dp5_step(s, &u, &k1, mid * hs, &ym, &y4m, &k7m, &bad);
+                if (event_value(s, ev, &ym) < 0.0) hi = mid; else lo = mid;
+            }
+            if (hi < theta) { theta = hi; hit = ev; }
+        }
+        if (o->diag) {
+            double n = orc_index_raw(s, y5.v[0], y5.v[1], NULL);
+            double H = fabs(y5.v[2] * y5.v[2] + y5.v[3] * y5.v[3] + pz * pz - n * n) / (n * n);
+            if (H > ti->max_H) ti->max_H = H;
+        }
+        if (hit == EV_NONE) {
+            u = y5;
+            z += pz * hs;
+            if (o->integ == 1) { k1 = k7; h = hnext; }
+            continue;
+        }
+        /* advance to the event with the partial step */
+        {
+            st4 ye, y4e, k7e;
+            if (o->integ == 0) rk4_step(s, &u, theta * hs, &ye, &bad);
+            else dp5_step(s, &u, &k1, theta * hs, &ye, &y4e, &k7e, &bad);
+            u = ye;
+            z += pz * theta * hs;
+        }
+        h = (o->integ == 0) ? o->h : hnext;
+        have_k1 = 0;
+        if (++ti->events > o->max_events) return RAY_MAX_EVENTS;
+        double pp[3] = { u.v[2], u.v[3], pz };
+        double pabs = sqrt(pp[0] * pp[0] + pp[1] * pp[1] + pp[2] * pp[2]);
+        if (hit == EV_GRATING) {
+            double E, nx, ny;
+            orc_surface(s, u.v[0], &E);
+            orc_grating_normal(s, E, &nx, &ny);
+            double c = fabs(pp[0] * nx + pp[1] * ny) / pabs;
+            if (c < ti->min_cos) ti->min_cos = c;
+            reflect(pp, nx, ny);
+            ti->contacts++;
+            u.v[2] = pp[0]; u.v[3] = pp[1];
+            continue;
+        }
+        /* face crossing from inside: n1 = eq. (1) at the crossing, n2 = 1 */
+        double nf[3];
+        face_normal(hit, nf);
+        {
+            double c = fabs(pp[0] * nf[0] + pp[1] * nf[1]) / pabs;
+            if (c < ti->min_cos) ti->min_cos = c;
+        }
+        int through = snell(pp, nf, 1.0);
+        u.v[2] = pp[0]; u.v[3] = pp[1];
+        if (!through) continue;   /* total internal reflection: stay inside */
+        r[0] = u.v[0]; r[1] = u.v[1]; r[2] = z;
+        p[0] = pp[0]; p[1] = pp[1]; p[2] = pp[2];
+        if (bad) ti->bad_w++;
+        return RAY_OK;
+    }
+}
+
+/* Full path of one ray from (org, dir) until it escapes to the sky.
+   Returns the ray status; exit position and unit direction in out_*. */
+static int trace_one(const oscene* s, const oopts* o, const double org[3], const double dir[3],
+                     double out_org[3], double out_dir[3], trace_info* ti)
+{
+    double r[3] = { org[0], org[1], org[2] };
+    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double p[3] = { dir[0] / nd, dir[1] / nd, dir[2] / nd };
+    memset(ti, 0, sizeof(*ti));
+    ti->min_cos = 1.0;
+    for (;;) {
+        if (!all_finite(r, 3) || !all_finite(p, 3)) return RAY_NONFINITE;
+        /* in air: straight line (the acceleration of eq. (11) vanishes) */
+        int face;
+        double tb = air_box_entry(s, r, p, &face);
+        double tg = air_contact(s, r, p);
+        if (!isfinite(tb) && !isfinite(tg)) {
+            for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
+            return RAY_OK;
+        }
+        if (++ti->events > o->max_events) return RAY_MAX_EVENTS;
+        if (tg <= tb) {
+            for (int i = 0; i < 3; ++i) r[i] += tg * p[i];
+            double E, nx, ny;
+            orc_surface(s, r[0], &E);
+            orc_grating_normal(s, E, &nx, &ny);
+            double c = fabs(p[0] * nx + p[1] * ny);
+            if (c < ti->min_cos) ti->min_cos = c;
+            reflect(p, nx, ny);
+            ti->contacts++;
+            continue;
+        }
+        for (int i = 0; i < 3; ++i) r[i] += tb * p[i];
+        if (face == EV_TOP) r[1] = s->ytop;
+        else if (face == EV_RIGHT) r[0] = s->hw;
+        else r[0] = -s->hw;
+        double nf[3];
+        face_normal(face, nf);
+        for (int i = 0; i < 3; ++i) nf[i] = -nf[i];   /* from air into the box */
+        {
+            double c = fabs(p[0] * nf[0] + p[1] * nf[1]);
+            if (c < ti->min_cos) ti->min_cos = c;
+        }
+        int bad = 0;
+        double n2 = orc_index_raw(s, r[0], r[1], &bad);
+        if (bad) ti->bad_w++;
+        if (!snell(p, nf, n2)) continue;   /* reflected back into air */
+        int st = integrate_box(s, o, r, p, ti);
+        if (st != RAY_OK) return st;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Camera and jitter.                                                        */
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the n-th output of the      */
+/* generator seeded with `seed` is mix(seed + (n + 1) * 0x9E3779B97F4A7C15). */
+/* Uniform in [0,1): top 53 bits times 2^-53.                                */
+/* ------------------------------------------------------------------------ */
+uint64_t gco_splitmix64(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static double u01(uint64_t seed, uint64_t n)
+{
+    return (double)(gco_splitmix64(seed, n) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+static void normalize3(double v[3])
+{
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= r; v[1] /= r; v[2] /= r;
+}
+
+/* Pinhole camera (Sec. 4: a point camera).  Forward f = target - eye, right
+   r = f x y_hat, up u = r x f; square pixels, row 0 at the top; the vertical
+   opening angle is fov_y and the horizontal one follows from the aspect
+   ratio.  Sample s of pixel (i, j) goes through (i + u, j + v) with u, v the
+   jitter values (1/2 without jitter). */
+void gco_camera_ray(const double* cam, uint64_t seed, int i, int j, int s,
+                    double org[3], double dir[3])
+{
+    double f[3] = { cam[3] - cam[0], cam[4] - cam[1], cam[5] - cam[2] };
+    normalize3(f);
+    double r[3] = { -f[2], 0.0, f[0] };   /* f x (0,1,0) */
+    normalize3(r);
+    double up[3] = { r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0] };
+    int W = (int)cam[7], H = (int)cam[8], spp = (int)cam[9], jitter = (int)cam[10];
+    long scene = (long)cam[11];
+    double t = tan(0.5 * cam[6] * ORC_PI / 180.0);
+    double aspect = (double)W / (double)H;
+    double du = 0.5, dv = 0.5;
+    if (jitter) {
+        uint64_t c = ((((uint64_t)scene * (uint64_t)H + (uint64_t)j) * (uint64_t)W + (uint64_t)i) *
+                      (uint64_t)spp + (uint64_t)s) * 2ULL;
+        du = u01(seed, c);
+        dv = u01(seed, c + 1);
+    }
+    double sx = (2.0 * (i + du) / W - 1.0) * t * aspect;
+    double sy = (1.0 - 2.0 * (j + dv) / H) * t;
+    for (int k = 0; k < 3; ++k) {
+        org[k] = cam[k];
+        dir[k] = f[k] + sx * r[k] + sy * up[k];
+    }
+    normalize3(dir);
+}
+
+/* Procedural backdrop at infinity: an 8 x 8 latitude-longitude checkerboard
+   smoothed with tanh of sharpness K (K = inf gives hard squares).
+   phi = atan2(d_x, -d_z), theta = atan2(d_y, hypot(d_x, d_z)),
+   m = 1/2 + 1/2 tanh(K cos 4 phi) tanh(K sin 8 theta),
+   rgb = Cb + m (Ca - Cb), Ca = (0.95, 0.85, 0.30), Cb = (0.10, 0.20, 0.55). */
+void gco_sky(double K, const double d[3], double rgb[3])
+{
+    const double Ca[3] = { 0.95, 0.85, 0.30 }, Cb[3] = { 0.10, 0.20, 0.55 };
+    double phi = atan2(d[0], -d[2]);
+    double th = atan2(d[1], hypot(d[0], d[2]));
+    double a = cos(4.0 * phi), b = sin(8.0 * th);
+    double ta = isinf(K) ? (a > 0 ? 1.0 : (a < 0 ? -1.0 : 0.0)) : tanh(K * a);
+    double tb = isinf(K) ? (b > 0 ? 1.0 : (b < 0 ? -1.0 : 0.0)) : tanh(K * b);
+    double m = 0.5 + 0.5 * ta * tb;
+    for (int c = 0; c < 3; ++c) rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported entry points (called through ctypes by the test-suite).         */
+/* ------------------------------------------------------------------------ */
+int gco_lambertw(double zr, double zi, double* wr, double* wi)
+{
+    cplx w;
+    int r = orc_w0(zr + I * zi, &w);
+    *wr = creal(w);
+    *wi = cimag(w);
+    return r;
+}
+
+double gco_index(const double* scene, double x, double y)
+{
+    oscene s;
+    load_scene(scene, &s);
+    return orc_index_raw(&s, x, y, NULL);
+}
+
+void gco_accel(const double* scene, double x, double y, double out[2])
+{
+    oscene s;
+    load_scene(scene, &s);
+    orc_accel(&s, x, y, &out[0], &out[1], NULL);
+}
+
+void gco_grad_n_eq12(const double* scene, double x, double y, double out[2])
+{
+    oscene s;
+    load_scene(scene, &s);
+    orc_grad_n_eq12(&s, x, y, &out[0], &out[1]);
+}
+
+double gco_surface(const double* scene, double x, double* xi)
+{
+    oscene s;
+    load_scene(scene, &s);
+    double E;
+    double S = orc_surface(&s, x, &E);
+    if (xi) {
+        double N = floor(x / s.L + 0.5);
+        *xi = E / s.k + N * s.L;
+    }
+    return S;
+}
+
+/* Trace n rays.  info (may be NULL) gets 7 values per ray:
+   steps, rejected, events, contacts, min_cos, bad_w, max_H. */
+void gco_trace_rays(const double* scene, const double* opts, long n,
+                    const double* org, const double* dir, double* out_org, double* out_dir,
+                    int* status, double* info, int nthreads)
+{
+    oscene s;
+    oopts o;
+    load_scene(scene, &s);
+    load_opts(opts, &o);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (long i = 0; i < n; ++i) {
+        trace_info ti;
+        double oo[3] = { 0, 0, 0 }, od[3] = { 0, 0, 0 };
+        int st = trace_one(&s, &o, org + 3 * i, dir + 3 * i, oo, od, &ti);
+        for (int k = 0; k < 3; ++k) { out_org[3 * i + k] = oo[k]; out_dir[3 * i + k] = od[k]; }
+        status[i] = st;
+        if (info) {
+            info[7 * i + 0] = (double)ti.steps;
+            info[7 * i + 1] = (double)ti.rejected;
+            info[7 * i + 2] = (double)ti.events;
+            info[7 * i + 3] = (double)ti.contacts;
+            info[7 * i + 4] = ti.min_cos;
+            info[7 * i + 5] = (double)ti.bad_w;
+            info[7 * i + 6] = ti.max_H;
+        }
+    }
+}
+
+/* Render selected pixels (or all when npix < 0) of a scene.
+   rgb: 3 floats per listed pixel (or H x W x 3).  Each pixel is the mean of
+   its spp sky colours; a failed sample contributes black.
+   counters[4] (may be NULL): rays, accepted steps, rejected steps, failed. */
+void gco_render_pixels(const double* scene, const double* cam, uint64_t seed, const double* opts,
+                       long npix, const long* pix, double* rgb, double* counters, int nthreads)
+{
+    oscene s;
+    oopts o;
+    load_scene(scene, &s);
+    load_opts(opts, &o);
+    int W = (int)cam[7], H = (int)cam[8], spp = (int)cam[9];
+    long total = npix < 0 ? (long)W * H : npix;
+    double c_rays = 0, c_steps = 0, c_rej = 0, c_fail = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : c_rays, c_steps, c_rej, c_fail)
+#endif
+    for (long q = 0; q < total; ++q) {
+        long pidx = npix < 0 ? q : pix[q];
+        int i = (int)(pidx % W), j = (int)(pidx / W);
+        double acc[3] = { 0, 0, 0 };
+        for (int smp = 0; smp < spp; ++smp) {
+            double org[3], dir[3], oo[3], od[3], c[3];
+            trace_info ti;
+            gco_camera_ray(cam, seed, i, j, smp, org, dir);
+            int st = trace_one(&s, &o, org, dir, oo, od, &ti);
+            c_rays += 1;
+            c_steps += (double)ti.steps;
+            c_rej += (double)ti.rejected;
+            if (st != RAY_OK) { c_fail += 1; continue; }
+            gco_sky(s.K, od, c);
+            for (int k = 0; k < 3; ++k) acc[k] += c[k];
+        }
+        for (int k = 0; k < 3; ++k) rgb[3 * q + k] = acc[k] / spp;
+    }
+    if (counters) {
+        counters[0] = c_rays; counters[1] = c_steps; counters[2] = c_rej; counters[3] = c_fail;
+    }
+}
+
+/* eqs. (14), (15) at zero shift.  Images are npix x nch (channel fastest).
+   Each channel's spatial mean is subtracted (eq. (14)); the sums are then
+   pooled over channels: C = sum f' g' / sum f'^2 (eq. (15) at (0, 0)), and
+   the Pearson form sum f' g' / sqrt(sum f'^2 sum g'^2) is reported beside
+   it.  Accumulation in long double, two passes. */
+void gco_cross_correlate(const float* f, const float* g, long npix, int nch, double out[2])
+{
+    long double sfg = 0, sff = 0, sgg = 0;
+    for (int c = 0; c < nch; ++c) {
+        long double mf = 0, mg = 0;
+        for (long i = 0; i < npix; ++i) { mf += f[i * nch + c]; mg += g[i * nch + c]; }
+        mf /= npix;
+        mg /= npix;
+        for (long i = 0; i < npix; ++i) {
+            long double a = f[i * nch + c] - mf, b = g[i * nch + c] - mg;
+            sfg += a * b;
+            sff += a * a;
+            sgg += b * b;
+        }
+    }
+    out[0] = (double)(sfg / sff);
+    out[1] = (double)(sfg / sqrtl(sff * sgg));
+}
+
+/* Same on double images (oracle renders). */
+void gco_cross_correlate_f64(const double* f, const double* g, long npix, int nch, double out[2])
+{
+    long double sfg = 0, sff = 0, sgg = 0;
+    for (int c = 0; c < nch; ++c) {
+        long double mf = 0, mg = 0;
+        for (long i = 0; i < npix; ++i) { mf += f[i * nch + c]; mg += g[i * nch + c]; }
+        mf /= npix;
+        mg /= npix;
+        for (long i = 0; i < npix; ++i) {
+            long double a = f[i * nch + c] - mf, b = g[i * nch + c] - mg;
+            sfg += a * b;
+            sff += a * a;
+            sgg += b * b;
+        }
+    }
+    out[0] = (double)(sfg / sff);
+    out[1] = (double)(sfg / sqrtl(sff * sgg));
+}

@@ -1,0 +1,211 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle/gco.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The GPU library never
+loads this module or its shared object, and this module imports nothing from
+the GPU package.
+
+Inputs are the plain dictionaries built by the workload recipes (scene,
+camera, step options); they are flattened here into the oracle's own
+parameter arrays.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgco.so")
+SRC_PATH = os.path.join(_HERE, "gco.c")
+
+RAY_OK, RAY_MAX_STEPS, RAY_MAX_EVENTS, RAY_NONFINITE, RAY_STEP_UNDERFLOW = range(5)
+
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    import subprocess
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB_PATH, SRC_PATH, "-lm"]
+    if force or not os.path.exists(LIB_PATH):
+        subprocess.check_call(cmd)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.gco_lambertw.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        L.gco_lambertw.restype = ctypes.c_int
+        L.gco_index.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        L.gco_index.restype = ctypes.c_double
+        L.gco_accel.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.gco_grad_n_eq12.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.gco_surface.argtypes = [dp, ctypes.c_double, dp]
+        L.gco_surface.restype = ctypes.c_double
+        L.gco_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.gco_splitmix64.restype = ctypes.c_uint64
+        L.gco_camera_ray.argtypes = [dp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.gco_sky.argtypes = [ctypes.c_double, dp, dp]
+        L.gco_trace_rays.argtypes = [dp, dp, ctypes.c_long, dp, dp, dp, dp,
+                                     ctypes.POINTER(ctypes.c_int), dp, ctypes.c_int]
+        L.gco_render_pixels.argtypes = [dp, dp, ctypes.c_uint64, dp, ctypes.c_long,
+                                        ctypes.POINTER(ctypes.c_long), dp, dp, ctypes.c_int]
+        L.gco_cross_correlate.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                          ctypes.c_long, ctypes.c_int, dp]
+        L.gco_cross_correlate_f64.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def scene_array(sc):
+    return np.array([sc["Lambda"], sc["A"], sc["half_width"], sc["y_top"],
+                     sc["cloak"], sc["mirror"], sc["sky_K"], 0.0], dtype=np.float64)
+
+
+def opts_array(o):
+    integ = {"rk4": 0, "dopri5": 1}[o["integrator"]]
+    return np.array([integ, o["h"], o["rtol"], o["atol"], o["h_max"], o["max_events"],
+                     o["max_steps"], o["h0"], o["h_min"], float(o.get("diagnostics", 0))],
+                    dtype=np.float64)
+
+
+def camera_array(c):
+    return np.array(list(c["eye"]) + list(c["target"]) +
+                    [c["fov_y_deg"], c["width"], c["height"], c["spp"], c["jitter"],
+                     c["scene_index"]], dtype=np.float64)
+
+
+# --- pointwise functions -----------------------------------------------------
+
+def lambertw(z):
+    """Principal branch W0(z); returns (w, ok)."""
+    wr, wi = ctypes.c_double(), ctypes.c_double()
+    r = lib().gco_lambertw(float(np.real(z)), float(np.imag(z)), ctypes.byref(wr), ctypes.byref(wi))
+    return complex(wr.value, wi.value), r == 0
+
+
+def index(sc, x, y):
+    s = scene_array(sc)
+    return lib().gco_index(_dp(s), float(x), float(y))
+
+
+def accel(sc, x, y):
+    s = scene_array(sc)
+    out = np.zeros(2)
+    lib().gco_accel(_dp(s), float(x), float(y), _dp(out))
+    return out
+
+
+def grad_n_eq12(sc, x, y):
+    s = scene_array(sc)
+    out = np.zeros(2)
+    lib().gco_grad_n_eq12(_dp(s), float(x), float(y), _dp(out))
+    return out
+
+
+def surface(sc, x):
+    """Grating height S(x) and the trochoid parameter xi of eq. (2)."""
+    s = scene_array(sc)
+    xi = ctypes.c_double()
+    S = lib().gco_surface(_dp(s), float(x), ctypes.byref(xi))
+    return S, xi.value
+
+
+def splitmix64(seed, n):
+    return int(lib().gco_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(n)))
+
+
+def camera_ray(cam, i, j, s=0):
+    c = camera_array(cam)
+    org, d = np.zeros(3), np.zeros(3)
+    lib().gco_camera_ray(_dp(c), ctypes.c_uint64(cam["seed"]), int(i), int(j), int(s), _dp(org), _dp(d))
+    return org, d
+
+
+def camera_rays(cam):
+    """All sample rays of a camera, ordered (row j, column i, sample s)."""
+    W, H, spp = cam["width"], cam["height"], cam["spp"]
+    org = np.zeros((H * W * spp, 3))
+    d = np.zeros((H * W * spp, 3))
+    q = 0
+    for j in range(H):
+        for i in range(W):
+            for s in range(spp):
+                org[q], d[q] = camera_ray(cam, i, j, s)
+                q += 1
+    return org, d
+
+
+def sky(K, d):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(3)
+    lib().gco_sky(float(K), _dp(d), _dp(out))
+    return out
+
+
+# --- ray tracing and rendering ------------------------------------------------
+
+def trace_rays(sc, o, org, d, nthreads=0):
+    """Trace rays; returns dict with exit origin/direction, status and
+    per-ray info (steps, rejected, events, contacts, min_cos, bad_w, max_H)."""
+    org = np.ascontiguousarray(org, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+    n = org.shape[0]
+    s, p = scene_array(sc), opts_array(o)
+    oo, od = np.zeros((n, 3)), np.zeros((n, 3))
+    st = np.zeros(n, dtype=np.int32)
+    info = np.zeros((n, 7))
+    lib().gco_trace_rays(_dp(s), _dp(p), n, _dp(org), _dp(d), _dp(oo), _dp(od),
+                         st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(info), int(nthreads))
+    return dict(org=oo, dir=od, status=st, steps=info[:, 0].astype(np.int64),
+                rejected=info[:, 1].astype(np.int64), events=info[:, 2].astype(np.int64),
+                contacts=info[:, 3].astype(np.int64), min_cos=info[:, 4],
+                bad_w=info[:, 5].astype(np.int64), max_H=info[:, 6])
+
+
+def render(sc, cam, o, pixels=None, nthreads=0):
+    """Render all pixels (H x W x 3) or the listed linear pixel indices
+    (len x 3).  Returns (rgb, counters) with counters = dict(rays, steps,
+    rejected, failed)."""
+    s, c, p = scene_array(sc), camera_array(cam), opts_array(o)
+    W, H = cam["width"], cam["height"]
+    cnt = np.zeros(4)
+    if pixels is None:
+        rgb = np.zeros((H, W, 3))
+        lib().gco_render_pixels(_dp(s), _dp(c), ctypes.c_uint64(cam["seed"]), _dp(p), -1, None,
+                                _dp(rgb), _dp(cnt), int(nthreads))
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        rgb = np.zeros((pix.size, 3))
+        lib().gco_render_pixels(_dp(s), _dp(c), ctypes.c_uint64(cam["seed"]), _dp(p), pix.size,
+                                pix.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                                _dp(rgb), _dp(cnt), int(nthreads))
+    return rgb, dict(rays=int(cnt[0]), steps=int(cnt[1]), rejected=int(cnt[2]), failed=int(cnt[3]))
+
+
+def cross_correlate(f, g):
+    """eq. (15) at zero shift (C0) and the Pearson form (NCC)."""
+    f = np.asarray(f)
+    g = np.asarray(g)
+    nch = f.shape[-1] if f.ndim == 3 else 1
+    npix = f.size // nch
+    out = np.zeros(2)
+    if f.dtype == np.float32 and g.dtype == np.float32:
+        ff, gg = np.ascontiguousarray(f), np.ascontiguousarray(g)
+        fp = ff.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        gp = gg.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        lib().gco_cross_correlate(fp, gp, npix, nch, _dp(out))
+    else:
+        ff = np.ascontiguousarray(f, dtype=np.float64)
+        gg = np.ascontiguousarray(g, dtype=np.float64)
+        lib().gco_cross_correlate_f64(_dp(ff), _dp(gg), npix, nch, _dp(out))
+    return float(out[0]), float(out[1])

@@ -1,0 +1,115 @@
+"""Seeded synthetic workloads: scenes, cameras and step-control settings.
+
+This module holds only input recipes (plain numbers and a seeded sampler for
+the multi-scene batch).  It contains none of the method's arithmetic and is
+shared by the GPU tests, the CPU oracle tests and the benchmark.
+
+Scene fields follow the paper's notation (Sec. 2): grating period ``Lambda``,
+half peak-to-peak amplitude ``A`` (eq. (2)); the cloak of eq. (1) fills the
+box |x| <= half_width, grating < y <= y_top.  There is no public dataset for
+this method: the backdrop of the paper's renderings is a photograph that is
+not available, so every workload uses the procedural sky instead.
+"""
+import math
+
+import numpy as np
+
+SQRT45 = math.sqrt(45.0)
+
+
+def scene(A=0.1, half_width=2.0, y_top=1.5, Lambda=1.0, cloak=1, mirror=0, sky_K=16.0):
+    return dict(Lambda=float(Lambda), A=float(A), half_width=float(half_width),
+                y_top=float(y_top), cloak=int(cloak), mirror=int(mirror), sky_K=float(sky_K))
+
+
+def reference_scene(sc):
+    """Flat mirror at y = 0 in air (no grating, no cloak)."""
+    r = dict(sc)
+    r.update(cloak=0, mirror=1)
+    return r
+
+
+def uncloaked_scene(sc):
+    """The bare trochoid grating without the index profile."""
+    r = dict(sc)
+    r.update(cloak=0, mirror=0)
+    return r
+
+
+def camera(width, height, spp=1, jitter=False, seed=0, eye=(0.0, 3.0, 6.0),
+           target=(0.0, 0.0, 0.0), fov_y_deg=40.0, scene_index=0):
+    return dict(eye=tuple(float(v) for v in eye), target=tuple(float(v) for v in target),
+                fov_y_deg=float(fov_y_deg), width=int(width), height=int(height),
+                spp=int(spp), jitter=int(bool(jitter)), seed=int(seed),
+                scene_index=int(scene_index))
+
+
+def orbit_eye(az_deg, el_deg, R):
+    az, el = math.radians(az_deg), math.radians(el_deg)
+    return (R * math.sin(az) * math.cos(el), R * math.sin(el), R * math.cos(az) * math.cos(el))
+
+
+def opts(integrator="rk4", h=1e-3, rtol=1e-8, atol=None, h_max=0.02, max_events=32,
+         max_steps=10_000_000, h0=1e-3, h_min=1e-12, w_fallback=1e-2):
+    return dict(integrator=integrator, h=float(h), rtol=float(rtol),
+                atol=float(rtol if atol is None else atol), h_max=float(h_max),
+                max_events=int(max_events), max_steps=int(max_steps), h0=float(h0),
+                h_min=float(h_min), w_fallback=float(w_fallback))
+
+
+# --- the five workloads -------------------------------------------------------
+
+def plain_64():
+    """64 x 64, one ray through each pixel centre, A = 0.1, box |x| <= 2,
+    RK4 with h = 1e-3."""
+    return scene(A=0.1, half_width=2.0), camera(64, 64), opts("rk4", h=1e-3)
+
+
+def plain_vs_fp32_512():
+    """512 x 512, 4 jittered samples (seed 0), A = 0.1, box |x| <= 4,
+    DOPRI5 with rtol 1e-8 (FP64) and 1e-5 (FP32)."""
+    sc = scene(A=0.1, half_width=4.0)
+    cam = camera(512, 512, spp=4, jitter=True, seed=0)
+    return sc, cam, opts("dopri5", rtol=1e-8), opts("dopri5", rtol=1e-5)
+
+
+def branch_stress_1024():
+    """1024 x 1024, 8 spp (seed 2), A = 0.15 (A k = 0.942), grazing camera at
+    elevation 10 deg, distance 12, box |x| <= 4."""
+    sc = scene(A=0.15, half_width=4.0)
+    cam = camera(1024, 1024, spp=8, jitter=True, seed=2, eye=orbit_eye(0.0, 10.0, 12.0))
+    return sc, cam, opts("dopri5", rtol=1e-5)
+
+
+def grad_256():
+    """256 x 256, 4 spp (seed 3), A = 0.08, half-width 3, RK4 h = 1e-3."""
+    sc = scene(A=0.08, half_width=3.0)
+    cam = camera(256, 256, spp=4, jitter=True, seed=3)
+    return sc, cam, opts("rk4", h=1e-3)
+
+
+def batch_64(seed=1012, n_scenes=64, jitter_seed=1, resolutions=(256, 512, 1024)):
+    """64 scenes from one seed: A ~ U[0.02, 0.15], half-width ~ U[2, 8],
+    resolution uniform over {256, 512, 1024}, camera azimuth ~ U[-60, 60] deg
+    and elevation ~ U[15, 60] deg at distance sqrt(45) aimed at the origin,
+    4 jittered spp (jitter seed 1); y_top = 1.5."""
+    rng = np.random.default_rng(seed)
+    scenes, cams = [], []
+    for s in range(n_scenes):
+        A = rng.uniform(0.02, 0.15)
+        hw = rng.uniform(2.0, 8.0)
+        res = int(rng.choice(resolutions))
+        az = rng.uniform(-60.0, 60.0)
+        el = rng.uniform(15.0, 60.0)
+        scenes.append(scene(A=A, half_width=hw))
+        cams.append(camera(res, res, spp=4, jitter=True, seed=jitter_seed,
+                           eye=orbit_eye(az, el, SQRT45), scene_index=s))
+    return scenes, cams
+
+
+def sample_pixels(width, height, count, seed):
+    """Seeded, sorted subset of linear pixel indices (row-major)."""
+    rng = np.random.default_rng(seed)
+    n = width * height
+    count = min(count, n)
+    return np.sort(rng.choice(n, size=count, replace=False)).astype(np.int64)
