@@ -1,0 +1,167 @@
+"""Benchmark: ray-steps/s and rays/s of the FP32 and FP64 GPU paths on the
+512 x 512, 4 spp DOPRI5 workload, at CC error <= 1e-4.
+
+One step = render the cloaked image (FP32 path), render the flat-mirror
+reference and correlate them (eqs. (14)-(15)).  Inputs are synthetic and
+resident on the GPU before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12   # MI355X vector FP32, FLOP/s
+PEAK_FP64 = 78.6e12    # MI355X vector FP64, FLOP/s
+# algorithmic work per accepted integrator step (one DOPRI5 step: 6 RHS
+# evaluations with their complex Lambert-W update, the 7-stage combinations
+# and the error norm), in FLOP with FMA = 2
+FLOP_PER_STEP = {"dopri5": 680.0, "rk4": 354.0}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--rtol32", type=float, default=1e-7)
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this path has no multi-GPU mode (pass --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1012_5107_amd import binding as B
+    from paper_1012_5107_amd import workloads as W
+
+    sc, cam, op64, op32 = W.plain_vs_fp32_512()
+    op32 = dict(op32, rtol=args.rtol32, atol=args.rtol32)
+    ref_sc = W.reference_scene(sc)
+    ctx = B.context(0)
+    dev = torch.device("cuda", 0)
+    H, Wd = cam["height"], cam["width"]
+    img = torch.empty((H, Wd, 3), dtype=torch.float32, device=dev)
+    ref = torch.empty_like(img)
+    stream = torch.cuda.current_stream()
+
+    # counters of one pass (outside the timed region)
+    _, st32 = ctx.render(sc, cam, op32, prec="f32", out=img)
+    ctx.render(ref_sc, cam, op32, prec="f32", out=ref)
+    c32, ncc32 = ctx.cross_correlate(img, ref)
+    print(f"# fp32 pass: {st32}", file=sys.stderr, flush=True)
+
+    def step():
+        ctx.render(sc, cam, op32, prec="f32", out=img, stats=False)
+        ctx.render(ref_sc, cam, op32, prec="f32", out=ref, stats=False)
+        return ctx.cross_correlate(img, ref)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.render(sc, cam, op32, prec="f32", out=img, stats=False)
+        e1.record(stream)
+        ctx.render(ref_sc, cam, op32, prec="f32", out=ref, stats=False)
+        ctx.cross_correlate(img, ref)
+        e1.synchronize()
+        kernel_ms.append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(f"# fp32 step {dt * 1e3:.1f} ms, render kernel {np.mean(kernel_ms):.1f} ms", file=sys.stderr, flush=True)
+
+    steps32 = st32["accepted_steps"]
+    rays = st32["rays"]
+    value = steps32 / dt
+    k_ms = float(np.mean(kernel_ms))
+    achieved = steps32 * FLOP_PER_STEP[op32["integrator"]] / (k_ms * 1e-3)
+
+    out = {
+        "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
+        "value": value,
+        "unit": "ray-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512x512, 4 jittered spp, Lambda=1, A=0.1, cloak |x|<=4, y<=1.5, DOPRI5",
+                   "rtol_fp32": op32["rtol"], "rtol_fp64": op64["rtol"], "rays": rays,
+                   "ray_steps": steps32},
+        "rays_per_s": rays / dt,
+        "cc_fp32": c32,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "k_render32", "kernel_ms": k_ms},
+    }
+
+    if not args.no_fp64:
+        # FP64 plain path on the same workload: one timed pass
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        img64, st64 = ctx.render(sc, cam, op64, prec="f64")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        ref64, _ = ctx.render(ref_sc, cam, op64, prec="f64")
+        c64, _ = ctx.cross_correlate(img64, ref64)
+        out["fp64_plain"] = {"ray_steps_per_s": st64["accepted_steps"] / t64, "rays_per_s": st64["rays"] / t64,
+                             "ms": t64 * 1e3, "ray_steps": st64["accepted_steps"], "cc": c64,
+                             "achieved_tflops": st64["accepted_steps"] * FLOP_PER_STEP["dopri5"] / t64 / 1e12,
+                             "frac_fp64_peak": st64["accepted_steps"] * FLOP_PER_STEP["dopri5"] / t64 / PEAK_FP64}
+        out["cc_error_fp32_vs_fp64"] = abs(c32 - c64)
+        out["speedup_rays_fp32_vs_fp64"] = (rays / dt) / (st64["rays"] / t64)
+        d = (img - img64).abs().amax(dim=-1)
+        out["rgb_error_fp32_vs_fp64"] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt())}
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        npix = 64
+        sample = None
+        while True:
+            pix = W.sample_pixels(Wd, H, npix, seed=11)
+            t2 = time.perf_counter()
+            _, cnt = O.render(sc, cam, op64, pixels=pix)
+            tc = time.perf_counter() - t2
+            sample = (npix, cnt, tc)
+            if tc > args.cpu_seconds / 4 or npix >= Wd * H:
+                break
+            npix = min(Wd * H, int(npix * max(2.0, min(8.0, args.cpu_seconds / max(tc, 1e-3)))))
+        npix, cnt, tc = sample
+        threads = os.cpu_count()
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            pass
+        out["cpu_baseline"] = {"value": cnt["steps"] / tc, "unit": "ray-steps/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{npix} seeded pixels x 4 spp of the same workload (FP64 DOPRI5 rtol 1e-8), "
+                                         f"{cnt['rays']} rays, {cnt['steps']} ray-steps in {tc:.1f} s",
+                               "rays_per_s": cnt["rays"] / tc}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * gcloak.h -- C ABI of the MI355X (gfx950) Newtonian ray tracer for grating
+ * cloaks (Halimeh, Schmied, Wegener, "Newtonian photorealistic ray tracing
+ * of grating cloaks and correlation-function-based cloaking-quality
+ * assessment", Opt. Express 2010).
+ *
+ * The library renders what a pinhole camera sees in a metal grating mirror
+ * covered by the grating cloak and scores the image against a flat-mirror
+ * reference:
+ *   - index profile n = 1 / |1 + W0(i c k e^{ik(x+iy)})|, c = iA,
+ *     k = 2 pi / Lambda (Sec. 2, eq. (1); W0 is the principal Lambert
+ *     function, eq. (13)), truncated to n = 1 outside a finite box;
+ *   - rays obey the Newton-type law of Sec. 3 (eq. (11)); the library
+ *     integrates the equivalent form dr/dtau = p, dp/dtau = grad(n^2)/2 with
+ *     |p| = n (dt = n^2 dtau), refracts with Snell's law at the box faces
+ *     (Sec. 3) and reflects off the trochoid metal grating of eq. (2);
+ *   - escaped rays sample a procedural sky (an 8 x 8 latitude-longitude
+ *     checkerboard smoothed by tanh of sharpness K);
+ *   - images are compared with the zero-shift cross-correlation of
+ *     eqs. (14)-(15).
+ *
+ * Conventions for every call:
+ *   - All pointers named d_* are DEVICE pointers on the context's device;
+ *     the caller owns them.  Scene, camera and option structs are host
+ *     memory, read during the call only.  The library never returns memory.
+ *   - Work is enqueued on the given stream (0 = the null stream) and runs
+ *     asynchronously, except that calls returning host scalars (C0, ncc,
+ *     gc_stats) synchronise that stream before returning.
+ *   - Every call returns GC_OK (0) or a negative gc_status.  On error a
+ *     message is available from gc_last_error() (per host thread) and no
+ *     output is guaranteed.  No C++ exception crosses this interface.
+ *   - Per-ray failures are not call errors: they appear in the per-ray
+ *     status array or in gc_stats.failed, and a failed sample shades black.
+ *   - One gc_ctx per host thread; calls on one context must not overlap.
+ */
+#ifndef GCLOAK_H
+#define GCLOAK_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GC_OK = 0,
+    GC_EINVAL = -1,        /* bad argument (null pointer, size, NaN, ...) */
+    GC_EDOMAIN = -2,       /* A k >= 1 or A < 0: W0 is not single-valued on the cloak */
+    GC_ENOMEM = -3,        /* device scratch allocation failed */
+    GC_EDEVICE = -4,       /* a HIP call failed */
+    GC_EUNSUPPORTED = -5   /* option combination not provided */
+} gc_status;
+
+typedef enum { GC_F64 = 0, GC_F32 = 1 } gc_precision;
+typedef enum { GC_RK4 = 0, GC_DOPRI5 = 1 } gc_integrator;
+
+typedef enum {
+    GC_RAY_OK = 0,
+    GC_RAY_MAX_STEPS = 1,       /* more than max_steps accepted steps in the cloak */
+    GC_RAY_MAX_EVENTS = 2,      /* more than max_events interface events */
+    GC_RAY_NONFINITE = 3,       /* a non-finite value appeared in the ray state */
+    GC_RAY_STEP_UNDERFLOW = 4   /* DOPRI5 step fell below h_min */
+} gc_ray_status;
+
+/* Scene (Sec. 2).  Grating x = xi - A sin(k xi), y = A cos(k xi) (eq. (2)),
+ * infinite in x and z.  With cloak = 1 the index of eq. (1) fills the box
+ * |x| <= half_width, grating < y <= y_top (n = 1 elsewhere); half_width and
+ * y_top may be +inf.  mirror = 1 replaces the grating by the flat mirror
+ * y = 0 (only with cloak = 0: the reference image).  sky_K is the sky's
+ * tanh sharpness (+inf: hard squares). */
+typedef struct {
+    double Lambda;
+    double A;
+    double half_width;
+    double y_top;
+    int32_t cloak;
+    int32_t mirror;
+    double sky_K;
+} gc_scene;
+
+/* Pinhole camera (Sec. 4: a virtual point camera).  World up is +y; right
+ * = forward x up; square pixels, row 0 at the top; fov_y_deg is the full
+ * vertical opening angle.  Sample s of pixel (i, j) passes through
+ * (i + u, j + v), with u, v the SplitMix64 outputs number 2c and 2c + 1
+ * (c = ((scene_index H + j) W + i) spp + s) of the generator seeded with
+ * `seed`, each mapped to [0,1) by its top 53 bits; u = v = 1/2 when
+ * jitter = 0. */
+typedef struct {
+    double eye[3];
+    double target[3];
+    double fov_y_deg;
+    int32_t width;
+    int32_t height;
+    int32_t spp;
+    int32_t jitter;
+    uint64_t seed;
+    int64_t scene_index;
+} gc_camera;
+
+/* Integration options.  RK4: classical 4-stage, fixed step h.  DOPRI5:
+ * Dormand-Prince 5(4) with an RMS error norm over (x, y, p_x, p_y) scaled
+ * by atol + rtol max(|y_n|, |y_n+1|), step factor clamp [0.2, 5], safety
+ * 0.9, no growth right after a rejection, first step h0, caps h_max and
+ * h_min.  Step sizes are in tau (|dr/dtau| = n).  w_fallback is the
+ * |1 + W| threshold below which the FP32 path recomputes the Lambert
+ * function in FP64.  An event (box face or grating) ends a step at the
+ * partial step of the same integrator that lands on the surface. */
+typedef struct {
+    int32_t prec;          /* gc_precision */
+    int32_t integ;         /* gc_integrator */
+    double h;              /* RK4 step */
+    double rtol, atol;     /* DOPRI5 tolerances */
+    double h_max, h0, h_min;
+    double w_fallback;     /* default 1e-2 */
+    int32_t max_events;    /* default 32 */
+    int32_t reserved;
+    int64_t max_steps;     /* default 10^7 */
+} gc_opts;
+
+typedef struct {
+    int64_t rays;            /* samples traced */
+    int64_t accepted_steps;  /* integrator steps kept inside the cloak */
+    int64_t rejected_steps;  /* DOPRI5 attempts rejected */
+    int64_t events;          /* box entries/exits, internal reflections, grating contacts */
+    int64_t fallbacks;       /* FP32 path: Lambert-W evaluations redone in FP64 */
+    int64_t failed;          /* samples with status != GC_RAY_OK */
+} gc_stats;
+
+typedef struct gc_ctx gc_ctx;
+
+/* Create a context on HIP device `hip_device` (made current for the call).
+ * Returns GC_EINVAL for a null `out` or a bad device, GC_EDEVICE on HIP
+ * failure. */
+gc_status gc_create(gc_ctx** out, int hip_device);
+
+/* Release the context and its device scratch.  Null is ignored. */
+void gc_destroy(gc_ctx* ctx);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* gc_last_error(void);
+
+/* Fill `opts` with the defaults: FP64, RK4, h = 1e-3, rtol = atol = 1e-8,
+ * h_max = 0.02, h0 = 1e-3, h_min = 1e-12, w_fallback = 1e-2,
+ * max_events = 32, max_steps = 10^7. */
+void gc_default_opts(gc_opts* opts);
+
+/* Trace n rays (Sec. 3) from origins d_org and directions d_dir (n x 3
+ * doubles, row-major; directions need not be unit) until they escape.
+ * Outputs: exit point (where the ray left its last surface) and unit exit
+ * direction (n x 3 doubles each), per-ray gc_ray_status (int32), accepted
+ * steps (int64) and events (int32).  Any output pointer except d_out_dir may
+ * be null.  Works in the precision opts->prec.  n = 0 is a no-op. */
+gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts, int64_t n,
+                        const double* d_org, const double* d_dir,
+                        double* d_out_org, double* d_out_dir,
+                        int32_t* d_status, int64_t* d_steps, int32_t* d_events,
+                        hipStream_t stream);
+
+/* Render one image (Sec. 4): d_rgb is height x width x 3 float32 (HWC, row
+ * 0 at the top), each pixel the mean of its spp sky colours (failed samples
+ * black).  With scene->mirror = 1 (flat mirror, cloak = 0) the reference
+ * image is produced in closed form.  `st` (host, may be null) receives the
+ * counters and then the call synchronises the stream. */
+gc_status gc_render(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera,
+                    const gc_opts* opts, float* d_rgb, gc_stats* st, hipStream_t stream);
+
+/* Zero-shift cross-correlation of eqs. (14)-(15) between d_img (g) and the
+ * reference d_ref (f): both npix x nch float32, channel fastest.  Each
+ * channel's mean is subtracted (eq. (14)) and the sums are pooled over
+ * channels: *C0 = sum f'g' / sum f'^2 (eq. (15) at (0, 0)); *ncc = sum f'g'
+ * / sqrt(sum f'^2 sum g'^2) (may be null).  Sums are formed in FP64.
+ * Synchronises the stream.  GC_EINVAL if npix < 1, nch < 1 or the
+ * reference is constant. */
+gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref,
+                             int64_t npix, int32_t nch, double* C0, double* ncc,
+                             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCLOAK_H */

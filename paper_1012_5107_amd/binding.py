@@ -1,0 +1,214 @@
+"""Python binding of ``libgcloak.so`` (C ABI in ``include/gcloak.h``).
+
+Argument marshalling only: torch provides device memory and the current
+stream; every step of the computation runs in the library's HIP kernels.
+Importing this module loads the library and fails loudly when it has not been
+built (``python -m paper_1012_5107_amd.build``) -- there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgcloak.so")
+
+GC_OK, GC_EINVAL, GC_EDOMAIN, GC_ENOMEM, GC_EDEVICE, GC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GC_F64, GC_F32 = 0, 1
+GC_RK4, GC_DOPRI5 = 0, 1
+RAY_OK, RAY_MAX_STEPS, RAY_MAX_EVENTS, RAY_NONFINITE, RAY_STEP_UNDERFLOW = range(5)
+
+
+class GcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gcloak error {status}: {msg}")
+        self.status = status
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("Lambda", ctypes.c_double), ("A", ctypes.c_double), ("half_width", ctypes.c_double),
+                ("y_top", ctypes.c_double), ("cloak", ctypes.c_int32), ("mirror", ctypes.c_int32),
+                ("sky_K", ctypes.c_double)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("target", ctypes.c_double * 3), ("fov_y_deg", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
+                ("jitter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("scene_index", ctypes.c_int64)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("integ", ctypes.c_int32), ("h", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("h_max", ctypes.c_double),
+                ("h0", ctypes.c_double), ("h_min", ctypes.c_double), ("w_fallback", ctypes.c_double),
+                ("max_events", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_steps", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rays", ctypes.c_int64), ("accepted_steps", ctypes.c_int64), ("rejected_steps", ctypes.c_int64),
+                ("events", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("failed", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+# every symbol the header declares
+EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
+           "gc_cross_correlate"]
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1012_5107_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.gc_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    L.gc_create.restype = ctypes.c_int
+    L.gc_destroy.argtypes = [vp]
+    L.gc_destroy.restype = None
+    L.gc_last_error.argtypes = []
+    L.gc_last_error.restype = ctypes.c_char_p
+    L.gc_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.gc_default_opts.restype = None
+    L.gc_trace_rays.argtypes = [vp, ctypes.POINTER(Scene), ctypes.POINTER(Opts), i64, vp, vp, vp, vp, vp, vp, vp,
+                                vp]
+    L.gc_trace_rays.restype = ctypes.c_int
+    L.gc_render.argtypes = [vp, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts), vp,
+                            ctypes.POINTER(Stats), vp]
+    L.gc_render.restype = ctypes.c_int
+    L.gc_cross_correlate.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    L.gc_cross_correlate.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != GC_OK:
+        raise GcError(st, load().gc_last_error().decode())
+
+
+# --- struct marshalling ------------------------------------------------------
+
+def make_scene(sc):
+    return Scene(sc["Lambda"], sc["A"], sc["half_width"], sc["y_top"], int(sc["cloak"]), int(sc["mirror"]),
+                 sc["sky_K"])
+
+
+def make_camera(c):
+    cam = Camera()
+    cam.eye[:] = list(c["eye"])
+    cam.target[:] = list(c["target"])
+    cam.fov_y_deg = c["fov_y_deg"]
+    cam.width, cam.height, cam.spp = c["width"], c["height"], c["spp"]
+    cam.jitter = int(c["jitter"])
+    cam.seed = c["seed"]
+    cam.scene_index = c.get("scene_index", 0)
+    return cam
+
+
+def make_opts(o, prec="f64"):
+    p = Opts()
+    load().gc_default_opts(ctypes.byref(p))
+    p.prec = {"f64": GC_F64, "f32": GC_F32}[prec]
+    p.integ = {"rk4": GC_RK4, "dopri5": GC_DOPRI5}[o["integrator"]]
+    p.h, p.rtol, p.atol = o["h"], o["rtol"], o["atol"]
+    p.h_max, p.h0, p.h_min = o["h_max"], o["h0"], o["h_min"]
+    p.w_fallback = o.get("w_fallback", 1e-2)
+    p.max_events = o["max_events"]
+    p.max_steps = o["max_steps"]
+    return p
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns one library context on a device."""
+
+    def __init__(self, device=0):
+        L = load()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        _check(L.gc_create(ctypes.byref(h), self.device.index or 0))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ------------------------------------------------------------
+    def trace_rays(self, scene, opts, org, dirs, prec="f64", stream=None):
+        """Trace rays from device tensors org, dirs (n x 3 float64).  Returns
+        (exit_org, exit_dir, status, steps, events) device tensors."""
+        org = org.to(self.device, torch.float64).contiguous()
+        dirs = dirs.to(self.device, torch.float64).contiguous()
+        n = org.shape[0]
+        oo = torch.empty_like(org)
+        od = torch.empty_like(dirs)
+        st = torch.empty(n, dtype=torch.int32, device=self.device)
+        steps = torch.empty(n, dtype=torch.int64, device=self.device)
+        ev = torch.empty(n, dtype=torch.int32, device=self.device)
+        sc, op = make_scene(scene), make_opts(opts, prec)
+        _check(load().gc_trace_rays(self._h, ctypes.byref(sc), ctypes.byref(op), n, org.data_ptr(),
+                                    dirs.data_ptr(), oo.data_ptr(), od.data_ptr(), st.data_ptr(), steps.data_ptr(),
+                                    ev.data_ptr(), _stream_handle(stream)))
+        return oo, od, st, steps, ev
+
+    def render(self, scene, camera, opts, prec="f64", out=None, stats=True, stream=None):
+        """Render an H x W x 3 float32 image on the device.  Returns
+        (image, stats dict or None)."""
+        H, W = camera["height"], camera["width"]
+        img = out if out is not None else torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        sc, cam, op = make_scene(scene), make_camera(camera), make_opts(opts, prec)
+        st = Stats()
+        _check(load().gc_render(self._h, ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(op), img.data_ptr(),
+                                ctypes.byref(st) if stats else None, _stream_handle(stream)))
+        return img, (st.as_dict() if stats else None)
+
+    def cross_correlate(self, img, ref, stream=None):
+        """eq. (15) at zero shift and the Pearson form, from device images."""
+        img = img.to(self.device, torch.float32).contiguous()
+        ref = ref.to(self.device, torch.float32).contiguous()
+        nch = img.shape[-1] if img.dim() == 3 else 1
+        npix = img.numel() // nch
+        c0, ncc = ctypes.c_double(), ctypes.c_double()
+        _check(load().gc_cross_correlate(self._h, img.data_ptr(), ref.data_ptr(), npix, nch, ctypes.byref(c0),
+                                         ctypes.byref(ncc), _stream_handle(stream)))
+        return c0.value, ncc.value
+
+
+_default = {}
+
+
+def context(device=0):
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def render(scene, camera, opts, prec="f64", device=0):
+    return context(device).render(scene, camera, opts, prec)
+
+
+def trace_rays(scene, opts, org, dirs, prec="f64", device=0):
+    return context(device).trace_rays(scene, opts, org, dirs, prec)
+
+
+def cross_correlate(img, ref, device=0):
+    return context(device).cross_correlate(img, ref)

@@ -1,0 +1,553 @@
+// gc_lane64.hpp -- FP64 per-lane ray tracer: free flight in air, box
+// entry and exit with Snell's law, integration inside the cloak, grating
+// contacts, and the event machinery shared with the FP32 path.
+//
+// Steps of one ray (Sec. 3 and Sec. 4):
+//   air:   straight line (the acceleration of eq. (11) vanishes outside the
+//          cloak) to the nearest of: the cloak box (Snell refraction into
+//          it), the bare grating of eq. (2) (mirror reflection), or nothing
+//          (the ray escapes to the sky);
+//   cloak: RK4 or DOPRI5 steps of dr/dtau = p, dp/dtau = grad(n^2)/2; a step
+//          whose end leaves the box (y > y_top, |x| > half_width) or enters
+//          the metal (virtual coordinate v = y + Re W / k < 0) is replaced by
+//          the partial step of the same integrator that ends on that surface;
+//          then the ray reflects (grating, or total internal reflection at a
+//          face) or refracts out of the box.
+#pragma once
+#include "gc_math.hpp"
+
+namespace gc {
+
+constexpr double kInf = __builtin_huge_val();
+
+struct St64 { double x, y, px, py; };
+
+struct LaneCount {
+    long long steps, rejected;
+    int events;
+    int fallbacks;
+};
+
+// ---------------------------------------------------------------------------
+// Grating geometry, eq. (2): x = xi - A sin(k xi), y = A cos(k xi).
+// ---------------------------------------------------------------------------
+// Solve M = E - e sin E (e < 1) for E: safeguarded Newton in [M - e, M + e].
+__device__ inline double kepler_E(double M, double e)
+{
+    double lo = M - e, hi = M + e;
+    double E = M + e * sin(M);
+    for (int it = 0; it < 60; ++it) {
+        double sn, c;
+        sincos(E, &sn, &c);
+        double f = E - e * sn - M;
+        if (f > 0.0) hi = E; else lo = E;
+        double En = E - f / (1.0 - e * c);
+        if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
+        double dE = En - E;
+        E = En;
+        if (fabs(dE) <= 1e-15 * fmax(1.0, fabs(E))) break;
+    }
+    return E;
+}
+
+// trochoid parameter xi of the surface point above/below x
+__device__ inline double xi_of_x(const SceneDev& s, double x)
+{
+    double N = rint(x * s.invL);
+    double E = kepler_E(s.k * (x - N * s.L), s.e);
+    return E / s.k + N * s.L;
+}
+
+// G(xi) = d_y (X(xi) - x0) - d_x (Y(xi) - y0): zero where the line through
+// (x0, y0) with direction (d_x, d_y) meets the trochoid.
+__device__ inline double line_G(const SceneDev& s, double xi, double x0, double y0, double dx, double dy,
+                                double* dG)
+{
+    double sn, c;
+    sincos(s.k * xi, &sn, &c);
+    double X = xi - s.A * sn, Y = s.A * c;
+    if (dG) *dG = dy * (1.0 - s.e * c) + dx * s.e * sn;
+    return dy * (X - x0) - dx * (Y - y0);
+}
+
+// First contact of the ray r + t d (t > 0) with the bare metal surface; +inf
+// if none.  Writes the trochoid parameter of the contact point to *xi_hit.
+// G'(xi) = d_y - e R cos(k xi + phi) with R = |(d_x, d_y)|, so G is monotone
+// between consecutive critical points k xi + phi = +-acos(d_y / (e R)) + 2 pi m.
+// Above the surface sign(G) = sign(d_x); the first piece (in the direction of
+// travel) over which sign(d_x) G drops from positive to non-positive holds
+// the contact, found by safeguarded Newton.
+__device__ inline double air_contact(const SceneDev& s, const double r[3], const double d[3], double* xi_hit)
+{
+    const double x0 = r[0], y0 = r[1], dx = d[0], dy = d[1];
+    if (s.mirror == 1 || s.A == 0.0) {
+        *xi_hit = 0.0;
+        if (dy < 0.0 && y0 > 0.0) return -y0 / dy;
+        if (dy < 0.0 && y0 >= 0.0) return 0.0;
+        return kInf;
+    }
+    const double A = s.A;
+    double t0 = 0.0, t1;
+    if (dy < 0.0) {
+        if (y0 > A) t0 = (A - y0) / dy;
+        t1 = (-A - y0) / dy * (1.0 + 1e-12);
+    } else if (dy > 0.0) {
+        if (y0 >= A) return kInf;
+        t1 = (A - y0) / dy;
+    } else {
+        if (y0 > A || y0 < -A || dx == 0.0) return kInf;
+        t1 = s.L / fabs(dx);
+    }
+    const bool at_origin = (t0 == 0.0);
+    if (dx == 0.0) {
+        // the line stays above one surface point
+        double xi = xi_of_x(s, x0);
+        double S = A * cos(s.k * xi);
+        *xi_hit = xi;
+        double t = (S - y0) / dy;
+        if (dy < 0.0 && t > 0.0) return t;
+        return kInf;
+    }
+    const double sg = dx > 0.0 ? 1.0 : -1.0;
+    const double xia = xi_of_x(s, x0 + t0 * dx);
+    const double xib = xi_of_x(s, x0 + t1 * dx);
+    const double R = sqrt(dx * dx + dy * dy);
+    const double phi = atan2(dx, dy);
+    const bool has_crit = fabs(dy) < s.e * R;
+    const double alpha = has_crit ? acos(dy / (s.e * R)) : 0.0;
+    double xi = xia;
+    double G = sg * line_G(s, xi, x0, y0, dx, dy, nullptr);
+    if (!at_origin && G <= 0.0) { *xi_hit = xia; return t0; }
+    // critical phases in increasing order: c(2m) = -alpha + 2 pi m,
+    // c(2m + 1) = alpha + 2 pi m; walk them by index in the travel direction
+    long long j = 0;
+    if (has_crit) {
+        const double th = s.k * xia + phi;
+        if (sg > 0.0) {
+            long long m = (long long)floor((th + alpha) * kInvTwoPi);
+            j = (alpha + kTwoPi * m > th) ? 2 * m + 1 : 2 * m + 2;
+        } else {
+            long long m = (long long)ceil((th - alpha) * kInvTwoPi) - 1;
+            j = (-alpha + kTwoPi * (m + 1) < th) ? 2 * m + 2 : 2 * m + 1;
+        }
+    }
+    for (int piece = 0; piece < 1 << 16; ++piece) {
+        double xn = xib;
+        if (has_crit) {
+            long long m = (j >= 0) ? j / 2 : -((-j + 1) / 2);
+            double tn = ((j - 2 * m) == 1 ? alpha : -alpha) + kTwoPi * (double)m;
+            double xc = (tn - phi) / s.k;
+            xn = (sg > 0.0) ? fmin(xc, xib) : fmax(xc, xib);
+            j += (sg > 0.0) ? 1 : -1;
+        }
+        double Gn = sg * line_G(s, xn, x0, y0, dx, dy, nullptr);
+        if (G > 0.0 && Gn <= 0.0) {
+            // monotone bracket [xi, xn]: safeguarded Newton on G
+            double lo = xi, hi = xn;   // sg*G(lo) > 0 >= sg*G(hi)
+            double z = 0.5 * (lo + hi);
+            for (int it = 0; it < 100; ++it) {
+                double dG;
+                double g = sg * line_G(s, z, x0, y0, dx, dy, &dG);
+                dG *= sg;
+                if (g > 0.0) lo = z; else hi = z;
+                double zn = z - g / dG;
+                bool inside = (zn - lo) * (zn - hi) < 0.0;
+                if (!inside || !isfinite(zn)) zn = 0.5 * (lo + hi);
+                double step = fabs(zn - z);
+                z = zn;
+                if (step <= 1e-15 * fmax(1.0, fabs(z)) || fabs(hi - lo) <= 1e-15 * fmax(1.0, fabs(z))) break;
+            }
+            *xi_hit = z;
+            double sn, c;
+            sincos(s.k * z, &sn, &c);
+            double X = z - A * sn, Y = A * c;
+            double t = fabs(dx) >= fabs(dy) ? (X - x0) / dx : (Y - y0) / dy;
+            return t;
+        }
+        if (xn == xib) return kInf;
+        xi = xn;
+        G = Gn;
+    }
+    return kInf;
+}
+
+// Entry of the straight ray into the cloak box from air (face code: 0 top,
+// 1 right x = +hw, 2 left x = -hw; -1 none).
+__device__ inline double air_box_entry(const SceneDev& s, const double r[3], const double d[3], int* face)
+{
+    double best = kInf;
+    *face = -1;
+    if (!s.cloak) return best;
+    if (d[1] < 0.0 && r[1] > s.ytop) {
+        double t = (s.ytop - r[1]) / d[1];
+        double xe = r[0] + t * d[0];
+        if (fabs(xe) <= s.hw && t < best) { best = t; *face = 0; }
+    }
+    if (d[0] < 0.0 && r[0] > s.hw) {
+        double t = (s.hw - r[0]) / d[0];
+        double ye = r[1] + t * d[1];
+        if (ye <= s.ytop && ye >= s.S_hw && t < best) { best = t; *face = 1; }
+    }
+    if (d[0] > 0.0 && r[0] < -s.hw) {
+        double t = (-s.hw - r[0]) / d[0];
+        double ye = r[1] + t * d[1];
+        if (ye <= s.ytop && ye >= s.S_hw && t < best) { best = t; *face = 2; }
+    }
+    return best;
+}
+
+// Snell's law at a plane with unit normal nf (from medium 1 into 2): keep the
+// tangential part, choose the normal part for |p'| = n2; total internal
+// reflection when n2^2 < |p_t|^2.  Returns true if transmitted.
+__device__ inline bool snell(double p[3], const double nf[3], double n2)
+{
+    double pn = p[0] * nf[0] + p[1] * nf[1] + p[2] * nf[2];
+    double pt[3] = {p[0] - pn * nf[0], p[1] - pn * nf[1], p[2] - pn * nf[2]};
+    double q = n2 * n2 - (pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2]);
+    if (q < 0.0) {
+        for (int i = 0; i < 3; ++i) p[i] -= 2.0 * pn * nf[i];
+        return false;
+    }
+    double pnn = (pn >= 0.0 ? 1.0 : -1.0) * sqrt(q);
+    for (int i = 0; i < 3; ++i) p[i] = pt[i] + pnn * nf[i];
+    return true;
+}
+
+__device__ inline void reflect2(double& px, double& py, double nx, double ny)
+{
+    double pn = px * nx + py * ny;
+    px -= 2.0 * pn * nx;
+    py -= 2.0 * pn * ny;
+}
+
+// ---------------------------------------------------------------------------
+// One FP64 integrator step inside the cloak.  k1 = (p, a1) at u with the
+// converged W1 and dW1 = dW/dzeta there.  Returns the end state and the
+// W, a, dW at the end point (the next step's first stage).
+// ---------------------------------------------------------------------------
+struct Rhs64 {
+    double ax, ay;
+    cx<double> W, dW;
+};
+
+__device__ inline void rhs_at(const SceneDev& s, double x, double y, double xp, double yp, const Rhs64& prev,
+                              Rhs64& out)
+{
+    out.W = prev.W + prev.dW * mk(x - xp, y - yp);
+    rhs64(s, x, y, out.W, out.ax, out.ay, out.dW);
+}
+
+__device__ inline void rk4_step64(const SceneDev& s, const St64& u, const Rhs64& r1, double h, St64& ue,
+                                  Rhs64& re)
+{
+    const double hh = 0.5 * h;
+    Rhs64 r2, r3, r4;
+    double x2 = u.x + hh * u.px, y2 = u.y + hh * u.py;
+    double p2x = u.px + hh * r1.ax, p2y = u.py + hh * r1.ay;
+    rhs_at(s, x2, y2, u.x, u.y, r1, r2);
+    double x3 = u.x + hh * p2x, y3 = u.y + hh * p2y;
+    double p3x = u.px + hh * r2.ax, p3y = u.py + hh * r2.ay;
+    rhs_at(s, x3, y3, x2, y2, r2, r3);
+    double x4 = u.x + h * p3x, y4 = u.y + h * p3y;
+    double p4x = u.px + h * r3.ax, p4y = u.py + h * r3.ay;
+    rhs_at(s, x4, y4, x3, y3, r3, r4);
+    const double h6 = h / 6.0;
+    ue.x = u.x + h6 * (u.px + 2.0 * p2x + 2.0 * p3x + p4x);
+    ue.y = u.y + h6 * (u.py + 2.0 * p2y + 2.0 * p3y + p4y);
+    ue.px = u.px + h6 * (r1.ax + 2.0 * r2.ax + 2.0 * r3.ax + r4.ax);
+    ue.py = u.py + h6 * (r1.ay + 2.0 * r2.ay + 2.0 * r3.ay + r4.ay);
+    rhs_at(s, ue.x, ue.y, x4, y4, r4, re);
+}
+
+// Dormand-Prince 5(4) tableau (Dormand & Prince 1980).
+struct DP {
+    static constexpr double a21 = 1.0 / 5;
+    static constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+    static constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+    static constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
+    static constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
+                            a65 = -5103.0 / 18656;
+    static constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192, b5 = -2187.0 / 6784,
+                            b6 = 11.0 / 84;
+    // 5th minus 4th order weights
+    static constexpr double e1 = 35.0 / 384 - 5179.0 / 57600, e3 = 500.0 / 1113 - 7571.0 / 16695,
+                            e4 = 125.0 / 192 - 393.0 / 640, e5 = -2187.0 / 6784 + 92097.0 / 339200,
+                            e6 = 11.0 / 84 - 187.0 / 2100, e7 = -1.0 / 40;
+};
+
+// One DOPRI5 step; returns the scaled RMS error over (x, y, px, py) and the
+// 5th order end state with its RHS (FSAL).
+template <typename T>
+__device__ __forceinline__ T dp_comb6(T k1, T k2, T k3, T k4, T k5, T k6, T c1, T c2, T c3, T c4, T c5, T c6)
+{
+    return c1 * k1 + c2 * k2 + c3 * k3 + c4 * k4 + c5 * k5 + c6 * k6;
+}
+
+__device__ inline double dp5_step64(const SceneDev& s, const St64& u, const Rhs64& r1, double h, double rtol,
+                                    double atol, St64& ue, Rhs64& re)
+{
+    double kx[7], ky[7], kax[7], kay[7];
+    Rhs64 rp = r1, rn;
+    double xp = u.x, yp = u.y;
+    kx[0] = u.px; ky[0] = u.py; kax[0] = r1.ax; kay[0] = r1.ay;
+    const double A[6][6] = {{DP::a21, 0, 0, 0, 0, 0},
+                            {DP::a31, DP::a32, 0, 0, 0, 0},
+                            {DP::a41, DP::a42, DP::a43, 0, 0, 0},
+                            {DP::a51, DP::a52, DP::a53, DP::a54, 0, 0},
+                            {DP::a61, DP::a62, DP::a63, DP::a64, DP::a65, 0},
+                            {DP::b1, 0.0, DP::b3, DP::b4, DP::b5, DP::b6}};
+#pragma unroll
+    for (int st = 1; st < 7; ++st) {
+        double sx = 0, sy = 0, sax = 0, say = 0;
+#pragma unroll
+        for (int j = 0; j < st; ++j) {
+            sx += A[st - 1][j] * kx[j];
+            sy += A[st - 1][j] * ky[j];
+            sax += A[st - 1][j] * kax[j];
+            say += A[st - 1][j] * kay[j];
+        }
+        double x = u.x + h * sx, y = u.y + h * sy;
+        kx[st] = u.px + h * sax;
+        ky[st] = u.py + h * say;
+        rhs_at(s, x, y, xp, yp, rp, rn);
+        kax[st] = rn.ax;
+        kay[st] = rn.ay;
+        rp = rn;
+        xp = x;
+        yp = y;
+        if (st == 6) { ue.x = x; ue.y = y; ue.px = kx[6]; ue.py = ky[6]; }
+    }
+    re = rp;
+    const double E[7] = {DP::e1, 0.0, DP::e3, DP::e4, DP::e5, DP::e6, DP::e7};
+    double ex = 0, ey = 0, epx = 0, epy = 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        ex += E[j] * kx[j];
+        ey += E[j] * ky[j];
+        epx += E[j] * kax[j];
+        epy += E[j] * kay[j];
+    }
+    double q0 = h * ex / (atol + rtol * fmax(fabs(u.x), fabs(ue.x)));
+    double q1 = h * ey / (atol + rtol * fmax(fabs(u.y), fabs(ue.y)));
+    double q2 = h * epx / (atol + rtol * fmax(fabs(u.px), fabs(ue.px)));
+    double q3 = h * epy / (atol + rtol * fmax(fabs(u.py), fabs(ue.py)));
+    return sqrt(0.25 * (q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3));
+}
+
+__device__ inline void partial_step64(const SceneDev& s, const OptsDev& o, const St64& u, const Rhs64& r1,
+                                      double h, St64& ue, Rhs64& re)
+{
+    if (o.integ == 0) rk4_step64(s, u, r1, h, ue, re);
+    else (void)dp5_step64(s, u, r1, h, o.rtol, o.atol, ue, re);
+}
+
+// event functions, >= 0 inside the box: 0 top, 1 right, 2 left, 3 grating
+__device__ inline double event_fn(const SceneDev& s, int ev, const St64& u, const Rhs64& r)
+{
+    switch (ev) {
+    case 0: return s.ytop - u.y;
+    case 1: return s.hw - u.x;
+    case 2: return s.hw + u.x;
+    default: return u.y + r.W.re / s.k;
+    }
+}
+
+// Smallest theta in (0, 1] at which event `ev` of the partial step crosses
+// zero, by the Illinois variant of regula falsi on a bracket that keeps
+// e >= 0 at lo and e < 0 at hi; returns hi once hi - lo <= 1e-14.
+__device__ inline double locate_event(const SceneDev& s, const OptsDev& o, int ev, const St64& u,
+                                      const Rhs64& r1, double h, double f0, double f1)
+{
+    double lo = 0.0, hi = 1.0;
+    double flo = fmax(f0, 0.0), fhi = f1;
+    int side = 0;
+    for (int it = 0; it < 100 && hi - lo > 1e-14; ++it) {
+        double th = 0.5 * (lo + hi);
+        if (it < 40 && flo != fhi) {
+            double t = (lo * fhi - hi * flo) / (fhi - flo);
+            if (t > lo && t < hi) th = t;
+        }
+        St64 ue;
+        Rhs64 re;
+        partial_step64(s, o, u, r1, th * h, ue, re);
+        double f = event_fn(s, ev, ue, re);
+        if (f < 0.0) {
+            hi = th;
+            fhi = f;
+            if (side == -1) flo *= 0.5;
+            side = -1;
+        } else {
+            lo = th;
+            flo = f;
+            if (side == +1) fhi *= 0.5;
+            side = +1;
+        }
+    }
+    return hi;
+}
+
+// Handle the end of a step that crossed at least one event (FP64).
+// u, r1: state and RHS at the step start; ue, re: full-step end.  On return
+// u / r1 hold the post-event state (momentum updated) and the return value
+// tells whether the ray left the box (out_p then holds the momentum in air,
+// out_z advanced accordingly).  *dtau receives the tau advanced.
+__device__ inline bool handle_events64(const SceneDev& s, const OptsDev& o, St64& u, Rhs64& r1, double pz,
+                                       double h, const St64& ue, const Rhs64& re, double* dtau,
+                                       double out_p[3], double* min_cos)
+{
+    double best = 2.0;
+    int hit = -1;
+    for (int ev = 0; ev < 4; ++ev) {
+        if (ev == 3 && s.mirror == 1) continue;
+        double f1 = event_fn(s, ev, ue, re);
+        if (!(f1 < 0.0)) continue;
+        double f0 = event_fn(s, ev, u, r1);
+        double th = locate_event(s, o, ev, u, r1, h, f0, f1);
+        if (th < best) { best = th; hit = ev; }
+    }
+    St64 uc;
+    Rhs64 rc;
+    partial_step64(s, o, u, r1, best * h, uc, rc);
+    *dtau = best * h;
+    u = uc;
+    r1 = rc;
+    if (hit == 3) {
+        // grating contact: on the surface W = -A k e^{i k xi}, so the upward
+        // normal (A k sin k xi, 1 - A k cos k xi) is (-Im W, 1 + Re W)
+        double nx = -rc.W.im, ny = 1.0 + rc.W.re;
+        double inv = 1.0 / sqrt(nx * nx + ny * ny);
+        nx *= inv;
+        ny *= inv;
+        double pa = sqrt(u.px * u.px + u.py * u.py + pz * pz);
+        *min_cos = fmin(*min_cos, fabs(u.px * nx + u.py * ny) / pa);
+        reflect2(u.px, u.py, nx, ny);
+        return false;
+    }
+    double nf[3] = {0.0, 0.0, 0.0};
+    if (hit == 0) nf[1] = 1.0; else if (hit == 1) nf[0] = 1.0; else nf[0] = -1.0;
+    double p[3] = {u.px, u.py, pz};
+    double pa = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    *min_cos = fmin(*min_cos, fabs(p[0] * nf[0] + p[1] * nf[1]) / pa);
+    bool through = snell(p, nf, 1.0);
+    u.px = p[0];
+    u.py = p[1];
+    if (!through) return false;
+    out_p[0] = p[0];
+    out_p[1] = p[1];
+    out_p[2] = p[2];
+    return true;
+}
+
+// Integrate inside the box from (r, p) just inside a face.  On RS_OK r, p
+// hold the exit point and the momentum in air.
+__device__ inline int integrate_box64(const SceneDev& s, const OptsDev& o, double r[3], double p[3],
+                                      LaneCount& cnt, double* min_cos)
+{
+    St64 u = {r[0], r[1], p[0], p[1]};
+    double z = r[2];
+    const double pz = p[2];
+    Rhs64 r1;
+    r1.W = w0_cold(zarg64(s, u.x, u.y));
+    r1.dW = mk(0.0, 0.0);
+    rhs64(s, u.x, u.y, r1.W, r1.ax, r1.ay, r1.dW);
+    double h = (o.integ == 0) ? o.h : o.h0;
+    bool last_rej = false;
+    for (;;) {
+        if (cnt.steps >= o.max_steps) return RS_MAX_STEPS;
+        St64 ue;
+        Rhs64 re;
+        double hnext = h;
+        if (o.integ == 0) {
+            rk4_step64(s, u, r1, h, ue, re);
+        } else {
+            double err = dp5_step64(s, u, r1, h, o.rtol, o.atol, ue, re);
+            if (!isfinite(err)) return RS_NONFINITE;
+            if (err > 1.0) {
+                h *= fmax(0.2, 0.9 * pow(err, -0.2));
+                last_rej = true;
+                cnt.rejected++;
+                if (h < o.h_min) return RS_UNDERFLOW;
+                continue;
+            }
+            double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+            fac = fmin(5.0, fmax(0.2, fac));
+            if (last_rej) fac = fmin(fac, 1.0);
+            last_rej = false;
+            hnext = fmin(h * fac, o.h_max);
+        }
+        cnt.steps++;
+        if (!(isfinite(ue.x) && isfinite(ue.y) && isfinite(ue.px) && isfinite(ue.py))) return RS_NONFINITE;
+        bool ev = (ue.y > s.ytop) || (ue.x > s.hw) || (ue.x < -s.hw) ||
+                  (s.mirror == 0 && ue.y + re.W.re / s.k < 0.0);
+        if (!ev) {
+            u = ue;
+            r1 = re;
+            z += pz * h;
+            h = hnext;
+            continue;
+        }
+        double dtau, pout[3];
+        bool out = handle_events64(s, o, u, r1, pz, h, ue, re, &dtau, pout, min_cos);
+        z += pz * dtau;
+        if (++cnt.events > o.max_events) return RS_MAX_EVENTS;
+        h = (o.integ == 0) ? o.h : hnext;
+        if (out) {
+            r[0] = u.x; r[1] = u.y; r[2] = z;
+            p[0] = pout[0]; p[1] = pout[1]; p[2] = pout[2];
+            return RS_OK;
+        }
+    }
+}
+
+// Complete path of one ray in FP64.  Returns the status; the exit point and
+// the unit exit direction go to out_org / out_dir.
+__device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const double org[3], const double dir[3],
+                                  double out_org[3], double out_dir[3], LaneCount& cnt, double* min_cos)
+{
+    double r[3] = {org[0], org[1], org[2]};
+    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double p[3] = {dir[0] / nd, dir[1] / nd, dir[2] / nd};
+    for (;;) {
+        if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(p[0]) && isfinite(p[1]) &&
+              isfinite(p[2])))
+            return RS_NONFINITE;
+        int face;
+        double tb = air_box_entry(s, r, p, &face);
+        double xi;
+        double tg = air_contact(s, r, p, &xi);
+        if (!(tb < kInf) && !(tg < kInf)) {
+            for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
+            return RS_OK;
+        }
+        if (++cnt.events > o.max_events) return RS_MAX_EVENTS;
+        if (tg <= tb) {
+            for (int i = 0; i < 3; ++i) r[i] += tg * p[i];
+            double nx = 0.0, ny = 1.0;
+            if (!(s.mirror == 1 || s.A == 0.0)) {
+                double sn, c;
+                sincos(s.k * xi, &sn, &c);
+                nx = s.e * sn;
+                ny = 1.0 - s.e * c;
+                double inv = 1.0 / sqrt(nx * nx + ny * ny);
+                nx *= inv;
+                ny *= inv;
+            }
+            *min_cos = fmin(*min_cos, fabs(p[0] * nx + p[1] * ny));
+            reflect2(p[0], p[1], nx, ny);
+            continue;
+        }
+        for (int i = 0; i < 3; ++i) r[i] += tb * p[i];
+        double nf[3] = {0.0, 0.0, 0.0};
+        if (face == 0) { r[1] = s.ytop; nf[1] = -1.0; }
+        else if (face == 1) { r[0] = s.hw; nf[0] = -1.0; }
+        else { r[0] = -s.hw; nf[0] = 1.0; }
+        *min_cos = fmin(*min_cos, fabs(p[0] * nf[0] + p[1] * nf[1]));
+        cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
+        double n2 = 1.0 / sqrt(norm2(mk(1.0 + W.re, W.im)));
+        if (!snell(p, nf, n2)) continue;
+        int st = integrate_box64(s, o, r, p, cnt, min_cos);
+        if (st != RS_OK) return st;
+    }
+}
+
+}  // namespace gc

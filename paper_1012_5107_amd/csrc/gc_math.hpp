@@ -1,0 +1,321 @@
+// gc_math.hpp -- device math for the gfx950 grating-cloak ray tracer.
+//
+// Index profile of the grating cloak (Sec. 2, eq. (1)):
+//     n = 1 / |1 + W|,  W = W0(Z),  Z = i c k e^{ik(x+iy)} = -A k e^{-ky} e^{ikx}
+// (c = iA).  Rays follow dr/dtau = p, dp/dtau = grad(n^2)/2 = a with
+//     a_x + i a_y = i k conj(W) (1 + W)^2 / |1 + W|^6,
+// which is eq. (12) multiplied by n and is eq. (11) after dt = n^2 dtau.
+//
+// The Lambert function is never started cold inside the integration loop.
+// With Q = Z e^{-W} = -A k exp(-k y - Re W) cis(k x - Im W) the equation
+// W e^W = Z reads f(W) = W - Q = 0, f' = 1 + Q, f'' = -Q, and one Halley
+// step W <- W - 2 f f' / (2 f'^2 + f Q) costs a single complex exponential.
+// The start is a first-order predictor from the previous evaluation,
+// W + (dW/dzeta) dzeta with dW/dzeta = i k W / (1 + W).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gc {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr double kInvTwoPi = 0.15915494309189533577;
+constexpr double kLog2e = 1.44269504088896340736;
+constexpr double kInvE = 0.36787944117144232160;
+
+// ---------------------------------------------------------------------------
+// Launch-time parameter blocks (kernel arguments live in constant memory).
+// ---------------------------------------------------------------------------
+struct SceneDev {
+    double L, A, hw, ytop, K;
+    double k, e, invL;
+    double ybp;        // branch-point height (1 + ln(A k)) / k: Z crosses the cut only below it
+    double S_hw;       // grating height at x = +-half_width
+    int cloak, mirror;
+};
+
+struct CamDev {
+    double eye[3], f[3], r[3], u[3];
+    double t, aspect;
+    int W, H, spp, jitter;
+    uint64_t seed;
+    long long scene_index;
+};
+
+struct OptsDev {
+    int integ;         // 0 RK4, 1 DOPRI5
+    int max_events;
+    long long max_steps;
+    double h, rtol, atol, h_max, h0, h_min;
+    double wfb2;       // |1 + W|^2 below which FP32 redoes W in FP64
+};
+
+enum RayStatus { RS_OK = 0, RS_MAX_STEPS = 1, RS_MAX_EVENTS = 2, RS_NONFINITE = 3, RS_UNDERFLOW = 4 };
+
+// ---------------------------------------------------------------------------
+// Minimal complex arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T> struct cx { T re, im; };
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T> __device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.re, -a.im}; }
+
+// ---------------------------------------------------------------------------
+// Elementary functions: FP32 maps onto the hardware transcendental unit
+// (v_exp_f32 is 2^x, v_sin/v_cos take revolutions), FP64 uses the device
+// math library.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float exp_e(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ __forceinline__ double exp_e(double x) { return exp(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// cis(2 pi r) for |r| <= 1
+__device__ __forceinline__ void cis_rev(float r, float& c, float& s)
+{
+    c = __builtin_amdgcn_cosf(r);
+    s = __builtin_amdgcn_sinf(r);
+}
+__device__ __forceinline__ void cis_rev(double r, double& c, double& s) { sincospi(2.0 * r, &s, &c); }
+
+// ---------------------------------------------------------------------------
+// Lambert W0 from scratch (FP64): entry points, stage points below the
+// branch-point height, and recovery.  Halley iteration on f = W - z e^{-W}
+// from the textbook starts (Corless et al., Adv. Comput. Math. 5 (1996)):
+// Taylor series near 0, the branch-point series near -1/e, log(1 + z) and
+// the asymptotic log z - log log z.  The first start whose limit has a small
+// residual and lies in the principal range is kept.
+// ---------------------------------------------------------------------------
+__device__ inline cx<double> cexp_d(cx<double> w)
+{
+    double s, c;
+    sincos(w.im, &s, &c);
+    double m = exp(w.re);
+    return {m * c, m * s};
+}
+__device__ inline cx<double> clog_d(cx<double> z) { return {log(hypot(z.re, z.im)), atan2(z.im, z.re)}; }
+__device__ inline cx<double> csqrt_d(cx<double> z)
+{
+    double r = hypot(z.re, z.im);
+    double a = sqrt(0.5 * (r + fabs(z.re)));
+    if (a == 0.0) return {0.0, 0.0};
+    double b = 0.5 * z.im / a;
+    if (z.re >= 0.0) return {a, b};
+    return {fabs(b), copysign(a, z.im)};
+}
+__device__ inline cx<double> cdiv_d(cx<double> a, cx<double> b)
+{
+    double inv = 1.0 / norm2(b);
+    return inv * (a * conjg(b));
+}
+
+__device__ inline bool w0_principal(cx<double> w)
+{
+    if (!(fabs(w.im) < kPi)) return false;
+    if (w.im == 0.0) return w.re >= -1.0 - 1e-12;
+    double s, c;
+    sincos(w.im, &s, &c);
+    return w.re > -w.im * c / s - 1e-10;
+}
+
+__device__ inline bool w0_refine(cx<double> z, cx<double>& w)
+{
+    for (int it = 0; it < 40; ++it) {
+        cx<double> q = z * cexp_d(mk(-w.re, -w.im));
+        cx<double> f = w - q;
+        cx<double> fp = mk(1.0 + q.re, q.im);
+        cx<double> den = 2.0 * (fp * fp) + f * q;
+        if (den.re == 0.0 && den.im == 0.0) break;
+        cx<double> d = cdiv_d(2.0 * (f * fp), den);
+        w = w - d;
+        if (!(norm2(d) > 1e-32 * fmax(1.0, norm2(w)))) break;
+    }
+    cx<double> res = w * cexp_d(w) - z;
+    return isfinite(w.re) && isfinite(w.im) &&
+           norm2(res) <= 1e-28 * fmax(norm2(z), 1e-300) && w0_principal(w);
+}
+
+__device__ inline cx<double> w0_cold(cx<double> z)
+{
+    double az2 = norm2(z);
+    if (az2 == 0.0) return z;
+    cx<double> starts[4];
+    int n = 0;
+    if (az2 < 0.0625) starts[n++] = z - z * z + 1.5 * (z * z * z);
+    cx<double> zb = mk(z.re + kInvE, z.im);
+    if (norm2(zb) < 0.09) {
+        // p = sqrt(2 (e z + 1)) with e z + 1 = e (z + 1/e)
+        cx<double> p = csqrt_d(mk(2.0 * 2.71828182845904523536, 0.0) * zb);
+        starts[n++] = mk(-1.0, 0.0) + p - (1.0 / 3.0) * (p * p) + (11.0 / 72.0) * (p * p * p);
+    }
+    starts[n++] = clog_d(mk(1.0 + z.re, z.im));
+    {
+        cx<double> l1 = clog_d(z), l2 = clog_d(l1);
+        starts[n++] = l1 - l2 + cdiv_d(l2, l1);
+    }
+    cx<double> first = starts[0];
+    bool have = false;
+    for (int i = 0; i < n; ++i) {
+        cx<double> w = starts[i];
+        bool ok = w0_refine(z, w);
+        if (ok) return w;
+        if (!have) { first = w; have = true; }
+    }
+    return first;
+}
+
+// Z at (x, y) in FP64 with x reduced to the central period.
+__device__ inline cx<double> zarg64(const SceneDev& s, double x, double y)
+{
+    double xr = x - s.L * rint(x * s.invL);
+    double c, sn;
+    cis_rev(xr * s.invL, c, sn);
+    double m = -s.e * exp(-s.k * y);
+    return {m * c, m * sn};
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side: W0 update, acceleration and dW/dzeta at (x, y).
+// `fx` is x inside its period (|fx| <= L/2 up to a small overshoot): the
+// phase of Z only needs fx / L in revolutions.
+// On entry W holds the predicted value; on exit the converged one.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void halley_step(const SceneDev& s, T fx, T y, cx<T>& W)
+{
+    const T k = (T)s.k, e = (T)s.e, invL = (T)s.invL;
+    T m = -e * exp_e(-k * y - W.re);
+    T c, sn;
+    cis_rev(fx * invL - W.im * (T)kInvTwoPi, c, sn);
+    cx<T> q = {m * c, m * sn};
+    cx<T> f = W - q;
+    cx<T> fp = {(T)1 + q.re, q.im};
+    cx<T> num = (T)2 * (f * fp);
+    cx<T> den = (T)2 * (fp * fp) + f * q;
+    T inv = rcp(norm2(den));
+    cx<T> d = inv * (num * conjg(den));
+    W = W - d;
+}
+
+// acceleration and derivative of W from a converged W
+template <typename T>
+__device__ __forceinline__ void accel_from_w(const SceneDev& s, cx<T> W, T& ax, T& ay, cx<T>& dW, T& d2)
+{
+    const T k = (T)s.k;
+    cx<T> D = {(T)1 + W.re, W.im};
+    d2 = norm2(D);
+    T r = rcp(d2);
+    cx<T> D2 = D * D;
+    cx<T> t = conjg(W) * D2;
+    T r3 = r * r * r;
+    // i k t r^3
+    ax = -k * t.im * r3;
+    ay = k * t.re * r3;
+    // dW/dzeta = i k W conj(D) / |D|^2
+    cx<T> u = W * conjg(D);
+    dW = {-k * u.im * r, k * u.re * r};
+}
+
+// FP64 right-hand side with warm start: iterate Halley to convergence.
+// Below the branch-point height, within a tenth of a period of a crest line
+// x = N Lambda, Z lies next to its branch cut and the warm start could cross
+// it: there W0 is taken from scratch.
+__device__ __forceinline__ bool near_cut(double fx, double y, double ybp, double L)
+{
+    return y < ybp && fabs(fx) < 0.1 * L;
+}
+
+__device__ inline void rhs64(const SceneDev& s, double x, double y, cx<double>& W,
+                             double& ax, double& ay, cx<double>& dW)
+{
+    double fx = x - s.L * rint(x * s.invL);
+    if (near_cut(fx, y, s.ybp, s.L)) {
+        W = w0_cold(zarg64(s, x, y));
+    } else {
+        for (int it = 0; it < 8; ++it) {
+            cx<double> w0 = W;
+            halley_step<double>(s, fx, y, W);
+            double d2 = norm2(W - w0);
+            if (!(d2 > 1e-30 * fmax(1e-10, norm2(W)))) break;
+        }
+        if (!(isfinite(W.re) && isfinite(W.im))) W = w0_cold(zarg64(s, x, y));
+    }
+    double d2;
+    accel_from_w<double>(s, W, ax, ay, dW, d2);
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output number n of the
+// generator seeded with `seed`.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double uniform53(uint64_t seed, uint64_t n)
+{
+    return (double)(splitmix64(seed, n) >> 11) * 1.1102230246251565404e-16;
+}
+
+// Camera sample direction (unit) for pixel (i, j), sample s.
+__device__ inline void camera_dir(const CamDev& c, int i, int j, int smp, double d[3])
+{
+    double du = 0.5, dv = 0.5;
+    if (c.jitter) {
+        uint64_t ctr = ((((uint64_t)c.scene_index * (uint64_t)c.H + (uint64_t)j) * (uint64_t)c.W +
+                         (uint64_t)i) * (uint64_t)c.spp + (uint64_t)smp) * 2ull;
+        du = uniform53(c.seed, ctr);
+        dv = uniform53(c.seed, ctr + 1ull);
+    }
+    double sx = (2.0 * (i + du) / c.W - 1.0) * c.t * c.aspect;
+    double sy = (1.0 - 2.0 * (j + dv) / c.H) * c.t;
+    double n2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        d[a] = c.f[a] + sx * c.r[a] + sy * c.u[a];
+        n2 += d[a] * d[a];
+    }
+    double inv = 1.0 / sqrt(n2);
+    for (int a = 0; a < 3; ++a) d[a] *= inv;
+}
+
+// Sky colour for a unit direction: with azimuth phi = atan2(d_x, -d_z) and
+// elevation theta = atan2(d_y, hypot(d_x, d_z)), cos 4 phi and sin 8 theta
+// are taken as the real / imaginary parts of powers of the unit complex
+// numbers (-d_z + i d_x)/rho and (rho + i d_y)/|d|, rho = hypot(d_x, d_z).
+template <typename T>
+__device__ inline void sky_rgb(T K, const T d[3], T rgb[3])
+{
+    T rho = sqrt(d[0] * d[0] + d[2] * d[2]);
+    T nrm = sqrt(rho * rho + d[1] * d[1]);
+    cx<T> a = {rho > (T)0 ? -d[2] / rho : (T)1, rho > (T)0 ? d[0] / rho : (T)0};
+    cx<T> a2 = a * a;
+    cx<T> a4 = a2 * a2;
+    cx<T> b = {rho / nrm, d[1] / nrm};
+    cx<T> b2 = b * b, b4 = b2 * b2, b8 = b4 * b4;
+    T c4 = a4.re, s8 = b8.im;
+    T ta, tb;
+    if (isinf(K)) {
+        ta = c4 > 0 ? (T)1 : (c4 < 0 ? (T)-1 : (T)0);
+        tb = s8 > 0 ? (T)1 : (s8 < 0 ? (T)-1 : (T)0);
+    } else {
+        ta = tanh(K * c4);
+        tb = tanh(K * s8);
+    }
+    T m = (T)0.5 + (T)0.5 * ta * tb;
+    const T Ca[3] = {(T)0.95, (T)0.85, (T)0.30};
+    const T Cb[3] = {(T)0.10, (T)0.20, (T)0.55};
+    for (int c = 0; c < 3; ++c) rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);
+}
+
+}  // namespace gc
