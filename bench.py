@@ -81,16 +81,22 @@ def main():
         ctx.render(ref_sc, cam, op32, prec="f32", out=ref, stats=False)
         ctx.cross_correlate(img, ref)
         e1.synchronize()
-        kernel_ms.append(e0.elapsed_time(e1))
+        kernel_ms.append(e0.elapsed_time(e1))   # the whole FP32 render
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    print(f"# fp32 step {dt * 1e3:.1f} ms, render kernel {np.mean(kernel_ms):.1f} ms", file=sys.stderr, flush=True)
+    print(f"# fp32 step {dt * 1e3:.1f} ms, FP32 render {np.mean(kernel_ms):.1f} ms", file=sys.stderr, flush=True)
 
     steps32 = st32["accepted_steps"]
     rays = st32["rays"]
     value = steps32 / dt
-    k_ms = float(np.mean(kernel_ms))
-    achieved = steps32 * FLOP_PER_STEP[op32["integrator"]] / (k_ms * 1e-3)
+    # dominant kernel: the FP32 in-cloak kernel; its device time comes from
+    # HIP events recorded by the library around each of its launches on this
+    # stream, and its work is the steps it took (the rest were taken by the
+    # FP64 event kernel)
+    _, stk = ctx.render(sc, cam, op32, prec="f32", out=img)
+    hot_steps = stk["accepted_steps"] - stk["fp64_steps"]
+    k_ms = stk["hot_ms"]
+    achieved = hot_steps * FLOP_PER_STEP[op32["integrator"]] / (k_ms * 1e-3)
 
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
@@ -112,7 +118,12 @@ def main():
         "cc_fp32": c32,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_render32", "kernel_ms": k_ms},
+                     "kernel": "k_wf_box<DOPRI5>" if op32["integrator"] == "dopri5" else "k_wf_box<RK4>",
+                     "kernel_ms": k_ms, "kernel_steps": hot_steps},
+        "fp32_breakdown": {"hot_ms": stk["hot_ms"], "event_ms": stk["event_ms"], "tail_ms": stk["tail_ms"],
+                           "total_ms": stk["total_ms"], "rounds": stk["rounds"], "tail_rays": stk["tail_rays"],
+                           "fp64_steps": stk["fp64_steps"], "fallbacks": stk["fallbacks"],
+                           "failed": stk["failed"]},
     }
 
     if not args.no_fp64:

@@ -120,11 +120,18 @@ typedef struct {
 
 typedef struct {
     int64_t rays;            /* samples traced */
-    int64_t accepted_steps;  /* integrator steps kept inside the cloak */
+    int64_t accepted_steps;  /* integrator steps kept inside the cloak (all precisions) */
     int64_t rejected_steps;  /* DOPRI5 attempts rejected */
     int64_t events;          /* box entries/exits, internal reflections, grating contacts */
-    int64_t fallbacks;       /* FP32 path: Lambert-W evaluations redone in FP64 */
+    int64_t fallbacks;       /* FP32 path: steps handed to FP64 because a stage needed it */
     int64_t failed;          /* samples with status != GC_RAY_OK */
+    int64_t fp64_steps;      /* FP32 path: accepted steps taken by the FP64 event kernel (rounds) */
+    int64_t rounds;          /* FP32 path: in-cloak / event rounds */
+    int64_t tail_rays;       /* FP32 path: rays finished by the tail kernel */
+    double hot_ms;           /* FP32 path: device time of the FP32 in-cloak kernel (HIP events) */
+    double event_ms;         /* FP32 path: device time of the FP64 event and air kernels */
+    double tail_ms;          /* FP32 path: device time of the tail kernel */
+    double total_ms;         /* FP32 path: device time of the whole call */
 } gc_stats;
 
 typedef struct gc_ctx gc_ctx;
@@ -164,6 +171,20 @@ gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts,
  * counters and then the call synchronises the stream. */
 gc_status gc_render(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera,
                     const gc_opts* opts, float* d_rgb, gc_stats* st, hipStream_t stream);
+
+/* Render n_scenes scenes in one launch of the FP32 pipeline (opts->prec
+ * must be GC_F32): all samples of all scenes share the queues of the
+ * persistent in-cloak kernel, so scenes of uneven resolution, amplitude,
+ * cloak width and viewpoint keep the GPU busy together.  scenes[i] and
+ * cameras[i] are host arrays of n_scenes entries; d_rgb[i] (host array of
+ * device pointers) receives image i (height_i x width_i x 3 float32).  When
+ * d_ref is non-null, d_ref[i] is the reference image of scene i and C0[i]
+ * (host, n_scenes doubles) receives eq. (15) at zero shift for it.  `st`
+ * (may be null) receives counters summed over all scenes.  Synchronises
+ * the stream.  Reflection-only scenes (mirror = 1) are not accepted here. */
+gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                          const gc_opts* opts, float* const* d_rgb, const float* const* d_ref, double* C0,
+                          gc_stats* st, hipStream_t stream);
 
 /* Zero-shift cross-correlation of eqs. (14)-(15) between d_img (g) and the
  * reference d_ref (f): both npix x nch float32, channel fastest.  Each

@@ -47,15 +47,19 @@ class Opts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("accepted_steps", ctypes.c_int64), ("rejected_steps", ctypes.c_int64),
-                ("events", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("failed", ctypes.c_int64)]
+                ("events", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("fp64_steps", ctypes.c_int64), ("rounds", ctypes.c_int64), ("tail_rays", ctypes.c_int64),
+                ("hot_ms", ctypes.c_double), ("event_ms", ctypes.c_double), ("tail_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
 
 
 # every symbol the header declares
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
-           "gc_cross_correlate"]
+           "gc_render_batch", "gc_cross_correlate"]
 
 _lib = None
 
@@ -82,6 +86,10 @@ def load():
     L.gc_render.argtypes = [vp, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts), vp,
                             ctypes.POINTER(Stats), vp]
     L.gc_render.restype = ctypes.c_int
+    L.gc_render_batch.argtypes = [vp, i32, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts),
+                                  ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(Stats), vp]
+    L.gc_render_batch.restype = ctypes.c_int
     L.gc_cross_correlate.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), vp]
     L.gc_cross_correlate.restype = ctypes.c_int
@@ -181,6 +189,27 @@ class Context:
                                 ctypes.byref(st) if stats else None, _stream_handle(stream)))
         return img, (st.as_dict() if stats else None)
 
+    def render_batch(self, scenes, cameras, opts, refs=None, outs=None, stream=None):
+        """Render several scenes in one FP32 pipeline launch.  Returns (list of
+        H x W x 3 images, list of C0 or None, stats dict)."""
+        n = len(scenes)
+        imgs = outs if outs is not None else [
+            torch.empty((c["height"], c["width"], 3), dtype=torch.float32, device=self.device) for c in cameras]
+        sc = (Scene * n)(*[make_scene(x) for x in scenes])
+        cam = (Camera * n)(*[make_camera(x) for x in cameras])
+        op = make_opts(opts, "f32")
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in imgs])
+        rp = None
+        c0 = None
+        if refs is not None:
+            refs = [r.to(self.device, torch.float32).contiguous() for r in refs]
+            rp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in refs])
+            c0 = (ctypes.c_double * n)()
+        st = Stats()
+        _check(load().gc_render_batch(self._h, n, sc, cam, ctypes.byref(op), ptrs, rp, c0, ctypes.byref(st),
+                                      _stream_handle(stream)))
+        return imgs, (list(c0) if c0 is not None else None), st.as_dict()
+
     def cross_correlate(self, img, ref, stream=None):
         """eq. (15) at zero shift and the Pearson form, from device images."""
         img = img.to(self.device, torch.float32).contiguous()
@@ -208,6 +237,10 @@ def render(scene, camera, opts, prec="f64", device=0):
 
 def trace_rays(scene, opts, org, dirs, prec="f64", device=0):
     return context(device).trace_rays(scene, opts, org, dirs, prec)
+
+
+def render_batch(scenes, cameras, opts, refs=None, device=0):
+    return context(device).render_batch(scenes, cameras, opts, refs)
 
 
 def cross_correlate(img, ref, device=0):

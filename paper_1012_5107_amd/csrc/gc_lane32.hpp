@@ -1,29 +1,30 @@
-// gc_lane32.hpp -- FP32 integration inside the cloak.
+// gc_lane32.hpp -- FP32 integration inside the cloak (the hot loop).
 //
-// The ray state inside the box is kept in FP32 with x split into an integer
-// grating period and the offset within it (the index of eq. (1) is exactly
-// Lambda-periodic in x, so the phase of Z only needs the offset), and every
+// The in-cloak ray state is FP32 with x split into an integer grating period
+// and the offset within it (the index of eq. (1) is exactly Lambda-periodic
+// in x, so the phase of Z only needs the offset, in revolutions), and every
 // state component carries a compensation term so that the many small
-// increments of a long path do not lose their low bits.
+// increments of a long path keep their low bits.
 //
-// FP64 is used only where the precision split requires it:
-//   - Lambert W near the branch point Z = -1/e: when |1 + W| falls below
-//     w_fallback (n = 1/|1 + W| is then large and FP32 loses digits), and
-//     for stage points below the branch-point height, where Z can cross the
-//     branch cut and a warm start could land on another branch;
-//   - every event: a step flagged in FP32 as crossing a face or the grating
-//     is redone from its start in FP64, and the crossing is located there
-//     (root solve of the partial step), as is everything in air.
+// Nothing here touches FP64.  A stage point that needs it -- |1 + W| below
+// w_fallback (n = 1/|1 + W| is large near the branch point Z = -1/e and FP32
+// loses digits there), or an evaluation path that crosses the branch cut
+// (a crest line x = N Lambda below the branch-point height, where a warm
+// start could land on another branch) -- only raises a flag; the caller then
+// hands the whole step to the FP64 event path, as it does for face and
+// grating crossings.
 #pragma once
-#include "gc_lane64.hpp"
+#include "gc_math.hpp"
 
 namespace gc {
 
+// per-scene FP32 constants of the hot loop
 struct Sc32 {
     float L, invL, k, invk, ne, mkl2e, ybp, wfb2;
 };
 
-__device__ __forceinline__ Sc32 make_sc32(const SceneDev& s, const OptsDev& o)
+
+__device__ __forceinline__ Sc32 make_sc32(const SceneDev& s, double wfb2)
 {
     Sc32 c;
     c.L = (float)s.L;
@@ -33,7 +34,7 @@ __device__ __forceinline__ Sc32 make_sc32(const SceneDev& s, const OptsDev& o)
     c.ne = (float)(-s.e);
     c.mkl2e = (float)(-s.k * kLog2e);
     c.ybp = (float)s.ybp;
-    c.wfb2 = (float)o.wfb2;
+    c.wfb2 = (float)wfb2;
     return c;
 }
 
@@ -44,11 +45,11 @@ struct Rhs32 {
 
 struct St32 {
     int cell;
-    float fx, y, px, py;   // leading parts (fx: offset of x inside period `cell`)
+    float fx, y, px, py;      // leading parts (fx: offset of x inside period `cell`)
     float lx, ly, lpx, lpy;   // compensation terms
 };
 
-// One Halley step for W e^W = Z in the form W - Z e^{-W} = 0.
+// One Halley step for W e^W = Z in the form W - Z e^{-W} = 0.  Returns |dW|^2.
 __device__ __forceinline__ float halley32(const Sc32& c, float fx, float y, cx<float>& W)
 {
     float m = c.ne * __builtin_amdgcn_exp2f(c.mkl2e * y - W.re * 1.44269504088896341f);
@@ -65,12 +66,32 @@ __device__ __forceinline__ float halley32(const Sc32& c, float fx, float y, cx<f
     return norm2(d);
 }
 
-// RHS in FP32 at offset fx (period `cell`) and height y; W holds the
-// prediction on entry.  NITER Halley steps (0 = iterate to convergence).
-template <int NITER>
-__device__ __forceinline__ void rhs32(const SceneDev& s, const Sc32& c, int cell, float fx, float y,
-                                      Rhs32& r, int& fallbacks)
+// acceleration and dW/dzeta from a converged W (FP32)
+__device__ __forceinline__ float accel32(const Sc32& c, Rhs32& r)
 {
+    cx<float> D = {1.0f + r.W.re, r.W.im};
+    float d2 = norm2(D);
+    float rr = __builtin_amdgcn_rcpf(d2);
+    cx<float> t = conjg(r.W) * (D * D);
+    float kr3 = c.k * rr * rr * rr;
+    r.ax = -kr3 * t.im;
+    r.ay = kr3 * t.re;
+    cx<float> u = r.W * conjg(D);
+    float kr = c.k * rr;
+    r.dW = {-kr * u.im, kr * u.re};
+    return d2;
+}
+
+// RHS at offset fx and height y, warm-started from the evaluation `prev`
+// taken at (xp, yp) (offsets in the same period): predictor, NITER Halley
+// steps (0: iterate until the update is below FP32 resolution), acceleration.
+// Sets `bad` when the point needs the FP64 path.
+template <int NITER>
+__device__ __forceinline__ void eval32(const Sc32& c, float fx, float y, float xp, float yp, const Rhs32& prev,
+                                       Rhs32& r, bool& bad)
+{
+    const float dx = fx - xp, dy = y - yp;
+    r.W = {prev.W.re + prev.dW.re * dx - prev.dW.im * dy, prev.W.im + prev.dW.re * dy + prev.dW.im * dx};
     if (NITER > 0) {
 #pragma unroll
         for (int it = 0; it < NITER; ++it) halley32(c, fx, y, r.W);
@@ -80,22 +101,16 @@ __device__ __forceinline__ void rhs32(const SceneDev& s, const Sc32& c, int cell
             if (!(d2 > 1e-13f * (1.0f + norm2(r.W)))) break;
         }
     }
-    float d2;
-    accel_from_w<float>(s, r.W, r.ax, r.ay, r.dW, d2);
-    if (!(d2 >= c.wfb2) || (y < c.ybp && fabsf(fx) < 0.1f * c.L)) {
-        // FP64 redo near the branch point
-        double x = (double)cell * s.L + (double)fx;
-        cx<double> W = {(double)r.W.re, (double)r.W.im};
-        if (!(isfinite(W.re) && isfinite(W.im)) || norm2(mk(1.0 + W.re, W.im)) < 1e-6) W = w0_cold(zarg64(s, x, y));
-        double ax, ay;
-        cx<double> dW;
-        rhs64(s, x, (double)y, W, ax, ay, dW);
-        r.W = {(float)W.re, (float)W.im};
-        r.dW = {(float)dW.re, (float)dW.im};
-        r.ax = (float)ax;
-        r.ay = (float)ay;
-        fallbacks++;
-    }
+    float d2 = accel32(c, r);
+    // the crest line of this period is fx = 0
+    bad |= !(d2 >= c.wfb2) || (fminf(y, yp) < c.ybp && fx * xp <= 0.0f);
+}
+
+// RHS at the point where r.W was itself obtained (re-convergence after a load).
+__device__ __forceinline__ void refresh32(const Sc32& c, float fx, float y, Rhs32& r)
+{
+    halley32(c, fx, y, r.W);
+    accel32(c, r);
 }
 
 __device__ __forceinline__ void comp_add(float& hi, float& lo, float inc)
@@ -106,96 +121,44 @@ __device__ __forceinline__ void comp_add(float& hi, float& lo, float inc)
     hi = t;
 }
 
-__device__ __forceinline__ St64 promote(const SceneDev& s, const St32& u)
+__device__ __forceinline__ bool renorm_cell(const Sc32& c, St32& u)
 {
-    St64 v;
-    v.x = (double)u.cell * s.L + ((double)u.fx + (double)u.lx);
-    v.y = (double)u.y + (double)u.ly;
-    v.px = (double)u.px + (double)u.lpx;
-    v.py = (double)u.py + (double)u.lpy;
-    return v;
+    if (u.fx > 0.5f * c.L) { u.fx -= c.L; u.cell += 1; return true; }
+    if (u.fx < -0.5f * c.L) { u.fx += c.L; u.cell -= 1; return true; }
+    return false;
 }
 
-__device__ __forceinline__ void demote_split(double v, float& hi, float& lo)
-{
-    hi = (float)v;
-    lo = (float)(v - (double)hi);
-}
-
-__device__ __forceinline__ St32 demote(const SceneDev& s, const St64& v)
-{
-    St32 u;
-    double cellf = rint(v.x * s.invL);
-    u.cell = (int)cellf;
-    demote_split(v.x - cellf * s.L, u.fx, u.lx);
-    demote_split(v.y, u.y, u.ly);
-    demote_split(v.px, u.px, u.lpx);
-    demote_split(v.py, u.py, u.lpy);
-    return u;
-}
-
-__device__ __forceinline__ Rhs32 demote(const Rhs64& r)
-{
-    Rhs32 q;
-    q.ax = (float)r.ax;
-    q.ay = (float)r.ay;
-    q.W = {(float)r.W.re, (float)r.W.im};
-    q.dW = {(float)r.dW.re, (float)r.dW.im};
-    return q;
-}
-
-__device__ __forceinline__ Rhs64 promote(const SceneDev& s, const St64& u, const Rhs32& r)
-{
-    Rhs64 q;
-    q.W = {(double)r.W.re, (double)r.W.im};
-    rhs64(s, u.x, u.y, q.W, q.ax, q.ay, q.dW);
-    return q;
-}
-
-__device__ __forceinline__ void renorm_cell(const Sc32& c, St32& u)
-{
-    if (u.fx > 0.5f * c.L) { u.fx -= c.L; u.cell += 1; }
-    else if (u.fx < -0.5f * c.L) { u.fx += c.L; u.cell -= 1; }
-}
-
-// Predicted W at a point displaced by (dx, dy) from the one r was taken at.
-__device__ __forceinline__ void predict(Rhs32& out, const Rhs32& r, float dx, float dy)
-{
-    out.W = {r.W.re + r.dW.re * dx - r.dW.im * dy, r.W.im + r.dW.re * dy + r.dW.im * dx};
-}
-
-// Classical RK4 step in FP32 (one Halley step per stage from the predictor).
-__device__ __forceinline__ void rk4_step32(const SceneDev& s, const Sc32& c, const St32& u, const Rhs32& r1,
-                                           float h, St32& ue, Rhs32& re, int& fb)
+// Classical RK4 step (one Halley step per stage from the predictor); re is
+// the RHS at the end point, i.e. the next step's first stage.
+__device__ __forceinline__ void rk4_step32(const Sc32& c, const St32& u, const Rhs32& r1, float h, St32& ue,
+                                           Rhs32& re, bool& bad)
 {
     const float hh = 0.5f * h;
     Rhs32 r2, r3, r4;
     float x2 = u.fx + hh * u.px, y2 = u.y + hh * u.py;
     float p2x = u.px + hh * r1.ax, p2y = u.py + hh * r1.ay;
-    predict(r2, r1, hh * u.px, hh * u.py);
-    rhs32<1>(s, c, u.cell, x2, y2, r2, fb);
+    eval32<1>(c, x2, y2, u.fx, u.y, r1, r2, bad);
     float x3 = u.fx + hh * p2x, y3 = u.y + hh * p2y;
     float p3x = u.px + hh * r2.ax, p3y = u.py + hh * r2.ay;
-    predict(r3, r2, x3 - x2, y3 - y2);
-    rhs32<1>(s, c, u.cell, x3, y3, r3, fb);
+    eval32<1>(c, x3, y3, x2, y2, r2, r3, bad);
     float x4 = u.fx + h * p3x, y4 = u.y + h * p3y;
     float p4x = u.px + h * r3.ax, p4y = u.py + h * r3.ay;
-    predict(r4, r3, x4 - x3, y4 - y3);
-    rhs32<1>(s, c, u.cell, x4, y4, r4, fb);
+    eval32<1>(c, x4, y4, x3, y3, r3, r4, bad);
     const float h6 = h * (1.0f / 6.0f);
     ue = u;
     comp_add(ue.fx, ue.lx, h6 * (u.px + 2.0f * p2x + 2.0f * p3x + p4x));
     comp_add(ue.y, ue.ly, h6 * (u.py + 2.0f * p2y + 2.0f * p3y + p4y));
     comp_add(ue.px, ue.lpx, h6 * (r1.ax + 2.0f * r2.ax + 2.0f * r3.ax + r4.ax));
     comp_add(ue.py, ue.lpy, h6 * (r1.ay + 2.0f * r2.ay + 2.0f * r3.ay + r4.ay));
-    predict(re, r4, ue.fx - x4, ue.y - y4);
+    // the end point's RHS (the next step's first stage), then the period shift
+    eval32<1>(c, ue.fx, ue.y, x4, y4, r4, re, bad);
     renorm_cell(c, ue);
-    rhs32<1>(s, c, ue.cell, ue.fx, ue.y, re, fb);
 }
 
-// DOPRI5 step in FP32; returns the scaled RMS error (same norm as FP64).
-__device__ __forceinline__ float dp5_step32(const SceneDev& s, const Sc32& c, const St32& u, const Rhs32& r1,
-                                            float h, float rtol, float atol, St32& ue, Rhs32& re, int& fb)
+// DOPRI5 step in FP32; returns the scaled RMS error over (x, y, px, py).
+// xabs0 = |x| at the step start (for the error scale).
+__device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const Rhs32& r1, float h, float rtol,
+                                            float atol, St32& ue, Rhs32& re, bool& bad)
 {
     const float A[6][6] = {{(float)DP::a21, 0, 0, 0, 0, 0},
                            {(float)DP::a31, (float)DP::a32, 0, 0, 0, 0},
@@ -209,9 +172,8 @@ __device__ __forceinline__ float dp5_step32(const SceneDev& s, const Sc32& c, co
     kx[0] = u.px; ky[0] = u.py; kax[0] = r1.ax; kay[0] = r1.ay;
     Rhs32 rp = r1, rn;
     float xp = u.fx, yp = u.y;
-    float x6 = 0, y6 = 0;
 #pragma unroll
-    for (int st = 1; st < 7; ++st) {
+    for (int st = 1; st < 6; ++st) {
         float sx = 0, sy = 0, sax = 0, say = 0;
 #pragma unroll
         for (int j = 0; j < st; ++j) {
@@ -223,21 +185,14 @@ __device__ __forceinline__ float dp5_step32(const SceneDev& s, const Sc32& c, co
         float x = u.fx + h * sx, y = u.y + h * sy;
         kx[st] = u.px + h * sax;
         ky[st] = u.py + h * say;
-        if (st < 6) {
-            predict(rn, rp, x - xp, y - yp);
-            rhs32<0>(s, c, u.cell, x, y, rn, fb);
-            kax[st] = rn.ax;
-            kay[st] = rn.ay;
-            rp = rn;
-            xp = x;
-            yp = y;
-        } else {
-            x6 = x;
-            y6 = y;
-            (void)sx;
-        }
+        eval32<0>(c, x, y, xp, yp, rp, rn, bad);
+        kax[st] = rn.ax;
+        kay[st] = rn.ay;
+        rp = rn;
+        xp = x;
+        yp = y;
     }
-    // 5th order end state with compensation; its RHS is the 7th stage (FSAL)
+    // 5th order end state (compensated); its RHS is the 7th stage (FSAL)
     {
         float sx = 0, sy = 0, sax = 0, say = 0;
 #pragma unroll
@@ -253,11 +208,9 @@ __device__ __forceinline__ float dp5_step32(const SceneDev& s, const Sc32& c, co
         comp_add(ue.px, ue.lpx, h * sax);
         comp_add(ue.py, ue.lpy, h * say);
     }
-    predict(re, rp, x6 - xp, y6 - yp);
-    float fx_end = ue.fx;
+    const int cell0 = u.cell;
+    eval32<0>(c, ue.fx, ue.y, xp, yp, rp, re, bad);
     renorm_cell(c, ue);
-    rhs32<0>(s, c, ue.cell, ue.fx, ue.y, re, fb);
-    (void)fx_end;
     kx[6] = ue.px;
     ky[6] = ue.py;
     kax[6] = re.ax;
@@ -270,7 +223,7 @@ __device__ __forceinline__ float dp5_step32(const SceneDev& s, const Sc32& c, co
         epx += E[j] * kax[j];
         epy += E[j] * kay[j];
     }
-    float xa0 = fabsf((float)u.cell * c.L + u.fx), xa1 = fabsf((float)ue.cell * c.L + ue.fx);
+    float xa0 = fabsf((float)cell0 * c.L + u.fx), xa1 = fabsf((float)ue.cell * c.L + ue.fx);
     float q0 = h * ex / (atol + rtol * fmaxf(xa0, xa1));
     float q1 = h * ey / (atol + rtol * fmaxf(fabsf(u.y), fabsf(ue.y)));
     float q2 = h * epx / (atol + rtol * fmaxf(fabsf(u.px), fabsf(ue.px)));
@@ -283,142 +236,10 @@ __device__ __forceinline__ bool st32_finite(const St32& u)
     return isfinite(u.fx) && isfinite(u.y) && isfinite(u.px) && isfinite(u.py);
 }
 
-// FP32 counterpart of integrate_box64.
-__device__ inline int integrate_box32(const SceneDev& s, const OptsDev& o, double r[3], double p[3],
-                                      LaneCount& cnt, double* min_cos)
+// err^(-1/5) through the hardware log2/exp2
+__device__ __forceinline__ float pow_m02(float err)
 {
-    const Sc32 c = make_sc32(s, o);
-    const float rtol = (float)o.rtol, atol = (float)o.atol;
-    double z = r[2];
-    const double pz = p[2];
-    St32 u;
-    Rhs32 r1;
-    {
-        St64 u64 = {r[0], r[1], p[0], p[1]};
-        Rhs64 r64;
-        r64.W = w0_cold(zarg64(s, u64.x, u64.y));
-        rhs64(s, u64.x, u64.y, r64.W, r64.ax, r64.ay, r64.dW);
-        u = demote(s, u64);
-        r1 = demote(r64);
-    }
-    float h = (float)((o.integ == 0) ? o.h : o.h0);
-    bool last_rej = false;
-    int fb = 0;
-    for (;;) {
-        if (cnt.steps >= o.max_steps) { cnt.fallbacks += fb; return RS_MAX_STEPS; }
-        St32 ue;
-        Rhs32 re;
-        float hnext = h;
-        if (o.integ == 0) {
-            rk4_step32(s, c, u, r1, h, ue, re, fb);
-        } else {
-            float err = dp5_step32(s, c, u, r1, h, rtol, atol, ue, re, fb);
-            if (!isfinite(err)) { cnt.fallbacks += fb; return RS_NONFINITE; }
-            if (err > 1.0f) {
-                h *= fmaxf(0.2f, 0.9f * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err)));
-                last_rej = true;
-                cnt.rejected++;
-                if (h < (float)o.h_min) { cnt.fallbacks += fb; return RS_UNDERFLOW; }
-                continue;
-            }
-            float fac = (err == 0.0f) ? 5.0f : 0.9f * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
-            fac = fminf(5.0f, fmaxf(0.2f, fac));
-            if (last_rej) fac = fminf(fac, 1.0f);
-            last_rej = false;
-            hnext = fminf(h * fac, (float)o.h_max);
-        }
-        cnt.steps++;
-        if (!st32_finite(ue)) { cnt.fallbacks += fb; return RS_NONFINITE; }
-        const double xe = (double)ue.cell * s.L + ((double)ue.fx + (double)ue.lx);
-        const double ye = (double)ue.y + (double)ue.ly;
-        bool ev = (ye > s.ytop) || (xe > s.hw) || (xe < -s.hw) ||
-                  (s.mirror == 0 && ue.y + re.W.re * c.invk < 0.0f);
-        if (!ev) {
-            u = ue;
-            r1 = re;
-            z += pz * (double)h;
-            h = hnext;
-            continue;
-        }
-        // redo the step in FP64 and locate the crossing there
-        St64 u64 = promote(s, u);
-        Rhs64 r64 = promote(s, u64, r1);
-        St64 ue64;
-        Rhs64 re64;
-        partial_step64(s, o, u64, r64, (double)h, ue64, re64);
-        bool ev64 = (ue64.y > s.ytop) || (ue64.x > s.hw) || (ue64.x < -s.hw) ||
-                    (s.mirror == 0 && ue64.y + re64.W.re / s.k < 0.0);
-        if (!ev64) {
-            u = demote(s, ue64);
-            r1 = demote(re64);
-            z += pz * (double)h;
-            h = hnext;
-            continue;
-        }
-        double dtau, pout[3];
-        bool out = handle_events64(s, o, u64, r64, pz, (double)h, ue64, re64, &dtau, pout, min_cos);
-        z += pz * dtau;
-        if (++cnt.events > o.max_events) { cnt.fallbacks += fb; return RS_MAX_EVENTS; }
-        if (out) {
-            r[0] = u64.x; r[1] = u64.y; r[2] = z;
-            p[0] = pout[0]; p[1] = pout[1]; p[2] = pout[2];
-            cnt.fallbacks += fb;
-            return RS_OK;
-        }
-        u = demote(s, u64);
-        r1 = demote(r64);
-        h = (o.integ == 0) ? (float)o.h : hnext;
-    }
-}
-
-// Ray path with the in-cloak part in FP32 (air segments and events FP64).
-__device__ inline int trace_ray32(const SceneDev& s, const OptsDev& o, const double org[3], const double dir[3],
-                                  double out_org[3], double out_dir[3], LaneCount& cnt, double* min_cos)
-{
-    double r[3] = {org[0], org[1], org[2]};
-    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-    double p[3] = {dir[0] / nd, dir[1] / nd, dir[2] / nd};
-    for (;;) {
-        if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(p[0]) && isfinite(p[1]) &&
-              isfinite(p[2])))
-            return RS_NONFINITE;
-        int face;
-        double tb = air_box_entry(s, r, p, &face);
-        double xi;
-        double tg = air_contact(s, r, p, &xi);
-        if (!(tb < kInf) && !(tg < kInf)) {
-            for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
-            return RS_OK;
-        }
-        if (++cnt.events > o.max_events) return RS_MAX_EVENTS;
-        if (tg <= tb) {
-            for (int i = 0; i < 3; ++i) r[i] += tg * p[i];
-            double nx = 0.0, ny = 1.0;
-            if (!(s.mirror == 1 || s.A == 0.0)) {
-                double sn, cs;
-                sincos(s.k * xi, &sn, &cs);
-                nx = s.e * sn;
-                ny = 1.0 - s.e * cs;
-                double inv = 1.0 / sqrt(nx * nx + ny * ny);
-                nx *= inv;
-                ny *= inv;
-            }
-            *min_cos = fmin(*min_cos, fabs(p[0] * nx + p[1] * ny));
-            reflect2(p[0], p[1], nx, ny);
-            continue;
-        }
-        for (int i = 0; i < 3; ++i) r[i] += tb * p[i];
-        double nf[3] = {0.0, 0.0, 0.0};
-        if (face == 0) { r[1] = s.ytop; nf[1] = -1.0; }
-        else if (face == 1) { r[0] = s.hw; nf[0] = -1.0; }
-        else { r[0] = -s.hw; nf[0] = 1.0; }
-        *min_cos = fmin(*min_cos, fabs(p[0] * nf[0] + p[1] * nf[1]));
-        cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
-        double n2 = 1.0 / sqrt(norm2(mk(1.0 + W.re, W.im)));
-        if (!snell(p, nf, n2)) continue;
-        int st = integrate_box32(s, o, r, p, cnt, min_cos);
-        if (st != RS_OK) return st;
-    }
+    return __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
 }
 
 }  // namespace gc

@@ -77,7 +77,7 @@ __device__ inline double line_G(const SceneDev& s, double xi, double x0, double 
 // Above the surface sign(G) = sign(d_x); the first piece (in the direction of
 // travel) over which sign(d_x) G drops from positive to non-positive holds
 // the contact, found by safeguarded Newton.
-__device__ inline double air_contact(const SceneDev& s, const double r[3], const double d[3], double* xi_hit)
+__device__ __noinline__ double air_contact(const SceneDev& s, const double r[3], const double d[3], double* xi_hit)
 {
     const double x0 = r[0], y0 = r[1], dx = d[0], dy = d[1];
     if (s.mirror == 1 || s.A == 0.0) {
@@ -234,7 +234,7 @@ __device__ inline void rhs_at(const SceneDev& s, double x, double y, double xp, 
                               Rhs64& out)
 {
     out.W = prev.W + prev.dW * mk(x - xp, y - yp);
-    rhs64(s, x, y, out.W, out.ax, out.ay, out.dW);
+    rhs64(s, x, y, out.W, out.ax, out.ay, out.dW, crosses_cut(s, x, y, xp, yp));
 }
 
 __device__ inline void rk4_step64(const SceneDev& s, const St64& u, const Rhs64& r1, double h, St64& ue,
@@ -258,22 +258,6 @@ __device__ inline void rk4_step64(const SceneDev& s, const St64& u, const Rhs64&
     ue.py = u.py + h6 * (r1.ay + 2.0 * r2.ay + 2.0 * r3.ay + r4.ay);
     rhs_at(s, ue.x, ue.y, x4, y4, r4, re);
 }
-
-// Dormand-Prince 5(4) tableau (Dormand & Prince 1980).
-struct DP {
-    static constexpr double a21 = 1.0 / 5;
-    static constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
-    static constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
-    static constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
-    static constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
-                            a65 = -5103.0 / 18656;
-    static constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192, b5 = -2187.0 / 6784,
-                            b6 = 11.0 / 84;
-    // 5th minus 4th order weights
-    static constexpr double e1 = 35.0 / 384 - 5179.0 / 57600, e3 = 500.0 / 1113 - 7571.0 / 16695,
-                            e4 = 125.0 / 192 - 393.0 / 640, e5 = -2187.0 / 6784 + 92097.0 / 339200,
-                            e6 = 11.0 / 84 - 187.0 / 2100, e7 = -1.0 / 40;
-};
 
 // One DOPRI5 step; returns the scaled RMS error over (x, y, px, py) and the
 // 5th order end state with its RHS (FSAL).
@@ -352,36 +336,82 @@ __device__ inline double event_fn(const SceneDev& s, int ev, const St64& u, cons
     }
 }
 
-// Smallest theta in (0, 1] at which event `ev` of the partial step crosses
-// zero, by the Illinois variant of regula falsi on a bracket that keeps
-// e >= 0 at lo and e < 0 at hi; returns hi once hi - lo <= 1e-14.
-__device__ inline double locate_event(const SceneDev& s, const OptsDev& o, int ev, const St64& u,
-                                      const Rhs64& r1, double h, double f0, double f1)
+// d/dtau of event function `ev` at state u with RHS r
+__device__ inline double event_rate(const SceneDev& s, int ev, const St64& u, const Rhs64& r)
 {
+    switch (ev) {
+    case 0: return -u.py;
+    case 1: return -u.px;
+    case 2: return u.px;
+    default: return u.py + (u.px * r.dW.re - u.py * r.dW.im) / s.k;   // v = y + Re W / k
+    }
+}
+
+// Root in (0, 1) of the cubic Hermite interpolant of an event function with
+// values f0 >= 0 > f1 and slopes m0, m1 (per unit theta): the first sign
+// change on an 8-point grid, refined by bisection + Newton on the cubic.
+__device__ inline double hermite_root(double f0, double f1, double m0, double m1, double* slope)
+{
+    auto P = [&](double t, double* dp) {
+        double t2 = t * t, t3 = t2 * t;
+        if (dp) *dp = (6 * t2 - 6 * t) * f0 + (3 * t2 - 4 * t + 1) * m0 + (-6 * t2 + 6 * t) * f1 + (3 * t2 - 2 * t) * m1;
+        return (2 * t3 - 3 * t2 + 1) * f0 + (t3 - 2 * t2 + t) * m0 + (-2 * t3 + 3 * t2) * f1 + (t3 - t2) * m1;
+    };
     double lo = 0.0, hi = 1.0;
-    double flo = fmax(f0, 0.0), fhi = f1;
-    int side = 0;
-    for (int it = 0; it < 100 && hi - lo > 1e-14; ++it) {
-        double th = 0.5 * (lo + hi);
-        if (it < 40 && flo != fhi) {
-            double t = (lo * fhi - hi * flo) / (fhi - flo);
-            if (t > lo && t < hi) th = t;
-        }
+    for (int i = 1; i <= 8; ++i) {
+        double t = i * 0.125;
+        if (P(t, nullptr) < 0.0) { hi = t; lo = t - 0.125; break; }
+    }
+    double t = 0.5 * (lo + hi);
+    for (int it = 0; it < 40; ++it) {
+        double dp;
+        double p = P(t, &dp);
+        if (p < 0.0) hi = t; else lo = t;
+        double tn = (dp != 0.0) ? t - p / dp : 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (fabs(tn - t) < 1e-15 || hi - lo < 1e-15) { t = tn; break; }
+        t = tn;
+    }
+    P(t, slope);
+    return t;
+}
+
+// Smallest theta in (0, 1] at which event `ev` of the partial step Phi(theta h)
+// crosses zero.  f0 / f1: event values at the step start / full-step end
+// (f1 < 0), rates d0 / d1 their tau-derivatives.  The first trial is the
+// root of the cubic Hermite interpolant; then a secant iteration safeguarded
+// by the bracket [lo, hi] (e >= 0 at lo, e < 0 at hi), which is closed to
+// 1e-14 by a last trial placed just across the converged root.  Returns hi.
+__device__ inline double locate_event(const SceneDev& s, const OptsDev& o, int ev, const St64& u,
+                                      const Rhs64& r1, double h, double f0, double f1, double d0, double d1,
+                                      const St64& u_end, const Rhs64& r_end, St64& u_hi, Rhs64& r_hi)
+{
+    u_hi = u_end;
+    r_hi = r_end;
+    double lo = 0.0, hi = 1.0;
+    double slope = 0.0;
+    double x = hermite_root(fmax(f0, 0.0), f1, h * d0, h * d1, &slope);
+    double fx = 0.0, xprev = -1.0, fprev = 0.0;
+    for (int it = 0; it < 60; ++it) {
         St64 ue;
         Rhs64 re;
-        partial_step64(s, o, u, r1, th * h, ue, re);
-        double f = event_fn(s, ev, ue, re);
-        if (f < 0.0) {
-            hi = th;
-            fhi = f;
-            if (side == -1) flo *= 0.5;
-            side = -1;
+        partial_step64(s, o, u, r1, x * h, ue, re);
+        fx = event_fn(s, ev, ue, re);
+        if (fx < 0.0) { hi = x; u_hi = ue; r_hi = re; } else lo = x;
+        if (hi - lo <= 1e-14) break;
+        double t;
+        if (xprev < 0.0) {
+            t = (slope != 0.0) ? x - fx / slope : 0.5 * (lo + hi);
+        } else if (fx != fprev) {
+            t = x - fx * (x - xprev) / (fx - fprev);
         } else {
-            lo = th;
-            flo = f;
-            if (side == +1) fhi *= 0.5;
-            side = +1;
+            t = 0.5 * (lo + hi);
         }
+        if (it >= 20 || !(t > lo && t < hi)) t = 0.5 * (lo + hi);
+        if (fabs(t - x) < 0.5e-14) t = (fx < 0.0) ? fmax(hi - 0.9e-14, 0.5 * (lo + hi)) : fmin(lo + 0.9e-14, 0.5 * (lo + hi));
+        xprev = x;
+        fprev = fx;
+        x = t;
     }
     return hi;
 }
@@ -397,17 +427,19 @@ __device__ inline bool handle_events64(const SceneDev& s, const OptsDev& o, St64
 {
     double best = 2.0;
     int hit = -1;
+    St64 uc = ue;
+    Rhs64 rc = re;
     for (int ev = 0; ev < 4; ++ev) {
         if (ev == 3 && s.mirror == 1) continue;
         double f1 = event_fn(s, ev, ue, re);
         if (!(f1 < 0.0)) continue;
         double f0 = event_fn(s, ev, u, r1);
-        double th = locate_event(s, o, ev, u, r1, h, f0, f1);
-        if (th < best) { best = th; hit = ev; }
+        St64 uh;
+        Rhs64 rh;
+        double th = locate_event(s, o, ev, u, r1, h, f0, f1, event_rate(s, ev, u, r1), event_rate(s, ev, ue, re),
+                                 ue, re, uh, rh);
+        if (th < best) { best = th; hit = ev; uc = uh; rc = rh; }
     }
-    St64 uc;
-    Rhs64 rc;
-    partial_step64(s, o, u, r1, best * h, uc, rc);
     *dtau = best * h;
     u = uc;
     r1 = rc;
@@ -438,88 +470,124 @@ __device__ inline bool handle_events64(const SceneDev& s, const OptsDev& o, St64
     return true;
 }
 
+// Outcome of one step inside the box.
+enum StepOutcome { SO_INSIDE = 0, SO_EXITED = 1, SO_FAIL = 2 };
+
+// In-box stepper state carried between steps.
+struct Box64 {
+    St64 u;
+    Rhs64 r1;
+    double z, pz, h;
+    bool last_rej;
+};
+
+// One accepted integrator step from b (FP64), with DOPRI5 step control, event
+// detection, location and handling.  On SO_EXITED r_out / p_out hold the
+// point where the ray left the box and its momentum in air.  On SO_FAIL
+// *status holds the reason.
+__device__ inline int box_step64(const SceneDev& s, const OptsDev& o, Box64& b, LaneCount& cnt,
+                                 double* min_cos, double r_out[3], double p_out[3], int* status)
+{
+    St64 ue;
+    Rhs64 re;
+    double h = b.h, hnext = b.h;
+    for (;;) {
+        if (o.integ == 0) {
+            rk4_step64(s, b.u, b.r1, h, ue, re);
+            break;
+        }
+        double err = dp5_step64(s, b.u, b.r1, h, o.rtol, o.atol, ue, re);
+        if (!isfinite(err)) { *status = RS_NONFINITE; return SO_FAIL; }
+        if (err > 1.0) {
+            h *= fmax(0.2, 0.9 * pow(err, -0.2));
+            b.last_rej = true;
+            cnt.rejected++;
+            if (h < o.h_min) { *status = RS_UNDERFLOW; return SO_FAIL; }
+            continue;
+        }
+        double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
+        fac = fmin(5.0, fmax(0.2, fac));
+        if (b.last_rej) fac = fmin(fac, 1.0);
+        b.last_rej = false;
+        hnext = fmin(h * fac, o.h_max);
+        break;
+    }
+    cnt.steps++;
+    if (!(isfinite(ue.x) && isfinite(ue.y) && isfinite(ue.px) && isfinite(ue.py))) {
+        *status = RS_NONFINITE;
+        return SO_FAIL;
+    }
+    bool ev = (ue.y > s.ytop) || (ue.x > s.hw) || (ue.x < -s.hw) ||
+              (s.mirror == 0 && ue.y + re.W.re / s.k < 0.0);
+    if (!ev) {
+        b.u = ue;
+        b.r1 = re;
+        b.z += b.pz * h;
+        b.h = hnext;
+        return SO_INSIDE;
+    }
+    double dtau, pout[3];
+    bool out = handle_events64(s, o, b.u, b.r1, b.pz, h, ue, re, &dtau, pout, min_cos);
+    b.z += b.pz * dtau;
+    b.h = (o.integ == 0) ? o.h : hnext;
+    if (++cnt.events > o.max_events) { *status = RS_MAX_EVENTS; return SO_FAIL; }
+    if (!out) return SO_INSIDE;
+    r_out[0] = b.u.x; r_out[1] = b.u.y; r_out[2] = b.z;
+    p_out[0] = pout[0]; p_out[1] = pout[1]; p_out[2] = pout[2];
+    return SO_EXITED;
+}
+
+// Stepper state on entry into the box at (r, p) (p already refracted).
+__device__ inline Box64 box_enter64(const SceneDev& s, const OptsDev& o, const double r[3], const double p[3])
+{
+    Box64 b;
+    b.u = {r[0], r[1], p[0], p[1]};
+    b.z = r[2];
+    b.pz = p[2];
+    b.r1.W = w0_cold(zarg64(s, b.u.x, b.u.y));
+    rhs64(s, b.u.x, b.u.y, b.r1.W, b.r1.ax, b.r1.ay, b.r1.dW);
+    b.h = (o.integ == 0) ? o.h : o.h0;
+    b.last_rej = false;
+    return b;
+}
+
 // Integrate inside the box from (r, p) just inside a face.  On RS_OK r, p
 // hold the exit point and the momentum in air.
 __device__ inline int integrate_box64(const SceneDev& s, const OptsDev& o, double r[3], double p[3],
                                       LaneCount& cnt, double* min_cos)
 {
-    St64 u = {r[0], r[1], p[0], p[1]};
-    double z = r[2];
-    const double pz = p[2];
-    Rhs64 r1;
-    r1.W = w0_cold(zarg64(s, u.x, u.y));
-    r1.dW = mk(0.0, 0.0);
-    rhs64(s, u.x, u.y, r1.W, r1.ax, r1.ay, r1.dW);
-    double h = (o.integ == 0) ? o.h : o.h0;
-    bool last_rej = false;
+    Box64 b = box_enter64(s, o, r, p);
     for (;;) {
         if (cnt.steps >= o.max_steps) return RS_MAX_STEPS;
-        St64 ue;
-        Rhs64 re;
-        double hnext = h;
-        if (o.integ == 0) {
-            rk4_step64(s, u, r1, h, ue, re);
-        } else {
-            double err = dp5_step64(s, u, r1, h, o.rtol, o.atol, ue, re);
-            if (!isfinite(err)) return RS_NONFINITE;
-            if (err > 1.0) {
-                h *= fmax(0.2, 0.9 * pow(err, -0.2));
-                last_rej = true;
-                cnt.rejected++;
-                if (h < o.h_min) return RS_UNDERFLOW;
-                continue;
-            }
-            double fac = (err == 0.0) ? 5.0 : 0.9 * pow(err, -0.2);
-            fac = fmin(5.0, fmax(0.2, fac));
-            if (last_rej) fac = fmin(fac, 1.0);
-            last_rej = false;
-            hnext = fmin(h * fac, o.h_max);
-        }
-        cnt.steps++;
-        if (!(isfinite(ue.x) && isfinite(ue.y) && isfinite(ue.px) && isfinite(ue.py))) return RS_NONFINITE;
-        bool ev = (ue.y > s.ytop) || (ue.x > s.hw) || (ue.x < -s.hw) ||
-                  (s.mirror == 0 && ue.y + re.W.re / s.k < 0.0);
-        if (!ev) {
-            u = ue;
-            r1 = re;
-            z += pz * h;
-            h = hnext;
-            continue;
-        }
-        double dtau, pout[3];
-        bool out = handle_events64(s, o, u, r1, pz, h, ue, re, &dtau, pout, min_cos);
-        z += pz * dtau;
-        if (++cnt.events > o.max_events) return RS_MAX_EVENTS;
-        h = (o.integ == 0) ? o.h : hnext;
-        if (out) {
-            r[0] = u.x; r[1] = u.y; r[2] = z;
-            p[0] = pout[0]; p[1] = pout[1]; p[2] = pout[2];
-            return RS_OK;
-        }
+        int st = RS_OK;
+        int so = box_step64(s, o, b, cnt, min_cos, r, p, &st);
+        if (so == SO_FAIL) return st;
+        if (so == SO_EXITED) return RS_OK;
     }
 }
 
-// Complete path of one ray in FP64.  Returns the status; the exit point and
-// the unit exit direction go to out_org / out_dir.
-__device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const double org[3], const double dir[3],
-                                  double out_org[3], double out_dir[3], LaneCount& cnt, double* min_cos)
+// Outcome of a walk through air.
+enum AirOutcome { AO_ESCAPED = 0, AO_ENTERED = 1, AO_FAIL = 2 };
+
+// Straight flight from (r, p) through air, reflecting off the bare grating,
+// until the ray escapes (p = unit exit direction) or enters the box (r on the
+// face, p refracted inside).  The acceleration of eq. (11) vanishes outside
+// the cloak.
+__device__ inline int air_walk(const SceneDev& s, const OptsDev& o, double r[3], double p[3], LaneCount& cnt,
+                               double* min_cos, int* status)
 {
-    double r[3] = {org[0], org[1], org[2]};
-    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-    double p[3] = {dir[0] / nd, dir[1] / nd, dir[2] / nd};
     for (;;) {
         if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(p[0]) && isfinite(p[1]) &&
-              isfinite(p[2])))
-            return RS_NONFINITE;
+              isfinite(p[2]))) {
+            *status = RS_NONFINITE;
+            return AO_FAIL;
+        }
         int face;
         double tb = air_box_entry(s, r, p, &face);
         double xi;
         double tg = air_contact(s, r, p, &xi);
-        if (!(tb < kInf) && !(tg < kInf)) {
-            for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
-            return RS_OK;
-        }
-        if (++cnt.events > o.max_events) return RS_MAX_EVENTS;
+        if (!(tb < kInf) && !(tg < kInf)) return AO_ESCAPED;
+        if (++cnt.events > o.max_events) { *status = RS_MAX_EVENTS; return AO_FAIL; }
         if (tg <= tb) {
             for (int i = 0; i < 3; ++i) r[i] += tg * p[i];
             double nx = 0.0, ny = 1.0;
@@ -545,7 +613,27 @@ __device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const dou
         cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
         double n2 = 1.0 / sqrt(norm2(mk(1.0 + W.re, W.im)));
         if (!snell(p, nf, n2)) continue;
-        int st = integrate_box64(s, o, r, p, cnt, min_cos);
+        return AO_ENTERED;
+    }
+}
+
+// Complete path of one ray in FP64.  Returns the status; the exit point and
+// the unit exit direction go to out_org / out_dir.
+__device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const double org[3], const double dir[3],
+                                  double out_org[3], double out_dir[3], LaneCount& cnt, double* min_cos)
+{
+    double r[3] = {org[0], org[1], org[2]};
+    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double p[3] = {dir[0] / nd, dir[1] / nd, dir[2] / nd};
+    for (;;) {
+        int st = RS_OK;
+        int ao = air_walk(s, o, r, p, cnt, min_cos, &st);
+        if (ao == AO_FAIL) return st;
+        if (ao == AO_ESCAPED) {
+            for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
+            return RS_OK;
+        }
+        st = integrate_box64(s, o, r, p, cnt, min_cos);
         if (st != RS_OK) return st;
     }
 }

@@ -5,12 +5,14 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gcloak.h"
 #include "gc_lane64.hpp"
-#include "gc_lane32.hpp"
+#include "gc_wave.hpp"
 
 using namespace gc;
 
@@ -132,69 +134,6 @@ __global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float
 }
 
 // ---------------------------------------------------------------------------
-// FP32 kernels (one pixel per lane; the in-cloak loop runs in FP32).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_trace_rays32(SceneDev s, OptsDev o, long long n, const double* org,
-                                                      const double* dir, double* out_org, double* out_dir,
-                                                      int* status, long long* steps, int* events,
-                                                      DevCounters* cnt)
-{
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long c_steps = 0, c_rej = 0, c_ev = 0, c_fail = 0, c_rays = 0, c_fb = 0;
-    if (i < n) {
-        double r[3] = {org[3 * i], org[3 * i + 1], org[3 * i + 2]};
-        double d[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
-        double oo[3] = {0, 0, 0}, od[3] = {0, 0, 0};
-        LaneCount lc = {0, 0, 0, 0};
-        double mc = 1.0;
-        int st = trace_ray32(s, o, r, d, oo, od, lc, &mc);
-        if (out_org) for (int a = 0; a < 3; ++a) out_org[3 * i + a] = oo[a];
-        for (int a = 0; a < 3; ++a) out_dir[3 * i + a] = od[a];
-        if (status) status[i] = st;
-        if (steps) steps[i] = lc.steps;
-        if (events) events[i] = lc.events;
-        c_rays = 1;
-        c_steps = lc.steps;
-        c_rej = lc.rejected;
-        c_ev = lc.events;
-        c_fb = lc.fallbacks;
-        c_fail = st != RS_OK;
-    }
-    add_counters(cnt, c_rays, c_steps, c_rej, c_ev, c_fb, c_fail);
-}
-
-__global__ void __launch_bounds__(256) k_render32(SceneDev s, CamDev cam, OptsDev o, float* rgb,
-                                                  DevCounters* cnt)
-{
-    long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long npx = (long long)cam.W * cam.H;
-    unsigned long long c_steps = 0, c_rej = 0, c_ev = 0, c_fail = 0, c_rays = 0, c_fb = 0;
-    if (pix < npx) {
-        int i = (int)(pix % cam.W), j = (int)(pix / cam.W);
-        float acc[3] = {0, 0, 0};
-        for (int smp = 0; smp < cam.spp; ++smp) {
-            double d[3], oo[3], od[3];
-            camera_dir(cam, i, j, smp, d);
-            LaneCount lc = {0, 0, 0, 0};
-            double mc = 1.0;
-            int st = trace_ray32(s, o, cam.eye, d, oo, od, lc, &mc);
-            c_rays++;
-            c_steps += lc.steps;
-            c_rej += lc.rejected;
-            c_ev += lc.events;
-            c_fb += lc.fallbacks;
-            if (st != RS_OK) { c_fail++; continue; }
-            float df[3] = {(float)od[0], (float)od[1], (float)od[2]};
-            float c[3];
-            sky_rgb<float>((float)s.K, df, c);
-            for (int a = 0; a < 3; ++a) acc[a] += c[a];
-        }
-        for (int a = 0; a < 3; ++a) rgb[3 * pix + a] = acc[a] / (float)cam.spp;
-    }
-    add_counters(cnt, c_rays, c_steps, c_rej, c_ev, c_fb, c_fail);
-}
-
-// ---------------------------------------------------------------------------
 // Cross-correlation, eqs. (14)-(15): one pass of FP64 moments per channel
 // (sum f, sum g, sum f^2, sum g^2, sum f g), then centred sums from them.
 // Partials: per block, 5 x nch doubles; a single block folds them.
@@ -288,11 +227,30 @@ __global__ void __launch_bounds__(256) k_cc_final(const double* __restrict__ par
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
+// Device buffers of the FP32 pipeline, grown on demand.
+struct WfStore {
+    long long cap_rays = 0;
+    int cap_scenes = 0;
+    void* rays = nullptr;       // one allocation for all per-ray arrays
+    int* queues = nullptr;      // 3 x cap_rays
+    void* tables = nullptr;     // scenes, cameras, offsets, image pointers
+    QCtr* ctr = nullptr;
+    WfTotals* tot = nullptr;
+    QCtr* h_ctr = nullptr;      // pinned host copy of the counters
+    int box_blocks[2] = {0, 0}; // persistent grid of k_wf_box<RK4>, <DOPRI5>
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // per call
+    long long fp64_steps = 0, rounds = 0, tail_rays = 0;
+    double hot_ms = 0.0, event_ms = 0.0, tail_ms = 0.0, total_ms = 0.0;
+};
+
 struct gc_ctx {
     int device;
+    int n_cu;
     DevCounters* d_cnt;
     double* d_part;
     double* d_ccout;
+    WfStore wf;
 };
 
 static thread_local std::string g_err;
@@ -434,6 +392,281 @@ static gc_status read_counters(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
     st->events = (int64_t)h.events;
     st->fallbacks = (int64_t)h.fallbacks;
     st->failed = (int64_t)h.failed;
+    st->fp64_steps = 0;
+    st->rounds = 0;
+    st->hot_ms = st->event_ms = st->total_ms = st->tail_ms = 0.0;
+    st->tail_rays = 0;
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 pipeline orchestration.
+// ---------------------------------------------------------------------------
+static size_t wf_ray_bytes(long long n) { return (size_t)n * (7 * 8 + 7 * 4 + 14 * 4 + 3 * 4 + 4); }
+
+static void wf_carve(void* base, long long n, WfRays& R)
+{
+    char* p = (char*)base;
+    auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) & ~(size_t)255; return r; };
+    double** d[] = {&R.rx, &R.ry, &R.rz, &R.qx, &R.qy, &R.qz, &R.z0};
+    for (double** q : d) *q = (double*)take(sizeof(double) * n);
+    int** ip[] = {&R.cell, &R.steps, &R.rej, &R.events, &R.flags, &R.scene, &R.status, &R.fbk};
+    for (int** q : ip) *q = (int*)take(sizeof(int) * n);
+    float** fp[] = {&R.fx, &R.lx, &R.y, &R.ly, &R.px, &R.lpx, &R.py, &R.lpy, &R.pz, &R.Wr, &R.Wi, &R.h, &R.tau,
+                    &R.ltau};
+    for (float** q : fp) *q = (float*)take(sizeof(float) * n);
+    R.rgb = (float*)take(sizeof(float) * 3 * n);
+}
+
+static size_t wf_table_bytes(int ns)
+{
+    return (size_t)ns * (sizeof(SceneDev) + sizeof(CamDev) + sizeof(float*)) + (size_t)(ns + 1) * 2 * sizeof(long long) +
+           1024;
+}
+
+static gc_status wf_reserve(gc_ctx* ctx, long long n_rays, int n_scenes)
+{
+    WfStore& w = ctx->wf;
+    if (!w.ctr) {
+        if (hipMalloc(&w.ctr, sizeof(QCtr)) != hipSuccess || hipMalloc(&w.tot, sizeof(WfTotals)) != hipSuccess ||
+            hipHostMalloc(&w.h_ctr, sizeof(QCtr)) != hipSuccess)
+            return fail(GC_ENOMEM, "pipeline counters: allocation failed");
+        int nb = 0;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wf_box<0>, 256, 0));
+        w.box_blocks[0] = (nb > 0 ? nb : 1) * ctx->n_cu;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_wf_box<1>, 256, 0));
+        w.box_blocks[1] = (nb > 0 ? nb : 1) * ctx->n_cu;
+        for (hipEvent_t& e : w.ev) HIP_OK(hipEventCreate(&e));
+    }
+    if (n_rays > w.cap_rays) {
+        if (w.rays) (void)hipFree(w.rays);
+        if (w.queues) (void)hipFree(w.queues);
+        w.rays = nullptr;
+        w.queues = nullptr;
+        w.cap_rays = 0;
+        long long cap = n_rays + n_rays / 8;
+        if (hipMalloc(&w.rays, wf_ray_bytes(cap) + 64 * 256) != hipSuccess ||
+            hipMalloc((void**)&w.queues, sizeof(int) * 4 * (size_t)cap) != hipSuccess)
+            return fail(GC_ENOMEM, "pipeline ray buffers (%lld rays): allocation failed", cap);
+        w.cap_rays = cap;
+    }
+    if (n_scenes > w.cap_scenes) {
+        if (w.tables) (void)hipFree(w.tables);
+        w.tables = nullptr;
+        w.cap_scenes = 0;
+        if (hipMalloc(&w.tables, wf_table_bytes(n_scenes)) != hipSuccess)
+            return fail(GC_ENOMEM, "pipeline scene tables: allocation failed");
+        w.cap_scenes = n_scenes;
+    }
+    return GC_OK;
+}
+
+struct WfTables {
+    SceneDev* scenes;
+    CamDev* cams;
+    long long* ray_off;
+    long long* pix_off;
+    float** images;
+};
+
+static WfTables wf_tables(void* base, int ns)
+{
+    WfTables t;
+    char* p = (char*)base;
+    t.scenes = (SceneDev*)p;
+    p += sizeof(SceneDev) * ns;
+    t.cams = (CamDev*)p;
+    p += sizeof(CamDev) * ns;
+    p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    t.ray_off = (long long*)p;
+    p += sizeof(long long) * (ns + 1);
+    t.pix_off = (long long*)p;
+    p += sizeof(long long) * (ns + 1);
+    t.images = (float**)p;
+    return t;
+}
+
+// Run the pipeline for a filled WfArgs (tables already on the device).
+static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
+{
+    WfStore& w = ctx->wf;
+    const int integ = a.o.integ;
+    const unsigned init_blocks = (unsigned)((a.n_rays + 255) / 256);
+    w.fp64_steps = 0;
+    w.rounds = 0;
+    w.tail_rays = 0;
+    w.hot_ms = w.event_ms = w.tail_ms = 0.0;
+    HIP_OK(hipEventRecord(w.ev[0], stream));
+    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, 1);
+    hipLaunchKernelGGL(k_wf_init, dim3(init_blocks), dim3(256), 0, stream, a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    unsigned len = w.h_ctr->box_len[0];
+    const unsigned tail_max = 128u * (unsigned)ctx->n_cu;
+    for (int round = 0; len > 0; ++round) {
+        const int cur = round & 1;
+        if (len <= tail_max) {
+            // finish the remaining rays without round barriers
+            const int n_simd = 4 * ctx->n_cu;
+            int lanes = (int)std::min<unsigned>(64u, std::max<unsigned>(1u, (len + 2 * n_simd - 1) / (2 * n_simd)));
+            unsigned blocks = (len + lanes - 1) / lanes;
+            HIP_OK(hipEventRecord(w.ev[1], stream));
+            if (integ == 0)
+                hipLaunchKernelGGL(k_wf_tail<0>, dim3(blocks), dim3(64), 0, stream, a, cur, lanes);
+            else
+                hipLaunchKernelGGL(k_wf_tail<1>, dim3(blocks), dim3(64), 0, stream, a, cur, lanes);
+            HIP_OK(hipEventRecord(w.ev[2], stream));
+            HIP_OK(hipGetLastError());
+            HIP_OK(hipStreamSynchronize(stream));
+            float t1 = 0.f;
+            HIP_OK(hipEventElapsedTime(&t1, w.ev[1], w.ev[2]));
+            w.tail_ms += t1;
+            w.tail_rays = len;
+            w.rounds = round + 1;
+            break;
+        }
+        // grids sized by the rays in flight: every ray flags at most one
+        // event per round and every event yields at most one ray in air
+        const unsigned need = (len + 255) / 256;
+        const unsigned box_g = std::min<unsigned>(need, (unsigned)w.box_blocks[integ]);
+        const unsigned ev_g = std::min<unsigned>(need, (unsigned)(8 * ctx->n_cu));
+        hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
+        HIP_OK(hipEventRecord(w.ev[1], stream));
+        if (integ == 0)
+            hipLaunchKernelGGL(k_wf_box<0>, dim3(box_g), dim3(256), 0, stream, a, cur);
+        else
+            hipLaunchKernelGGL(k_wf_box<1>, dim3(box_g), dim3(256), 0, stream, a, cur);
+        HIP_OK(hipEventRecord(w.ev[2], stream));
+        if (integ == 0)
+            hipLaunchKernelGGL(k_wf_event<0>, dim3(ev_g), dim3(256), 0, stream, a, cur);
+        else
+            hipLaunchKernelGGL(k_wf_event<1>, dim3(ev_g), dim3(256), 0, stream, a, cur);
+        hipLaunchKernelGGL(k_wf_air, dim3(ev_g), dim3(256), 0, stream, a, cur);
+        HIP_OK(hipEventRecord(w.ev[3], stream));
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        float t1 = 0.f, t2 = 0.f;
+        HIP_OK(hipEventElapsedTime(&t1, w.ev[1], w.ev[2]));
+        HIP_OK(hipEventElapsedTime(&t2, w.ev[2], w.ev[3]));
+        w.hot_ms += t1;
+        w.event_ms += t2;
+        w.fp64_steps += w.h_ctr->ev_len;
+        w.rounds = round + 1;
+        len = w.h_ctr->box_len[cur ^ 1];
+        if (round > 1000000) return fail(GC_EDEVICE, "pipeline did not drain");
+    }
+    return GC_OK;
+}
+
+static WfArgs wf_args(gc_ctx* ctx, const OptsDev& o, int ns, long long n_rays)
+{
+    WfStore& w = ctx->wf;
+    WfArgs a;
+    std::memset(&a, 0, sizeof a);
+    wf_carve(w.rays, w.cap_rays, a.R);
+    a.qbox[0] = w.queues;
+    a.qbox[1] = w.queues + w.cap_rays;
+    a.qev = w.queues + 2 * w.cap_rays;
+    a.qair = w.queues + 3 * w.cap_rays;
+    a.ctr = w.ctr;
+    WfTables t = wf_tables(w.tables, ns);
+    a.scenes = t.scenes;
+    a.cams = t.cams;
+    a.ray_off = t.ray_off;
+    a.n_scenes = ns;
+    a.n_rays = n_rays;
+    a.o = o;
+    return a;
+}
+
+static gc_status wf_read_totals(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
+{
+    WfTotals h;
+    HIP_OK(hipEventRecord(ctx->wf.ev[4], stream));
+    HIP_OK(hipMemcpyAsync(&h, ctx->wf.tot, sizeof h, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    float tt = 0.f;
+    HIP_OK(hipEventElapsedTime(&tt, ctx->wf.ev[0], ctx->wf.ev[4]));
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->rays = (int64_t)h.rays;
+        st->accepted_steps = (int64_t)h.steps;
+        st->rejected_steps = (int64_t)h.rejected;
+        st->events = (int64_t)h.events;
+        st->fallbacks = (int64_t)h.fallbacks;
+        st->failed = (int64_t)h.failed;
+        st->fp64_steps = ctx->wf.fp64_steps;
+        st->rounds = ctx->wf.rounds;
+        st->hot_ms = ctx->wf.hot_ms;
+        st->event_ms = ctx->wf.event_ms;
+        st->tail_ms = ctx->wf.tail_ms;
+        st->tail_rays = ctx->wf.tail_rays;
+        st->total_ms = tt;
+    }
+    return GC_OK;
+}
+
+// Render n scenes with the FP32 pipeline into the given device images.
+static gc_status wf_render(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
+                           float* const* d_rgb, gc_stats* st, hipStream_t stream)
+{
+    std::vector<long long> roff(ns + 1), poff(ns + 1);
+    roff[0] = poff[0] = 0;
+    for (int i = 0; i < ns; ++i) {
+        long long npx = (long long)cams[i].W * cams[i].H;
+        poff[i + 1] = poff[i] + npx;
+        roff[i + 1] = roff[i] + npx * cams[i].spp;
+    }
+    const long long n_rays = roff[ns], n_pix = poff[ns];
+    if (n_rays > (1ll << 31) - 1) return fail(GC_EINVAL, "more than 2^31 - 1 samples in one launch");
+    gc_status r = wf_reserve(ctx, n_rays, ns);
+    if (r != GC_OK) return r;
+    // tables: staged in host memory, copied in one go
+    const size_t tb = wf_table_bytes(ns);
+    std::vector<char> host(tb, 0);
+    WfTables th = wf_tables(host.data(), ns);
+    for (int i = 0; i < ns; ++i) {
+        th.scenes[i] = sc[i];
+        th.cams[i] = cams[i];
+        th.images[i] = d_rgb[i];
+    }
+    for (int i = 0; i <= ns; ++i) { th.ray_off[i] = roff[i]; th.pix_off[i] = poff[i]; }
+    HIP_OK(hipMemcpyAsync(ctx->wf.tables, host.data(), tb, hipMemcpyHostToDevice, stream));
+    WfArgs a = wf_args(ctx, o, ns, n_rays);
+    r = wf_run(ctx, a, stream);
+    if (r != GC_OK) return r;
+    WfTables td = wf_tables(ctx->wf.tables, ns);
+    HIP_OK(hipMemsetAsync(ctx->wf.tot, 0, sizeof(WfTotals), stream));
+    hipLaunchKernelGGL(k_wf_finish, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, stream, a,
+                       (float* const*)td.images, (const long long*)td.pix_off, n_pix, ctx->wf.tot);
+    HIP_OK(hipGetLastError());
+    return wf_read_totals(ctx, st, stream);
+}
+
+static gc_status wf_trace(gc_ctx* ctx, const SceneDev& s, const OptsDev& o, long long n, const double* org,
+                          const double* dir, double* out_org, double* out_dir, int* status, long long* steps,
+                          int* events, hipStream_t stream)
+{
+    gc_status r = wf_reserve(ctx, n, 1);
+    if (r != GC_OK) return r;
+    std::vector<char> host(wf_table_bytes(1), 0);
+    WfTables th = wf_tables(host.data(), 1);
+    th.scenes[0] = s;
+    th.ray_off[0] = 0;
+    th.ray_off[1] = n;
+    HIP_OK(hipMemcpyAsync(ctx->wf.tables, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+    WfArgs a = wf_args(ctx, o, 1, n);
+    a.in_org = org;
+    a.in_dir = dir;
+    r = wf_run(ctx, a, stream);
+    if (r != GC_OK) return r;
+    HIP_OK(hipMemsetAsync(ctx->wf.tot, 0, sizeof(WfTotals), stream));
+    hipLaunchKernelGGL(k_wf_trace_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a, out_org,
+                       out_dir, status, steps, events, ctx->wf.tot);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(stream));
     return GC_OK;
 }
 
@@ -469,6 +702,11 @@ gc_status gc_create(gc_ctx** out, int hip_device)
     gc_ctx* c = new (std::nothrow) gc_ctx();
     if (!c) return fail(GC_ENOMEM, "host allocation failed");
     c->device = hip_device;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return fail(GC_EDEVICE, "hipGetDeviceProperties failed"); }
+        c->n_cu = prop.multiProcessorCount;
+    }
     if (hipMalloc(&c->d_cnt, sizeof(DevCounters)) != hipSuccess ||
         hipMalloc(&c->d_part, sizeof(double) * kCCBlocks * 5 * kCCMaxCh) != hipSuccess ||
         hipMalloc(&c->d_ccout, sizeof(double) * 4) != hipSuccess) {
@@ -486,6 +724,12 @@ void gc_destroy(gc_ctx* c)
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_ccout) (void)hipFree(c->d_ccout);
+    if (c->wf.rays) (void)hipFree(c->wf.rays);
+    if (c->wf.queues) (void)hipFree(c->wf.queues);
+    if (c->wf.tables) (void)hipFree(c->wf.tables);
+    if (c->wf.ctr) (void)hipFree(c->wf.ctr);
+    if (c->wf.tot) (void)hipFree(c->wf.tot);
+    if (c->wf.h_ctr) (void)hipHostFree(c->wf.h_ctr);
     delete c;
 }
 
@@ -510,9 +754,8 @@ gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts,
                            d_dir, d_out_org, d_out_dir, (int*)d_status, (long long*)d_steps, (int*)d_events,
                            ctx->d_cnt);
     else
-        hipLaunchKernelGGL(k_trace_rays32, dim3((unsigned)nb), dim3(256), 0, stream, s, o, (long long)n, d_org,
-                           d_dir, d_out_org, d_out_dir, (int*)d_status, (long long*)d_steps, (int*)d_events,
-                           ctx->d_cnt);
+        return wf_trace(ctx, s, o, (long long)n, d_org, d_dir, d_out_org, d_out_dir, (int*)d_status,
+                        (long long*)d_steps, (int*)d_events, stream);
     HIP_OK(hipGetLastError());
     return GC_OK;
 }
@@ -538,9 +781,42 @@ gc_status gc_render(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera,
     else if (opts->prec == GC_F64)
         hipLaunchKernelGGL(k_render64, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
     else
-        hipLaunchKernelGGL(k_render32, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
+        return wf_render(ctx, 1, &s, &c, o, &d_rgb, stats, stream);
     HIP_OK(hipGetLastError());
     if (stats) return read_counters(ctx, stats, stream);
+    return GC_OK;
+}
+
+gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                          const gc_opts* opts, float* const* d_rgb, const float* const* d_ref, double* C0,
+                          gc_stats* st, hipStream_t stream)
+{
+    if (!ctx) return fail(GC_EINVAL, "ctx is null");
+    if (n_scenes < 1 || !scenes || !cameras || !d_rgb) return fail(GC_EINVAL, "need n_scenes >= 1 and non-null arrays");
+    if (d_ref && !C0) return fail(GC_EINVAL, "C0 must be non-null when d_ref is given");
+    OptsDev o;
+    gc_status r;
+    if ((r = make_opts(opts, &o)) != GC_OK) return r;
+    if (opts->prec != GC_F32) return fail(GC_EUNSUPPORTED, "gc_render_batch runs the FP32 pipeline (prec = GC_F32)");
+    std::vector<SceneDev> sd(n_scenes);
+    std::vector<CamDev> cd(n_scenes);
+    for (int i = 0; i < n_scenes; ++i) {
+        if ((r = make_scene(&scenes[i], &sd[i])) != GC_OK) return fail(r, "scene %d: %s", i, g_err.c_str());
+        if (scenes[i].mirror == 1) return fail(GC_EUNSUPPORTED, "scene %d: flat-mirror scenes are rendered by gc_render", i);
+        if ((r = make_camera(&cameras[i], &cd[i])) != GC_OK) return fail(r, "camera %d: %s", i, g_err.c_str());
+        if (!d_rgb[i]) return fail(GC_EINVAL, "image pointer %d is null", i);
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    gc_stats tmp;
+    r = wf_render(ctx, n_scenes, sd.data(), cd.data(), o, d_rgb, st ? st : &tmp, stream);
+    if (r != GC_OK) return r;
+    if (d_ref) {
+        for (int i = 0; i < n_scenes; ++i) {
+            long long npix = (long long)cd[i].W * cd[i].H;
+            r = gc_cross_correlate(ctx, d_rgb[i], d_ref[i], npix, 3, &C0[i], nullptr, stream);
+            if (r != GC_OK) return r;
+        }
+    }
     return GC_OK;
 }
 

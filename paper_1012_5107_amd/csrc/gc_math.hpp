@@ -87,8 +87,8 @@ __device__ __forceinline__ void cis_rev(float r, float& c, float& s)
 __device__ __forceinline__ void cis_rev(double r, double& c, double& s) { sincospi(2.0 * r, &s, &c); }
 
 // ---------------------------------------------------------------------------
-// Lambert W0 from scratch (FP64): entry points, stage points below the
-// branch-point height, and recovery.  Halley iteration on f = W - z e^{-W}
+// Lambert W0 from scratch (FP64): entry points, evaluation paths that cross
+// the branch cut, and recovery.  Halley iteration on f = W - z e^{-W}
 // from the textbook starts (Corless et al., Adv. Comput. Math. 5 (1996)):
 // Taylor series near 0, the branch-point series near -1/e, log(1 + z) and
 // the asymptotic log z - log log z.  The first start whose limit has a small
@@ -143,7 +143,7 @@ __device__ inline bool w0_refine(cx<double> z, cx<double>& w)
            norm2(res) <= 1e-28 * fmax(norm2(z), 1e-300) && w0_principal(w);
 }
 
-__device__ inline cx<double> w0_cold(cx<double> z)
+__device__ __noinline__ cx<double> w0_cold(cx<double> z)
 {
     double az2 = norm2(z);
     if (az2 == 0.0) return z;
@@ -225,21 +225,16 @@ __device__ __forceinline__ void accel_from_w(const SceneDev& s, cx<T> W, T& ax, 
 }
 
 // FP64 right-hand side with warm start: iterate Halley to convergence.
-// Below the branch-point height, within a tenth of a period of a crest line
-// x = N Lambda, Z lies next to its branch cut and the warm start could cross
-// it: there W0 is taken from scratch.
-__device__ __forceinline__ bool near_cut(double fx, double y, double ybp, double L)
-{
-    return y < ybp && fabs(fx) < 0.1 * L;
-}
-
+// FP64 right-hand side with a warm start: W holds the prediction on entry;
+// Halley steps until the update is at rounding level.  `cold` asks for W0
+// from scratch instead (the evaluation path crossed the branch cut).
 __device__ inline void rhs64(const SceneDev& s, double x, double y, cx<double>& W,
-                             double& ax, double& ay, cx<double>& dW)
+                             double& ax, double& ay, cx<double>& dW, bool cold = false)
 {
-    double fx = x - s.L * rint(x * s.invL);
-    if (near_cut(fx, y, s.ybp, s.L)) {
+    if (cold) {
         W = w0_cold(zarg64(s, x, y));
     } else {
+        double fx = x - s.L * rint(x * s.invL);
         for (int it = 0; it < 8; ++it) {
             cx<double> w0 = W;
             halley_step<double>(s, fx, y, W);
@@ -251,6 +246,31 @@ __device__ inline void rhs64(const SceneDev& s, double x, double y, cx<double>& 
     double d2;
     accel_from_w<double>(s, W, ax, ay, dW, d2);
 }
+
+// Z = -A k e^{-ky} e^{ikx} lies on the branch cut (-inf, -1/e] exactly on the
+// crest lines x = N Lambda below the branch-point height y_bp = (1 + ln A k)/k.
+// A warm start carried from (xp, yp) to (x, y) can only change branch if the
+// segment between them crosses such a line below y_bp.
+__device__ __forceinline__ bool crosses_cut(const SceneDev& s, double x, double y, double xp, double yp)
+{
+    return fmin(y, yp) < s.ybp && floor(x * s.invL) != floor(xp * s.invL);
+}
+
+// Dormand-Prince 5(4) tableau (Dormand & Prince, J. Comput. Appl. Math. 6
+// (1980) 19-26): 5th-order weights b, and e = b - b* (5th minus 4th order).
+struct DP {
+    static constexpr double a21 = 1.0 / 5;
+    static constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+    static constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+    static constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
+    static constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
+                            a65 = -5103.0 / 18656;
+    static constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192, b5 = -2187.0 / 6784,
+                            b6 = 11.0 / 84;
+    static constexpr double e1 = 35.0 / 384 - 5179.0 / 57600, e3 = 500.0 / 1113 - 7571.0 / 16695,
+                            e4 = 125.0 / 192 - 393.0 / 640, e5 = -2187.0 / 6784 + 92097.0 / 339200,
+                            e6 = 11.0 / 84 - 187.0 / 2100, e7 = -1.0 / 40;
+};
 
 // ---------------------------------------------------------------------------
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output number n of the

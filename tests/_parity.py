@@ -36,7 +36,7 @@ def conditioning(O, sc, op, org, d, idx, delta):
     return kappa
 
 
-def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, tol, delta, name):
+def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, tol, delta, name, max_factor=50):
     """Compare exit directions with the oracle's.
 
     FP64 (delta = 1e-15): every ray must agree within `tol`, or -- for rays
@@ -49,7 +49,9 @@ def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, to
     rays whose oracle exit moves by more than `tol` under such a perturbation
     cannot be reproduced in FP32 and are counted, not compared (at most 3%);
     at most 1% may change their event sequence; the other rays must have
-    their 99th percentile within `tol` and their maximum within 30 `tol`.
+    their 99th percentile within `tol` and their maximum within max_factor
+    `tol` (adaptive step control turns FP32 rounding into different step
+    sequences, whose truncation errors differ by up to the tolerance).
     Returns (errors, excluded mask, ill-conditioned mask)."""
     err = angle(gpu_dir, orc["dir"])
     mask = exclusion_mask(orc, gpu_status, gpu_events)
@@ -72,5 +74,5 @@ def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, to
         assert mask.sum() <= max(1, 0.01 * err.size), "too many excluded rays"
         assert ill.sum() <= max(2, 0.03 * err.size), "too many ill-conditioned rays"
         assert np.quantile(err[good], 0.99) <= tol
-        assert np.max(err[good]) <= 30 * tol
+        assert np.max(err[good]) <= max_factor * tol
     return err, mask, ill

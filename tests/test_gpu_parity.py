@@ -66,8 +66,8 @@ def test_trace_fp64_dopri5_matches_oracle(B):
     check_directions(O, sc, op64, org, d, orc, od, st, ev, 1e-10, 1e-15, "fp64 dopri5 48x48")
 
 
-@pytest.mark.parametrize("rtol32", [1e-5, 1e-7])
-def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32):
+@pytest.mark.parametrize("rtol32,max_factor", [(1e-5, 100), (1e-7, 50)])
+def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32, max_factor):
     # the oracle integrates with the same tolerance, so that the comparison
     # measures the FP32 arithmetic, not the step control; the error against a
     # converged reference is reported by the benchmark
@@ -77,7 +77,8 @@ def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32):
     org, d = _camera_rays(cam)
     orc = O.trace_rays(sc, op, org, d)
     oo, od, st, steps, ev = _gpu_trace(B, sc, op, org, d, "f32")
-    check_directions(O, sc, op, org, d, orc, od, st, ev, 1e-4, 1e-6, f"fp32 dopri5({rtol32}) vs oracle 48x48")
+    check_directions(O, sc, op, org, d, orc, od, st, ev, 1e-4, 1e-6, f"fp32 dopri5({rtol32}) vs oracle 48x48",
+                     max_factor=max_factor)
 
 
 @pytest.mark.parametrize("prec,tol_px", [("f64", 1e-6), ("f32", 5e-3)])
@@ -117,7 +118,12 @@ def test_cross_correlate_kernel_exact_moments(B):
         assert abs(c - c_ref) < 1e-10 and abs(n - n_ref) < 1e-10, (shape, c, c_ref)
     f = rng.uniform(0, 1, (20, 20, 3)).astype(np.float32)
     assert abs(B.cross_correlate(torch.from_numpy(f), torch.from_numpy(f))[0] - 1) < 1e-12
-    assert abs(B.cross_correlate(torch.from_numpy(1 - f), torch.from_numpy(f))[0] + 1) < 1e-12
+    # 1 - f rounded to float32 is the complement up to rounding: compare with
+    # the oracle on the same float32 data, and with -1 to float32 accuracy
+    g = (1 - f).astype(np.float32)
+    c_gpu = B.cross_correlate(torch.from_numpy(g), torch.from_numpy(f))[0]
+    assert abs(c_gpu - O.cross_correlate(f, g)[0]) < 1e-12
+    assert abs(c_gpu + 1) < 1e-6
 
 
 def test_edge_cases_and_errors(B):
@@ -167,3 +173,42 @@ def test_zero_amplitude_renders_reference(B):
         assert torch.max(torch.abs(g - f)).item() < 1e-5
         c0, _ = B.cross_correlate(g, f)
         assert abs(c0 - 1) < 1e-5
+
+
+def _small_batch(n=4, res=24, spp=2):
+    scenes, cams = W.batch_64()
+    out_c = []
+    for c in cams[:n]:
+        out_c.append(dict(c, width=res, height=res, spp=spp))
+    return scenes[:n], out_c
+
+
+def test_render_batch_equals_single_renders_and_oracle(B):
+    scenes, cams = _small_batch()
+    op = W.opts("dopri5", rtol=1e-7)
+    refs = [B.render(W.reference_scene(s), c, op, prec="f32")[0] for s, c in zip(scenes, cams)]
+    imgs, c0, st = B.context(0).render_batch(scenes, cams, op, refs=refs)
+    assert st["rays"] == sum(c["width"] * c["height"] * c["spp"] for c in cams)
+    for i, (s, c) in enumerate(zip(scenes, cams)):
+        single, _ = B.render(s, c, op, prec="f32")
+        # every sample is traced by the same per-ray code, whatever shares the launch
+        assert torch.equal(single, imgs[i])
+        g_orc, _ = O.render(s, c, op)
+        f_orc, _ = O.render(W.reference_scene(s), c, op)
+        c_orc = O.cross_correlate(f_orc, g_orc)[0]
+        print(f"[batch scene {i}] A={s['A']:.3f} hw={s['half_width']:.2f} C0 gpu={c0[i]:.6f} oracle={c_orc:.6f}",
+              flush=True)
+        assert abs(c0[i] - c_orc) <= 1e-3
+        dpx = np.abs(imgs[i].cpu().numpy() - g_orc).max(axis=-1)
+        assert np.quantile(dpx, 0.95) <= 5e-3
+
+
+def test_render_batch_errors(B):
+    scenes, cams = _small_batch(2)
+    op = W.opts("dopri5", rtol=1e-7)
+    with pytest.raises(B.GcError) as e:
+        B.context(0).render_batch([W.reference_scene(scenes[0]), scenes[1]], cams, op)
+    assert e.value.status == B.GC_EUNSUPPORTED
+    with pytest.raises(B.GcError) as e:
+        B.context(0).render_batch([dict(scenes[0], A=0.5), scenes[1]], cams, op)
+    assert e.value.status == B.GC_EDOMAIN
