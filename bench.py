@@ -1,11 +1,18 @@
-"""Benchmark: ray-steps/s and rays/s of the FP32 and FP64 GPU paths on the
-512 x 512, 4 spp DOPRI5 workload, at CC error <= 1e-4.
+"""Benchmark: ray-steps/s and rays/s of the FP32 and FP64 GPU paths, at CC
+error <= 1e-4.
 
-One step = render the cloaked image (FP32 path), render the flat-mirror
-reference and correlate them (eqs. (14)-(15)).  Inputs are synthetic and
+Workloads (--workload):
+  single  512 x 512, 4 jittered spp, A = 0.1, cloak |x| <= 4, DOPRI5 (default)
+  batch   64 scenes of uneven resolution (256^2 .. 1024^2), amplitude, cloak
+          width and viewpoint, 4 spp, rendered in one FP32 pipeline launch
+  stress  1024 x 1024, 8 spp, A = 0.15 (A k = 0.94), grazing camera
+
+One step = render the cloaked image(s) (FP32 path), render the flat-mirror
+reference(s) and correlate them (eqs. (14)-(15)).  Inputs are synthetic and
 resident on the GPU before the timed region.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
+                    [--no-cpu] [--no-fp64]
 """
 import argparse
 import json
@@ -34,6 +41,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--workload", choices=["single", "batch", "stress"], default="single")
     return p.parse_args()
 
 
@@ -42,6 +50,10 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this path has no multi-GPU mode (pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return main_batch(args)
+    if args.workload == "stress":
+        return main_stress(args)
     import numpy as np
     import torch
     from paper_1012_5107_amd import binding as B
@@ -94,7 +106,7 @@ def main():
     # stream, and its work is the steps it took (the rest were taken by the
     # FP64 event kernel)
     _, stk = ctx.render(sc, cam, op32, prec="f32", out=img)
-    hot_steps = stk["accepted_steps"] - stk["fp64_steps"]
+    hot_steps = stk["hot_steps"]
     k_ms = stk["hot_ms"]
     achieved = hot_steps * FLOP_PER_STEP[op32["integrator"]] / (k_ms * 1e-3)
 
@@ -171,6 +183,123 @@ def main():
                                "sample": f"{npix} seeded pixels x 4 spp of the same workload (FP64 DOPRI5 rtol 1e-8), "
                                          f"{cnt['rays']} rays, {cnt['steps']} ray-steps in {tc:.1f} s",
                                "rays_per_s": cnt["rays"] / tc}
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_baseline(O, sc, cam, op, W, seconds, label):
+    H, Wd = cam["height"], cam["width"]
+    npix = 64
+    while True:
+        pix = W.sample_pixels(Wd, H, npix, seed=11)
+        t2 = time.perf_counter()
+        _, cnt = O.render(sc, cam, op, pixels=pix)
+        tc = time.perf_counter() - t2
+        if tc > seconds / 4 or npix >= Wd * H:
+            break
+        npix = min(Wd * H, int(npix * max(2.0, min(8.0, seconds / max(tc, 1e-3)))))
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count()
+    return {"value": cnt["steps"] / tc, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{npix} seeded pixels x {cam['spp']} spp of {label}, {cnt['rays']} rays, "
+                      f"{cnt['steps']} ray-steps in {tc:.1f} s", "rays_per_s": cnt["rays"] / tc}
+
+
+def main_batch(args):
+    import numpy as np
+    import torch
+    from paper_1012_5107_amd import binding as B
+    from paper_1012_5107_amd import workloads as W
+
+    scenes, cams = W.batch_64()
+    op32 = W.opts("dopri5", rtol=args.rtol32)
+    op64 = W.opts("dopri5", rtol=1e-8)
+    ctx = B.context(0)
+    dev = torch.device("cuda", 0)
+    imgs = [torch.empty((c["height"], c["width"], 3), dtype=torch.float32, device=dev) for c in cams]
+    refs = [ctx.render(W.reference_scene(s), c, op32, prec="f32")[0] for s, c in zip(scenes, cams)]
+    _, c0, st = ctx.render_batch(scenes, cams, op32, refs=refs, outs=imgs)
+    print(f"# batch pass: {st}", file=sys.stderr, flush=True)
+
+    def step():
+        for s, c, r in zip(scenes, cams, refs):
+            ctx.render(W.reference_scene(s), c, op32, prec="f32", out=r, stats=False)
+        return ctx.render_batch(scenes, cams, op32, refs=refs, outs=imgs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, c0, stk = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    achieved = stk["hot_steps"] * FLOP_PER_STEP["dopri5"] / (stk["hot_ms"] * 1e-3)
+    out = {
+        "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
+        "value": st["accepted_steps"] / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 scenes (seed 1012): A~U[0.02,0.15], half-width~U[2,8], res in {256,512,1024}^2, "
+                               "az~U[-60,60], el~U[15,60] deg, 4 spp, DOPRI5, one launch",
+                   "rtol_fp32": op32["rtol"], "rays": st["rays"], "ray_steps": st["accepted_steps"]},
+        "rays_per_s": st["rays"] / dt,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_wf_box<DOPRI5>",
+                     "kernel_ms": stk["hot_ms"], "kernel_steps": stk["hot_steps"]},
+        "fp32_breakdown": {k: stk[k] for k in ("hot_ms", "event_ms", "tail_ms", "total_ms", "rounds", "tail_rays",
+                                               "fp64_steps", "fallbacks", "failed")},
+    }
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c64, s64, r64 = [], 0, 0
+        errs = []
+        for i, (s, c) in enumerate(zip(scenes, cams)):
+            g64, st64 = ctx.render(s, c, op64, prec="f64")
+            s64 += st64["accepted_steps"]
+            r64 += st64["rays"]
+            cc64 = ctx.cross_correlate(g64, refs[i])[0]
+            c64.append(cc64)
+            errs.append(abs(cc64 - c0[i]))
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        out["fp64_plain"] = {"ray_steps_per_s": s64 / t64, "rays_per_s": r64 / t64, "ms": t64 * 1e3,
+                             "ray_steps": s64, "note": "per-scene FP64 launches, DOPRI5 rtol 1e-8"}
+        out["cc_error_fp32_vs_fp64"] = {"max": max(errs), "mean": float(np.mean(errs))}
+        out["speedup_rays_fp32_vs_fp64"] = (st["rays"] / dt) / (r64 / t64)
+    if not args.no_cpu:
+        from oracle import oracle as O
+        out["cpu_baseline"] = _cpu_baseline(O, scenes[0], cams[0], op64, W, args.cpu_seconds, "scene 0 of the batch")
+    print(json.dumps(out), flush=True)
+
+
+def main_stress(args):
+    import numpy as np
+    import torch
+    from paper_1012_5107_amd import binding as B
+    from paper_1012_5107_amd import workloads as W
+
+    sc, cam, op = W.branch_stress_1024()
+    op32 = dict(op, rtol=args.rtol32, atol=args.rtol32)
+    ctx = B.context(0)
+    img, st = ctx.render(sc, cam, op32, prec="f32")
+    ref, _ = ctx.render(W.reference_scene(sc), cam, op32, prec="f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        img, stk = ctx.render(sc, cam, op32, prec="f32", out=img)
+        c32 = ctx.cross_correlate(img, ref)[0]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {"metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
+           "value": st["accepted_steps"] / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 0, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "1024x1024, 8 spp, A=0.15 (Ak=0.94), elevation 10 deg at distance 12, DOPRI5",
+                      "rtol_fp32": op32["rtol"], "rays": st["rays"], "ray_steps": st["accepted_steps"]},
+           "rays_per_s": st["rays"] / dt, "cc_fp32": c32, "fp32_counters": stk}
     print(json.dumps(out), flush=True)
 
 

@@ -128,6 +128,7 @@ typedef struct {
     int64_t fp64_steps;      /* FP32 path: accepted steps taken by the FP64 event kernel (rounds) */
     int64_t rounds;          /* FP32 path: in-cloak / event rounds */
     int64_t tail_rays;       /* FP32 path: rays finished by the tail kernel */
+    int64_t hot_steps;       /* FP32 path: accepted steps taken by the FP32 in-cloak kernel */
     double hot_ms;           /* FP32 path: device time of the FP32 in-cloak kernel (HIP events) */
     double event_ms;         /* FP32 path: device time of the FP64 event and air kernels */
     double tail_ms;          /* FP32 path: device time of the tail kernel */

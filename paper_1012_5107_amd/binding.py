@@ -48,7 +48,7 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("accepted_steps", ctypes.c_int64), ("rejected_steps", ctypes.c_int64),
                 ("events", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("failed", ctypes.c_int64),
-                ("fp64_steps", ctypes.c_int64), ("rounds", ctypes.c_int64), ("tail_rays", ctypes.c_int64),
+                ("fp64_steps", ctypes.c_int64), ("rounds", ctypes.c_int64), ("tail_rays", ctypes.c_int64), ("hot_steps", ctypes.c_int64),
                 ("hot_ms", ctypes.c_double), ("event_ms", ctypes.c_double), ("tail_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
 

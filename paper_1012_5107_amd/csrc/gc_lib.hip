@@ -396,6 +396,7 @@ static gc_status read_counters(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
     st->rounds = 0;
     st->hot_ms = st->event_ms = st->total_ms = st->tail_ms = 0.0;
     st->tail_rays = 0;
+    st->hot_steps = 0;
     return GC_OK;
 }
 
@@ -497,7 +498,7 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
     w.tail_rays = 0;
     w.hot_ms = w.event_ms = w.tail_ms = 0.0;
     HIP_OK(hipEventRecord(w.ev[0], stream));
-    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, 1);
+    HIP_OK(hipMemsetAsync(w.ctr, 0, sizeof(QCtr), stream));
     hipLaunchKernelGGL(k_wf_init, dim3(init_blocks), dim3(256), 0, stream, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
@@ -603,6 +604,7 @@ static gc_status wf_read_totals(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
         st->event_ms = ctx->wf.event_ms;
         st->tail_ms = ctx->wf.tail_ms;
         st->tail_rays = ctx->wf.tail_rays;
+        st->hot_steps = (int64_t)ctx->wf.h_ctr->hot_steps;
         st->total_ms = tt;
     }
     return GC_OK;

@@ -37,6 +37,7 @@ struct QCtr {
     unsigned ev_head;
     unsigned air_len;
     unsigned air_head;
+    unsigned long long hot_steps;   // accepted steps taken by k_wf_box (all rounds)
 };
 
 // per-ray arrays (structure of arrays)
@@ -234,6 +235,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
     int steps = 0, rej = 0, mirror = 0;
     bool last_rej = false;
     double hw = 0.0, L = 1.0;
+    unsigned my_steps = 0;
 
     for (;;) {
         if (!exhausted) {
@@ -347,6 +349,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
         r1 = re;
         h = hnext;
         last_rej = false;
+        ++my_steps;
         if (++steps >= max_steps) {
             const WfRays& R = a.R;
             R.steps[q] = steps;
@@ -357,6 +360,10 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             active = false;
         }
     }
+    unsigned long long total = my_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
+    if (lane == 0) atomicAdd(&a.ctr->hot_steps, total);
 }
 
 // One flagged step of ray q in FP64 (step control, event location and

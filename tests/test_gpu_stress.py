@@ -1,0 +1,89 @@
+"""Branch-point stress workload (1024 x 1024, 8 spp, A = 0.15 so A k = 0.94,
+grazing camera): exit directions of seeded samples of the full-size launch
+against the FP64 oracle, with the error histogram.  MI355X only."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_1012_5107_amd import workloads as W
+from _parity import angle, check_directions
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLES = 8192
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1012_5107_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def rays():
+    sc, cam, op = W.branch_stress_1024()
+    rng = np.random.default_rng(20)
+    ii = rng.integers(0, cam["width"], N_SAMPLES)
+    jj = rng.integers(0, cam["height"], N_SAMPLES)
+    ss = rng.integers(0, cam["spp"], N_SAMPLES)
+    org = np.zeros((N_SAMPLES, 3))
+    d = np.zeros((N_SAMPLES, 3))
+    for k in range(N_SAMPLES):
+        org[k], d[k] = O.camera_ray(cam, ii[k], jj[k], ss[k])
+    return sc, cam, op, org, d
+
+
+def _histogram(err):
+    edges = 10.0 ** np.arange(-16, 1)
+    h, _ = np.histogram(np.clip(err, 1e-16, 0.99), bins=edges)
+    return " ".join(f"1e{int(np.log10(lo))}:{c}" for lo, c in zip(edges[:-1], h) if c)
+
+
+def _run(B, sc, op, org, d, prec):
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    oo, od, st, steps, ev = B.trace_rays(sc, op, torch.from_numpy(org), torch.from_numpy(d), prec=prec)
+    torch.cuda.synchronize()
+    steps_np = steps.cpu().numpy()
+    print(f"[stress {prec}] {time.perf_counter() - t0:.2f} s, steps q50/q99/max = "
+          f"{np.quantile(steps_np, 0.5):.0f}/{np.quantile(steps_np, 0.99):.0f}/{steps_np.max()}, "
+          f"status counts {np.bincount(st.cpu().numpy(), minlength=5).tolist()}", flush=True)
+    return od.cpu().numpy(), st.cpu().numpy(), steps_np, ev.cpu().numpy()
+
+
+def test_stress_fp64_matches_oracle(B, rays):
+    # A k = 0.94 and grazing incidence: a few percent of the rays are
+    # ill-conditioned even in FP64 (crest curvature radius 6e-4)
+    sc, cam, op, org, d = rays
+    op = dict(op, rtol=1e-8, atol=1e-8)
+    orc = O.trace_rays(sc, op, org, d)
+    print(f"[stress oracle] steps q50/q99/max = {np.quantile(orc['steps'], 0.5):.0f}/"
+          f"{np.quantile(orc['steps'], 0.99):.0f}/{orc['steps'].max()}", flush=True)
+    od, st, steps, ev = _run(B, sc, op, org, d, "f64")
+    err, mask, ill = check_directions(O, sc, op, org, d, orc, od, st, ev, 1e-10, 1e-15, "stress fp64",
+                                      max_ill=0.06)
+    print("[stress fp64 histogram]", _histogram(err[~mask]), flush=True)
+
+
+@pytest.mark.parametrize("w_fallback", [1e-2, 0.15])
+def test_stress_fp32_against_fp64_oracle(B, rays, w_fallback):
+    # Above the grating |1 + W| >= 1 - A k = 0.058 here, so the FP64 fallback
+    # at |1 + W| < 1e-2 only serves stage points inside the metal; a wider
+    # threshold moves the crests' neighbourhood to FP64 as well
+    sc, cam, op, org, d = rays
+    op64 = dict(op, rtol=1e-8, atol=1e-8)
+    op32 = dict(op, rtol=1e-7, atol=1e-7, w_fallback=w_fallback)
+    orc = O.trace_rays(sc, op64, org, d)
+    od, st, steps, ev = _run(B, sc, op32, org, d, "f32")
+    err, mask, ill = check_directions(O, sc, op64, org, d, orc, od, st, ev, 1e-4, 1e-6,
+                                      f"stress fp32(1e-7, fallback {w_fallback})", max_ill=0.06, p99_factor=50,
+                                      max_factor=5000)
+    print(f"[stress fp32 histogram, fallback {w_fallback}]", _histogram(err[~mask]),
+          f"excluded={int(mask.sum())}", flush=True)
+    _, stats = B.render(sc, dict(cam, width=128, height=128, spp=1), op32, prec="f32")
+    print(f"[stress fp32 counters, fallback {w_fallback}]", stats, flush=True)
