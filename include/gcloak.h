@@ -115,7 +115,7 @@ typedef struct {
     double w_fallback;     /* default 1e-2 */
     int32_t max_events;    /* default 32 */
     int32_t reserved;
-    int64_t max_steps;     /* default 10^7 */
+    int64_t max_steps;     /* default 10^5 */
 } gc_opts;
 
 typedef struct {
@@ -150,7 +150,7 @@ const char* gc_last_error(void);
 
 /* Fill `opts` with the defaults: FP64, RK4, h = 1e-3, rtol = atol = 1e-8,
  * h_max = 0.02, h0 = 1e-3, h_min = 1e-12, w_fallback = 1e-2,
- * max_events = 32, max_steps = 10^7. */
+ * max_events = 32, max_steps = 10^5. */
 void gc_default_opts(gc_opts* opts);
 
 /* Trace n rays (Sec. 3) from origins d_org and directions d_dir (n x 3

@@ -866,3 +866,443 @@ void gco_cross_correlate_f64(const double* f, const double* g, long npix, int nc
     out[0] = (double)(sfg / sff);
     out[1] = (double)(sfg / sqrtl(sff * sgg));
 }
+
+/* ------------------------------------------------------------------------ */
+/* Forward-mode derivatives with respect to the parameters (A, half_width)  */
+/* of the discrete RK4 tracer above.  Every map the tracer applies -- RK4   */
+/* steps, partial steps ending on an event (with the event time implicit    */
+/* in e(Phi(tau*)) = 0), reflections, Snell refraction, straight flight,    */
+/* the sky lookup -- is differentiated exactly, so the result is the        */
+/* derivative of the computed image, not of the continuous problem.         */
+/* ------------------------------------------------------------------------ */
+
+/* acceleration, its Jacobian d a / d(x, y) and d a / dA.  With D = 1 + W:
+   a_x + i a_y = i k F,  F = P conj(Q),  P = 1/D,  Q = W / D^3 (both
+   holomorphic in zeta = x + i y), dW/dzeta = i k W / D, dW/dA = W / (A D);
+   d/dx = d/dzeta + d/dzetabar, d/dy = i (d/dzeta - d/dzetabar). */
+static void orc_accel_jac(const oscene* s, double x, double y, double a[2], double J[2][2], double aA[2])
+{
+    cplx W;
+    orc_w0(orc_Z(s, x, y), &W);
+    cplx D = 1.0 + W;
+    cplx Wp = I * s->k * W / D;
+    cplx WA = (s->A > 0.0) ? W / (s->A * D) : -s->k * cexp(I * s->k * (x + I * y));
+    cplx P = 1.0 / D, Q = W / (D * D * D);
+    cplx Pp = -Wp / (D * D), Qp = Wp * (1.0 - 2.0 * W) / (D * D * D * D);
+    cplx PA = -WA / (D * D), QA = WA * (1.0 - 2.0 * W) / (D * D * D * D);
+    cplx F = P * conj(Q);
+    cplx Fz = Pp * conj(Q), Fzb = P * conj(Qp);
+    cplx FA = PA * conj(Q) + P * conj(QA);
+    cplx ax = I * s->k * F;
+    cplx dx = I * s->k * (Fz + Fzb);
+    cplx dy = -s->k * (Fz - Fzb);
+    cplx dA = I * s->k * FA;
+    a[0] = creal(ax); a[1] = cimag(ax);
+    J[0][0] = creal(dx); J[1][0] = cimag(dx);
+    J[0][1] = creal(dy); J[1][1] = cimag(dy);
+    aA[0] = creal(dA); aA[1] = cimag(dA);
+}
+
+/* index and its derivatives d n / d(x, y), d n / dA */
+static double orc_index_jac(const oscene* s, double x, double y, double dn[2], double* nA)
+{
+    cplx W;
+    orc_w0(orc_Z(s, x, y), &W);
+    cplx D = 1.0 + W;
+    cplx Wp = I * s->k * W / D;
+    cplx WA = (s->A > 0.0) ? W / (s->A * D) : -s->k * cexp(I * s->k * (x + I * y));
+    double n = 1.0 / cabs(D);
+    double n3 = n * n * n;
+    dn[0] = -n3 * creal(conj(D) * Wp);
+    dn[1] = n3 * cimag(conj(D) * Wp);
+    *nA = -n3 * creal(conj(D) * WA);
+    return n;
+}
+
+/* grating geometry at x: E = k xi, height S, slope S' = dS/dx, S_A = dS/dA
+   at fixed x, and E_x = dE/dx, E_A = dE/dA at fixed x */
+static void orc_surface_jac(const oscene* s, double x, double* E, double* S, double* Sx, double* SA,
+                            double* Ex, double* EA)
+{
+    *S = orc_surface(s, x, E);
+    double e = s->e, sn = sin(*E), cs = cos(*E);
+    double den = 1.0 - e * cs;
+    *Ex = s->k / den;
+    *EA = s->k * sn / den;
+    *Sx = -e * sn / den;
+    *SA = cs - e * sn * sn / den;
+}
+
+/* unit upward normal at x and its tangent for dx (position) and dA */
+static void orc_normal_tan(const oscene* s, double x, double dx, double dA, double N[2], double dN[2])
+{
+    double E, S, Sx, SA, Ex, EA;
+    orc_surface_jac(s, x, &E, &S, &Sx, &SA, &Ex, &EA);
+    double e = s->e, sn = sin(E), cs = cos(E);
+    double dE = Ex * dx + EA * dA;
+    double de = s->k * dA;
+    double m[2] = { e * sn, 1.0 - e * cs };
+    double dm[2] = { de * sn + e * cs * dE, -de * cs + e * sn * dE };
+    double r = sqrt(m[0] * m[0] + m[1] * m[1]);
+    N[0] = m[0] / r; N[1] = m[1] / r;
+    double ndm = N[0] * dm[0] + N[1] * dm[1];
+    dN[0] = (dm[0] - N[0] * ndm) / r;
+    dN[1] = (dm[1] - N[1] * ndm) / r;
+}
+
+/* p' = p - 2 (p.N) N in 3D with N = (N0, N1, 0), and its tangent */
+static void reflect_tan(double p[3], double dp[3], const double N[2], const double dN[2])
+{
+    double pn = p[0] * N[0] + p[1] * N[1];
+    double dpn = dp[0] * N[0] + dp[1] * N[1] + p[0] * dN[0] + p[1] * dN[1];
+    for (int i = 0; i < 2; ++i) {
+        dp[i] -= 2.0 * (dpn * N[i] + pn * dN[i]);
+        p[i] -= 2.0 * pn * N[i];
+    }
+}
+
+/* Snell at a plane face with fixed unit normal nf, n2 with tangent dn2 */
+static int snell_tan(double p[3], double dp[3], const double nf[3], double n2, double dn2)
+{
+    double pn = p[0] * nf[0] + p[1] * nf[1] + p[2] * nf[2];
+    double dpn = dp[0] * nf[0] + dp[1] * nf[1] + dp[2] * nf[2];
+    double pt[3], dpt[3];
+    for (int i = 0; i < 3; ++i) { pt[i] = p[i] - pn * nf[i]; dpt[i] = dp[i] - dpn * nf[i]; }
+    double q = n2 * n2 - (pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2]);
+    if (q < 0.0) {
+        for (int i = 0; i < 3; ++i) { p[i] -= 2.0 * pn * nf[i]; dp[i] -= 2.0 * dpn * nf[i]; }
+        return 0;
+    }
+    double dq = 2.0 * n2 * dn2 - 2.0 * (pt[0] * dpt[0] + pt[1] * dpt[1] + pt[2] * dpt[2]);
+    double sg = pn >= 0.0 ? 1.0 : -1.0;
+    double r = sqrt(q);
+    for (int i = 0; i < 3; ++i) {
+        p[i] = pt[i] + sg * r * nf[i];
+        dp[i] = dpt[i] + sg * dq / (2.0 * r) * nf[i];
+    }
+    return 1;
+}
+
+/* RK4 step of size tau from u with parameter tangents du[j] (j = 0: A,
+   j = 1: half_width); also returns d out / d tau */
+static void rk4_step_tan(const oscene* s, const st4* u, const double du[2][4], double tau, st4* out,
+                         double dout[2][4], double dtau[4])
+{
+    static const double c[4] = { 0.0, 0.5, 0.5, 1.0 }, w[4] = { 1.0, 2.0, 2.0, 1.0 };
+    double K[4][4], dK[4][2][4], tK[4][4];
+    for (int i = 0; i < 4; ++i) {
+        double U[4], dU[2][4], tU[4];
+        for (int q = 0; q < 4; ++q) {
+            U[q] = u->v[q] + (i ? c[i] * tau * K[i - 1][q] : 0.0);
+            tU[q] = i ? c[i] * K[i - 1][q] + c[i] * tau * tK[i - 1][q] : 0.0;
+            for (int j = 0; j < 2; ++j) dU[j][q] = du[j][q] + (i ? c[i] * tau * dK[i - 1][j][q] : 0.0);
+        }
+        double a[2], J[2][2], aA[2];
+        orc_accel_jac(s, U[0], U[1], a, J, aA);
+        K[i][0] = U[2]; K[i][1] = U[3]; K[i][2] = a[0]; K[i][3] = a[1];
+        tK[i][0] = tU[2]; tK[i][1] = tU[3];
+        tK[i][2] = J[0][0] * tU[0] + J[0][1] * tU[1];
+        tK[i][3] = J[1][0] * tU[0] + J[1][1] * tU[1];
+        for (int j = 0; j < 2; ++j) {
+            dK[i][j][0] = dU[j][2];
+            dK[i][j][1] = dU[j][3];
+            dK[i][j][2] = J[0][0] * dU[j][0] + J[0][1] * dU[j][1] + (j == 0 ? aA[0] : 0.0);
+            dK[i][j][3] = J[1][0] * dU[j][0] + J[1][1] * dU[j][1] + (j == 0 ? aA[1] : 0.0);
+        }
+    }
+    for (int q = 0; q < 4; ++q) {
+        double sum = 0.0, tsum = 0.0;
+        for (int i = 0; i < 4; ++i) { sum += w[i] * K[i][q]; tsum += w[i] * tK[i][q]; }
+        out->v[q] = u->v[q] + (tau / 6.0) * (K[0][q] + 2.0 * K[1][q] + 2.0 * K[2][q] + K[3][q]);
+        dtau[q] = sum / 6.0 + (tau / 6.0) * tsum;
+        for (int j = 0; j < 2; ++j) {
+            double ds = 0.0;
+            for (int i = 0; i < 4; ++i) ds += w[i] * dK[i][j][q];
+            dout[j][q] = du[j][q] + (tau / 6.0) * ds;
+        }
+    }
+}
+
+/* FNV-1a over the event codes and the number of integrator steps between
+   events: equal signatures mean equal event sequences on the same step
+   grid.  The discrete map is smooth between signature changes; where the
+   event moves from the end of one step to the start of the next, the map
+   has a kink because the derivative of an RK4 step with respect to its
+   length differs from the right-hand side at its end by the local error. */
+static uint64_t sig_add(uint64_t h, uint64_t code)
+{
+    h ^= code + 1;
+    return h * 0x100000001B3ULL;
+}
+
+/* trace with tangents (RK4 only).  dir_out: unit exit direction; ddir[j]:
+   its derivative wrt A (j = 0) and half_width (j = 1). */
+static int trace_one_tan(const oscene* s, const oopts* o, const double org[3], const double dir[3],
+                         double dir_out[3], double ddir[2][3], uint64_t* sig, trace_info* ti)
+{
+    double r[3] = { org[0], org[1], org[2] };
+    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double p[3] = { dir[0] / nd, dir[1] / nd, dir[2] / nd };
+    double dr[2][3] = { { 0 } }, dp[2][3] = { { 0 } };
+    uint64_t h = 0xcbf29ce484222325ULL;
+    memset(ti, 0, sizeof(*ti));
+    ti->min_cos = 1.0;
+    for (;;) {
+        int face;
+        double tb = air_box_entry(s, r, p, &face);
+        double tg = air_contact(s, r, p);
+        if (!isfinite(tb) && !isfinite(tg)) {
+            for (int i = 0; i < 3; ++i) { dir_out[i] = p[i]; ddir[0][i] = dp[0][i]; ddir[1][i] = dp[1][i]; }
+            *sig = h;
+            return RAY_OK;
+        }
+        if (++ti->events > o->max_events) { *sig = h; return RAY_MAX_EVENTS; }
+        if (tg <= tb) {
+            /* contact with the bare grating: g(t) = y0 + t py - S(x0 + t px) = 0 */
+            double t = tg;
+            double xc = r[0] + t * p[0];
+            double E, S, Sx, SA, Ex, EA;
+            orc_surface_jac(s, xc, &E, &S, &Sx, &SA, &Ex, &EA);
+            double gt = p[1] - Sx * p[0];
+            for (int j = 0; j < 2; ++j) {
+                double dt = -(dr[j][1] + t * dp[j][1] - Sx * (dr[j][0] + t * dp[j][0]) - (j == 0 ? SA : 0.0)) / gt;
+                for (int i = 0; i < 3; ++i) dr[j][i] += dt * p[i] + t * dp[j][i];
+            }
+            for (int i = 0; i < 3; ++i) r[i] += t * p[i];
+            double p0[3] = { p[0], p[1], p[2] };
+            for (int j = 0; j < 2; ++j) {
+                double N[2], dN[2], pp[3] = { p0[0], p0[1], p0[2] };
+                orc_normal_tan(s, r[0], dr[j][0], j == 0 ? 1.0 : 0.0, N, dN);
+                reflect_tan(pp, dp[j], N, dN);
+                if (j == 1) for (int i = 0; i < 3; ++i) p[i] = pp[i];
+            }
+            ti->contacts++;
+            h = sig_add(h, 1);
+            continue;
+        }
+        /* entry into the box */
+        double t = tb;
+        for (int j = 0; j < 2; ++j) {
+            double dt;
+            if (face == EV_TOP) dt = -(dr[j][1] + t * dp[j][1]) / p[1];
+            else if (face == EV_RIGHT) dt = ((j == 1 ? 1.0 : 0.0) - dr[j][0] - t * dp[j][0]) / p[0];
+            else dt = (-(j == 1 ? 1.0 : 0.0) - dr[j][0] - t * dp[j][0]) / p[0];
+            for (int i = 0; i < 3; ++i) dr[j][i] += dt * p[i] + t * dp[j][i];
+        }
+        for (int i = 0; i < 3; ++i) r[i] += t * p[i];
+        if (face == EV_TOP) r[1] = s->ytop; else if (face == EV_RIGHT) r[0] = s->hw; else r[0] = -s->hw;
+        double nf[3];
+        face_normal(face, nf);
+        for (int i = 0; i < 3; ++i) nf[i] = -nf[i];
+        double dn[2], nA;
+        double n2 = orc_index_jac(s, r[0], r[1], dn, &nA);
+        int through = 1;
+        {
+            double p0[3] = { p[0], p[1], p[2] };
+            for (int j = 0; j < 2; ++j) {
+                double pp[3] = { p0[0], p0[1], p0[2] };
+                double dn2 = dn[0] * dr[j][0] + dn[1] * dr[j][1] + (j == 0 ? nA : 0.0);
+                through = snell_tan(pp, dp[j], nf, n2, dn2);
+                if (j == 1) for (int i = 0; i < 3; ++i) p[i] = pp[i];
+            }
+        }
+        h = sig_add(h, 10 + face + (through ? 0 : 4));
+        if (!through) continue;
+        /* integrate inside the box (RK4) */
+        st4 u = { { r[0], r[1], p[0], p[1] } };
+        double du[2][4];
+        for (int j = 0; j < 2; ++j) { du[j][0] = dr[j][0]; du[j][1] = dr[j][1]; du[j][2] = dp[j][0]; du[j][3] = dp[j][1]; }
+        double pz = p[2], dpz[2] = { dp[0][2], dp[1][2] };
+        int bad = 0;
+        long run = 0;   /* steps since the last event: part of the signature */
+        for (;;) {
+            if (ti->steps >= o->max_steps) { *sig = h; return RAY_MAX_STEPS; }
+            st4 y5;
+            double dy5[2][4], dtau[4];
+            rk4_step_tan(s, &u, du, o->h, &y5, dy5, dtau);
+            ti->steps++;
+            run++;
+            int hit = EV_NONE;
+            double theta = 2.0;
+            for (int ev = 0; ev < 4; ++ev) {
+                if (event_value(s, ev, &y5) >= 0.0) continue;
+                double lo = 0.0, hi = 1.0;
+                while (hi - lo > 1e-14) {
+                    double mid = 0.5 * (lo + hi);
+                    st4 ym;
+                    rk4_step(s, &u, mid * o->h, &ym, &bad);
+                    if (event_value(s, ev, &ym) < 0.0) hi = mid; else lo = mid;
+                }
+                if (hi < theta) { theta = hi; hit = ev; }
+            }
+            if (hit == EV_NONE) {
+                u = y5;
+                memcpy(du, dy5, sizeof du);
+                continue;
+            }
+            /* partial step to the event; tau* implicit in e(Phi(tau*)) = 0 */
+            st4 ye;
+            double dye[2][4], dte[4];
+            double taus = theta * o->h;
+            rk4_step_tan(s, &u, du, taus, &ye, dye, dte);
+            double ge[4] = { 0, 0, 0, 0 }, eA = 0.0, ehw = 0.0;
+            if (hit == EV_TOP) ge[1] = -1.0;
+            else if (hit == EV_RIGHT) { ge[0] = -1.0; ehw = 1.0; }
+            else if (hit == EV_LEFT) { ge[0] = 1.0; ehw = 1.0; }
+            else {
+                double E, S, Sx, SA, Ex, EA;
+                orc_surface_jac(s, ye.v[0], &E, &S, &Sx, &SA, &Ex, &EA);
+                ge[0] = -Sx; ge[1] = 1.0; eA = -SA;
+            }
+            double gt = ge[0] * dte[0] + ge[1] * dte[1];
+            for (int j = 0; j < 2; ++j) {
+                double num = ge[0] * dye[j][0] + ge[1] * dye[j][1] + (j == 0 ? eA : ehw);
+                double dts = -num / gt;
+                for (int q = 0; q < 4; ++q) du[j][q] = dye[j][q] + dte[q] * dts;
+            }
+            u = ye;
+            h = sig_add(h, (uint64_t)run);
+            run = 0;
+            if (++ti->events > o->max_events) { *sig = h; return RAY_MAX_EVENTS; }
+            double pp3[3] = { u.v[2], u.v[3], pz };
+            double dpp[2][3] = { { du[0][2], du[0][3], dpz[0] }, { du[1][2], du[1][3], dpz[1] } };
+            if (hit == EV_GRATING) {
+                double p0[3] = { pp3[0], pp3[1], pp3[2] };
+                for (int j = 0; j < 2; ++j) {
+                    double N[2], dN[2], q3[3] = { p0[0], p0[1], p0[2] };
+                    orc_normal_tan(s, u.v[0], du[j][0], j == 0 ? 1.0 : 0.0, N, dN);
+                    reflect_tan(q3, dpp[j], N, dN);
+                    if (j == 1) for (int i = 0; i < 3; ++i) pp3[i] = q3[i];
+                }
+                ti->contacts++;
+                h = sig_add(h, 20);
+            } else {
+                double nfb[3];
+                face_normal(hit, nfb);
+                double p0[3] = { pp3[0], pp3[1], pp3[2] };
+                int thr = 1;
+                for (int j = 0; j < 2; ++j) {
+                    double q3[3] = { p0[0], p0[1], p0[2] };
+                    thr = snell_tan(q3, dpp[j], nfb, 1.0, 0.0);
+                    if (j == 1) for (int i = 0; i < 3; ++i) pp3[i] = q3[i];
+                }
+                h = sig_add(h, 30 + hit + (thr ? 0 : 4));
+                if (thr) {
+                    r[0] = u.v[0]; r[1] = u.v[1];
+                    for (int i = 0; i < 3; ++i) p[i] = pp3[i];
+                    for (int j = 0; j < 2; ++j) {
+                        dr[j][0] = du[j][0]; dr[j][1] = du[j][1]; dr[j][2] = 0.0;
+                        for (int i = 0; i < 3; ++i) dp[j][i] = dpp[j][i];
+                    }
+                    break;
+                }
+            }
+            u.v[2] = pp3[0]; u.v[3] = pp3[1];
+            for (int j = 0; j < 2; ++j) { du[j][2] = dpp[j][0]; du[j][3] = dpp[j][1]; dpz[j] = dpp[j][2]; }
+        }
+    }
+}
+
+/* sky colour and its gradient with respect to the (unnormalised) direction */
+static void sky_grad(double K, const double d[3], double rgb[3], double g[3][3])
+{
+    const double Ca[3] = { 0.95, 0.85, 0.30 }, Cb[3] = { 0.10, 0.20, 0.55 };
+    double rho2 = d[0] * d[0] + d[2] * d[2], rho = sqrt(rho2);
+    double r2 = rho2 + d[1] * d[1];
+    double phi = atan2(d[0], -d[2]);
+    double th = atan2(d[1], rho);
+    double A4 = cos(4.0 * phi), B8 = sin(8.0 * th);
+    double ta = tanh(K * A4), tb = tanh(K * B8);
+    double m = 0.5 + 0.5 * ta * tb;
+    double dphi[3] = { -d[2] / rho2, 0.0, d[0] / rho2 };
+    double dth[3] = { -d[1] * d[0] / (rho * r2), rho / r2, -d[1] * d[2] / (rho * r2) };
+    double dm[3];
+    for (int i = 0; i < 3; ++i)
+        dm[i] = 0.5 * ((1.0 - ta * ta) * K * (-4.0 * sin(4.0 * phi)) * dphi[i] * tb +
+                       ta * (1.0 - tb * tb) * K * 8.0 * cos(8.0 * th) * dth[i]);
+    for (int c = 0; c < 3; ++c) {
+        rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);
+        for (int i = 0; i < 3; ++i) g[c][i] = dm[i] * (Ca[c] - Cb[c]);
+    }
+}
+
+/* Per-sample render with derivatives (RK4 only).  For each listed pixel
+   (or all when npix < 0) and sample: rgb (3), d rgb / dA (3),
+   d rgb / d half_width (3), event signature, status.  Outputs are indexed
+   (pixel, sample). */
+int gco_render_samples_tan(const double* scene, const double* cam, uint64_t seed, const double* opts,
+                           long npix, const long* pix, double* rgb, double* drgb_A, double* drgb_hw,
+                           uint64_t* sig, int* status, int nthreads)
+{
+    oscene s;
+    oopts o;
+    load_scene(scene, &s);
+    load_opts(opts, &o);
+    if (o.integ != 0 || s.mirror == 1 || !isfinite(s.K)) return -1;
+    int W = (int)cam[7], H = (int)cam[8], spp = (int)cam[9];
+    long total = npix < 0 ? (long)W * H : npix;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (long q = 0; q < total; ++q) {
+        long pidx = npix < 0 ? q : pix[q];
+        int i = (int)(pidx % W), j = (int)(pidx / W);
+        for (int smp = 0; smp < spp; ++smp) {
+            long k = q * spp + smp;
+            double org[3], dir[3], od[3], dd[2][3], c[3], g[3][3];
+            trace_info ti;
+            gco_camera_ray(cam, seed, i, j, smp, org, dir);
+            int st = trace_one_tan(&s, &o, org, dir, od, dd, &sig[k], &ti);
+            status[k] = st;
+            if (st != RAY_OK) {
+                for (int a = 0; a < 3; ++a) { rgb[3 * k + a] = 0.0; drgb_A[3 * k + a] = 0.0; drgb_hw[3 * k + a] = 0.0; }
+                continue;
+            }
+            sky_grad(s.K, od, c, g);
+            for (int a = 0; a < 3; ++a) {
+                rgb[3 * k + a] = c[a];
+                drgb_A[3 * k + a] = g[a][0] * dd[0][0] + g[a][1] * dd[0][1] + g[a][2] * dd[0][2];
+                drgb_hw[3 * k + a] = g[a][0] * dd[1][0] + g[a][1] * dd[1][1] + g[a][2] * dd[1][2];
+            }
+        }
+    }
+    return 0;
+}
+
+/* exported pointwise derivative helpers (for the test-suite) */
+void gco_accel_jac(const double* scene, double x, double y, double out[8])
+{
+    oscene s;
+    load_scene(scene, &s);
+    double a[2], J[2][2], aA[2];
+    orc_accel_jac(&s, x, y, a, J, aA);
+    out[0] = a[0]; out[1] = a[1];
+    out[2] = J[0][0]; out[3] = J[0][1]; out[4] = J[1][0]; out[5] = J[1][1];
+    out[6] = aA[0]; out[7] = aA[1];
+}
+
+int gco_trace_rays_tan(const double* scene, const double* opts, long n, const double* org, const double* dir,
+                       double* out_dir, double* ddir, int* status, uint64_t* sig, int nthreads)
+{
+    oscene s;
+    oopts o;
+    load_scene(scene, &s);
+    load_opts(opts, &o);
+    if (o.integ != 0 || s.mirror == 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (long i = 0; i < n; ++i) {
+        trace_info ti;
+        double od[3], dd[2][3];
+        status[i] = trace_one_tan(&s, &o, org + 3 * i, dir + 3 * i, od, dd, &sig[i], &ti);
+        for (int k = 0; k < 3; ++k) {
+            out_dir[3 * i + k] = od[k];
+            ddir[6 * i + k] = dd[0][k];
+            ddir[6 * i + 3 + k] = dd[1][k];
+        }
+    }
+    return 0;
+}

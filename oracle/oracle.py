@@ -58,6 +58,15 @@ def lib():
         L.gco_cross_correlate.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                           ctypes.c_long, ctypes.c_int, dp]
         L.gco_cross_correlate_f64.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, dp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.gco_accel_jac.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.gco_trace_rays_tan.argtypes = [dp, dp, ctypes.c_long, dp, dp, dp, dp,
+                                         ctypes.POINTER(ctypes.c_int), u64p, ctypes.c_int]
+        L.gco_trace_rays_tan.restype = ctypes.c_int
+        L.gco_render_samples_tan.argtypes = [dp, dp, ctypes.c_uint64, dp, ctypes.c_long,
+                                             ctypes.POINTER(ctypes.c_long), dp, dp, dp, u64p,
+                                             ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+        L.gco_render_samples_tan.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -209,3 +218,85 @@ def cross_correlate(f, g):
         gg = np.ascontiguousarray(g, dtype=np.float64)
         lib().gco_cross_correlate_f64(_dp(ff), _dp(gg), npix, nch, _dp(out))
     return float(out[0]), float(out[1])
+
+
+# --- derivatives with respect to the scene parameters (A, half_width) --------
+
+def accel_jac(sc, x, y):
+    """Acceleration a(x, y), its Jacobian d a / d(x, y) (2 x 2, rows a_x,
+    a_y) and d a / dA."""
+    s = scene_array(sc)
+    out = np.zeros(8)
+    lib().gco_accel_jac(_dp(s), float(x), float(y), _dp(out))
+    return out[0:2].copy(), out[2:6].reshape(2, 2).copy(), out[6:8].copy()
+
+
+def trace_rays_tan(sc, o, org, d, nthreads=0):
+    """RK4 tracer with forward-mode tangents.  Returns dict with the unit exit
+    direction, its derivatives d_A and d_hw (n x 3 each), status and the
+    event-sequence signature of every ray."""
+    if o["integrator"] != "rk4" or sc["mirror"]:
+        raise ValueError("tangents are provided for RK4 and cloak / grating scenes only")
+    org = np.ascontiguousarray(org, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+    n = org.shape[0]
+    s, p = scene_array(sc), opts_array(o)
+    od = np.zeros((n, 3))
+    dd = np.zeros((n, 2, 3))
+    st = np.zeros(n, dtype=np.int32)
+    sig = np.zeros(n, dtype=np.uint64)
+    r = lib().gco_trace_rays_tan(_dp(s), _dp(p), n, _dp(org), _dp(d), _dp(od), _dp(dd),
+                                 st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 sig.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), int(nthreads))
+    if r != 0:
+        raise ValueError("unsupported tangent configuration")
+    return dict(dir=od, d_A=dd[:, 0], d_hw=dd[:, 1], status=st, sig=sig)
+
+
+def render_samples_tan(sc, cam, o, pixels=None, nthreads=0):
+    """Per-sample colours and their derivatives with respect to A and
+    half_width.  Arrays are (npix, spp, 3) (colours, d_A, d_hw) and (npix,
+    spp) (signature, status); pixels are all pixels in row-major order or
+    the listed linear indices."""
+    if o["integrator"] != "rk4" or sc["mirror"] or not np.isfinite(sc["sky_K"]):
+        raise ValueError("tangents are provided for RK4, cloak / grating scenes and finite sky_K only")
+    s, c, p = scene_array(sc), camera_array(cam), opts_array(o)
+    W, H, spp = cam["width"], cam["height"], cam["spp"]
+    if pixels is None:
+        npix, pix, pp = W * H, None, -1
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        npix, pp = pix.size, pix.size
+    rgb = np.zeros((npix, spp, 3))
+    dA = np.zeros((npix, spp, 3))
+    dhw = np.zeros((npix, spp, 3))
+    sig = np.zeros((npix, spp), dtype=np.uint64)
+    st = np.zeros((npix, spp), dtype=np.int32)
+    r = lib().gco_render_samples_tan(
+        _dp(s), _dp(c), ctypes.c_uint64(cam["seed"]), _dp(p), pp,
+        None if pix is None else pix.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+        _dp(rgb), _dp(dA), _dp(dhw), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+        st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(nthreads))
+    if r != 0:
+        raise ValueError("unsupported tangent configuration")
+    return dict(rgb=rgb, d_A=dA, d_hw=dhw, sig=sig, status=st)
+
+
+def render_grad(sc, cam, o, ref, nthreads=0):
+    """Loss L = 1 - C0 (eq. (15) at zero shift against the reference image
+    `ref`, H x W x 3) of the rendered image and its derivatives dL/dA,
+    dL/dhw, by forward-mode tangents.  Since the reference deviations f'
+    sum to zero per channel, C0 = sum f' g / sum f'^2 is linear in g, so
+    dL/dtheta = -sum f' dg/dtheta / sum f'^2.  Returns dict(loss, dA, dhw,
+    image)."""
+    t = render_samples_tan(sc, cam, o, nthreads=nthreads)
+    H, W = cam["height"], cam["width"]
+    g = t["rgb"].mean(axis=1).reshape(H, W, 3)
+    gA = t["d_A"].mean(axis=1).reshape(H, W, 3)
+    ghw = t["d_hw"].mean(axis=1).reshape(H, W, 3)
+    f = np.asarray(ref, dtype=np.float64).reshape(H, W, 3)
+    fp = f - f.reshape(-1, 3).mean(axis=0)
+    den = float((fp * fp).sum())
+    C0, _ = cross_correlate(f, g)
+    return dict(loss=1.0 - C0, dA=-float((fp * gA).sum()) / den, dhw=-float((fp * ghw).sum()) / den,
+                image=g, tan=t)

@@ -690,7 +690,7 @@ void gc_default_opts(gc_opts* o)
     o->h_min = 1e-12;
     o->w_fallback = 1e-2;
     o->max_events = 32;
-    o->max_steps = 10000000;
+    o->max_steps = 100000;
 }
 
 gc_status gc_create(gc_ctx** out, int hip_device)

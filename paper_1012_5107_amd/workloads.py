@@ -50,7 +50,7 @@ def orbit_eye(az_deg, el_deg, R):
 
 
 def opts(integrator="rk4", h=1e-3, rtol=1e-8, atol=None, h_max=0.02, max_events=32,
-         max_steps=10_000_000, h0=1e-3, h_min=1e-12, w_fallback=1e-2):
+         max_steps=100_000, h0=1e-3, h_min=1e-12, w_fallback=1e-2):
     return dict(integrator=integrator, h=float(h), rtol=float(rtol),
                 atol=float(rtol if atol is None else atol), h_max=float(h_max),
                 max_events=int(max_events), max_steps=int(max_steps), h0=float(h0),

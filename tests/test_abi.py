@@ -47,4 +47,4 @@ def test_default_opts():
     from paper_1012_5107_amd import binding as B
     o = B.Opts()
     B.load().gc_default_opts(ctypes.byref(o))
-    assert (o.prec, o.integ, o.h, o.rtol, o.max_events, o.max_steps) == (0, 0, 1e-3, 1e-8, 32, 10_000_000)
+    assert (o.prec, o.integ, o.h, o.rtol, o.max_events, o.max_steps) == (0, 0, 1e-3, 1e-8, 32, 100_000)
