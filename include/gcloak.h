@@ -187,6 +187,49 @@ gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes,
                           const gc_opts* opts, float* const* d_rgb, const float* const* d_ref, double* C0,
                           gc_stats* st, hipStream_t stream);
 
+typedef enum {
+    GC_LOSS_C0 = 0,     /* L = 1 - C0: eq. (15) at zero shift, sum f'g' / sum f'^2 */
+    GC_LOSS_NCC = 1     /* L = 1 - NCC: sum f'g' / sqrt(sum f'^2 sum g'^2) */
+} gc_loss;
+
+/* Cloaking-quality loss L (gc_loss) of the image rendered as gc_render does,
+ * against the reference d_ref, and its derivatives with respect to the
+ * grating amplitude A (eq. (2)) and the cloak's half_width, by the discrete
+ * adjoint of the RK4 tracer (opts->integ must be GC_RK4).  opts->prec
+ * selects FP64 or FP32 in-cloak arithmetic; surface maps, sky and sums are
+ * FP64.  In FP32 the samples whose derivative FP32 cannot resolve -- paths
+ * of more than 20000 steps, or a sky parameter m more sensitive than 60 per
+ * radian to the initial direction -- are traced and differentiated again
+ * in FP64 (colour included).
+ * Each sample is traced forward with its state recorded every
+ * `checkpoint_every` steps (1..256; 64 is the usual choice) and at every
+ * event, then reversed from dm = 1, where m is the sky's blend parameter
+ * (colour = Cb + m (Ca - Cb)): segments are recomputed from their
+ * checkpoint and the transposed step Jacobians applied, including the
+ * derivative of every event time (partial steps ending on a face or on the
+ * grating, straight flights ending on the grating or the box).  The result
+ * is the derivative of the discrete image, sample by sample; a sample
+ * whose event sequence changes at the current parameters contributes its
+ * one-sided value, and samples near grazing contacts or crests have large
+ * derivatives that dominate the sum.
+ * d_ref: height x width x 3 float32 (device, not constant).  Optional
+ * outputs (null to skip): d_rgb receives the image (height x width x 3
+ * float32); d_sample_dm the per-sample dm/dA and dm/dhw (width * height *
+ * spp pairs of doubles, sample s of pixel (i, j) at ((j width + i) spp + s);
+ * zero for failed samples); loss / dL_dA / dL_dhw (host) the results; st
+ * the forward counters (rays, accepted_steps, events, failed; tail_rays =
+ * samples differentiated again in FP64 -- FP32 hand-overs and tapes longer
+ * than 256 records; rounds = samples that needed a tape for the longest
+ * trace the options allow; hot_ms / tail_ms / total_ms the device time of
+ * the first pass, of the FP64 passes and of the call).  Device scratch
+ * (tapes of up to 4 GiB) is owned by the context.  Synchronises the
+ * stream.  GC_EUNSUPPORTED for DOPRI5, flat-mirror scenes or sky_K = inf;
+ * GC_EINVAL for a constant reference (or, for NCC, a constant image). */
+gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
+                         const float* d_ref, int32_t loss_kind, int32_t checkpoint_every, float* d_rgb,
+                         double* d_sample_dm, double* loss, double* dL_dA, double* dL_dhw, gc_stats* st,
+                         hipStream_t stream);
+
 /* Zero-shift cross-correlation of eqs. (14)-(15) between d_img (g) and the
  * reference d_ref (f): both npix x nch float32, channel fastest.  Each
  * channel's mean is subtracted (eq. (14)) and the sums are pooled over

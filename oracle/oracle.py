@@ -282,21 +282,36 @@ def render_samples_tan(sc, cam, o, pixels=None, nthreads=0):
     return dict(rgb=rgb, d_A=dA, d_hw=dhw, sig=sig, status=st)
 
 
-def render_grad(sc, cam, o, ref, nthreads=0):
-    """Loss L = 1 - C0 (eq. (15) at zero shift against the reference image
-    `ref`, H x W x 3) of the rendered image and its derivatives dL/dA,
-    dL/dhw, by forward-mode tangents.  Since the reference deviations f'
-    sum to zero per channel, C0 = sum f' g / sum f'^2 is linear in g, so
-    dL/dtheta = -sum f' dg/dtheta / sum f'^2.  Returns dict(loss, dA, dhw,
-    image)."""
+def loss_weights(ref, img, loss="ncc"):
+    """dL/dg for the image g = img against the reference f = ref (both
+    H x W x 3), with f' and g' the deviations from the channel means
+    (eq. (14)), pooled over channels:
+      L = 1 - C0,  C0 = sum f' g' / sum f'^2 (eq. (15) at zero shift):
+          dL/dg = -f' / sum f'^2  (sum f' = 0 per channel, so the mean of
+          g drops out);
+      L = 1 - NCC, NCC = sum f' g' / sqrt(sum f'^2 sum g'^2):
+          dL/dg = -(f' / sqrt(sum f'^2 sum g'^2) - NCC g' / sum g'^2).
+    Returns (L, dL/dg)."""
+    f = np.asarray(ref, dtype=np.float64)
+    g = np.asarray(img, dtype=np.float64)
+    fp = f - f.reshape(-1, 3).mean(axis=0)
+    gp = g - g.reshape(-1, 3).mean(axis=0)
+    sff, sgg, sfg = float((fp * fp).sum()), float((gp * gp).sum()), float((fp * gp).sum())
+    if loss == "c0":
+        return 1.0 - sfg / sff, -fp / sff
+    ncc = sfg / np.sqrt(sff * sgg)
+    return 1.0 - ncc, -(fp / np.sqrt(sff * sgg) - ncc * gp / sgg)
+
+
+def render_grad(sc, cam, o, ref, loss="ncc", nthreads=0):
+    """Loss L (1 - NCC or 1 - C0, see loss_weights) of the rendered image
+    against the reference image `ref` (H x W x 3) and its derivatives dL/dA,
+    dL/dhw, by forward-mode tangents: dL/dtheta = sum dL/dg dg/dtheta.
+    Returns dict(loss, dA, dhw, image, tan)."""
     t = render_samples_tan(sc, cam, o, nthreads=nthreads)
     H, W = cam["height"], cam["width"]
     g = t["rgb"].mean(axis=1).reshape(H, W, 3)
     gA = t["d_A"].mean(axis=1).reshape(H, W, 3)
     ghw = t["d_hw"].mean(axis=1).reshape(H, W, 3)
-    f = np.asarray(ref, dtype=np.float64).reshape(H, W, 3)
-    fp = f - f.reshape(-1, 3).mean(axis=0)
-    den = float((fp * fp).sum())
-    C0, _ = cross_correlate(f, g)
-    return dict(loss=1.0 - C0, dA=-float((fp * gA).sum()) / den, dhw=-float((fp * ghw).sum()) / den,
-                image=g, tan=t)
+    L, wgt = loss_weights(np.asarray(ref).reshape(H, W, 3), g, loss)
+    return dict(loss=L, dA=float((wgt * gA).sum()), dhw=float((wgt * ghw).sum()), image=g, tan=t)

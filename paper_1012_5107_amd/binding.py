@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libgcloak.so")
 
 GC_OK, GC_EINVAL, GC_EDOMAIN, GC_ENOMEM, GC_EDEVICE, GC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GC_F64, GC_F32 = 0, 1
+GC_LOSS_C0, GC_LOSS_NCC = 0, 1
+SKY_CA = (0.95, 0.85, 0.30)   # sky colours: colour = CB + m (CA - CB)
+SKY_CB = (0.10, 0.20, 0.55)
 GC_RK4, GC_DOPRI5 = 0, 1
 RAY_OK, RAY_MAX_STEPS, RAY_MAX_EVENTS, RAY_NONFINITE, RAY_STEP_UNDERFLOW = range(5)
 
@@ -59,7 +62,7 @@ class Stats(ctypes.Structure):
 
 # every symbol the header declares
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
-           "gc_render_batch", "gc_cross_correlate"]
+           "gc_render_batch", "gc_render_grad", "gc_cross_correlate"]
 
 _lib = None
 
@@ -90,6 +93,10 @@ def load():
                                   ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(Stats), vp]
     L.gc_render_batch.restype = ctypes.c_int
+    dptr = ctypes.POINTER(ctypes.c_double)
+    L.gc_render_grad.argtypes = [vp, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts), vp, i32,
+                                 i32, vp, vp, dptr, dptr, dptr, ctypes.POINTER(Stats), vp]
+    L.gc_render_grad.restype = ctypes.c_int
     L.gc_cross_correlate.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), vp]
     L.gc_cross_correlate.restype = ctypes.c_int
@@ -210,6 +217,27 @@ class Context:
                                       _stream_handle(stream)))
         return imgs, (list(c0) if c0 is not None else None), st.as_dict()
 
+    def render_grad(self, scene, camera, opts, ref, prec="f64", loss="ncc", checkpoint_every=64, out=None,
+                    sample_dm=False, stream=None):
+        """Loss 1 - NCC (loss="ncc") or 1 - C0 of eq. (15) (loss="c0")
+        against the device reference image `ref` (H x W x 3) and its
+        derivatives with respect to A and half_width (discrete adjoint of the
+        RK4 tracer).  Returns dict(loss, dA, dhw, image, sample_dm (n x 2
+        float64 tensor of dm/dA, dm/dhw per sample, or None), stats)."""
+        H, W, spp = camera["height"], camera["width"], camera["spp"]
+        ref = ref.to(self.device, torch.float32).contiguous()
+        img = out if out is not None else torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        sg = torch.empty((H * W * spp, 2), dtype=torch.float64, device=self.device) if sample_dm else None
+        sc, cam, op = make_scene(scene), make_camera(camera), make_opts(opts, prec)
+        kind = {"c0": GC_LOSS_C0, "ncc": GC_LOSS_NCC}[loss]
+        lv, dA, dhw = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = Stats()
+        _check(load().gc_render_grad(self._h, ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(op), ref.data_ptr(),
+                                     kind, int(checkpoint_every), img.data_ptr(),
+                                     sg.data_ptr() if sg is not None else None, ctypes.byref(lv), ctypes.byref(dA),
+                                     ctypes.byref(dhw), ctypes.byref(st), _stream_handle(stream)))
+        return dict(loss=lv.value, dA=dA.value, dhw=dhw.value, image=img, sample_dm=sg, stats=st.as_dict())
+
     def cross_correlate(self, img, ref, stream=None):
         """eq. (15) at zero shift and the Pearson form, from device images."""
         img = img.to(self.device, torch.float32).contiguous()
@@ -245,3 +273,35 @@ def render_batch(scenes, cameras, opts, refs=None, device=0):
 
 def cross_correlate(img, ref, device=0):
     return context(device).cross_correlate(img, ref)
+
+
+def render_grad(scene, camera, opts, ref, prec="f64", loss="ncc", checkpoint_every=64, device=0):
+    return context(device).render_grad(scene, camera, opts, ref, prec, loss, checkpoint_every)
+
+
+class CloakLoss(torch.autograd.Function):
+    """L(A, half_width) = 1 - NCC (or 1 - C0 of eq. (15)) between the image
+    of the cloak and a reference image, as a differentiable function of a
+    float64 tensor params = [A, half_width].  The forward call runs the
+    library's adjoint once; backward scales its two derivatives by the
+    incoming gradient."""
+
+    @staticmethod
+    def forward(fctx, params, scene, camera, opts, ref, prec="f64", loss="ncc", checkpoint_every=64, device=0):
+        p = params.detach().to("cpu", torch.float64)
+        sc = dict(scene, A=float(p[0]), half_width=float(p[1]))
+        r = context(device).render_grad(sc, camera, opts, ref, prec, loss, checkpoint_every)
+        fctx.save_for_backward(torch.tensor([r["dA"], r["dhw"]], dtype=torch.float64))
+        fctx.params_device = params.device
+        return torch.tensor(r["loss"], dtype=torch.float64, device=params.device)
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (g,) = fctx.saved_tensors
+        grad = (grad_out.detach().to("cpu", torch.float64) * g).to(fctx.params_device)
+        return grad, None, None, None, None, None, None, None, None
+
+
+def cloak_loss(params, scene, camera, opts, ref, prec="f64", loss="ncc", checkpoint_every=64, device=0):
+    """Differentiable cloaking-quality loss (see CloakLoss)."""
+    return CloakLoss.apply(params, scene, camera, opts, ref, prec, loss, checkpoint_every, device)

@@ -13,6 +13,7 @@
 #include "gcloak.h"
 #include "gc_lane64.hpp"
 #include "gc_wave.hpp"
+#include "gc_adjoint.hpp"
 
 using namespace gc;
 
@@ -244,6 +245,26 @@ struct WfStore {
     double hot_ms = 0.0, event_ms = 0.0, tail_ms = 0.0, total_ms = 0.0;
 };
 
+// Device buffers of the adjoint, grown on demand.
+struct AdjStore {
+    double* tape = nullptr;
+    size_t tape_bytes = 0;
+    void* seg = nullptr;
+    size_t seg_bytes = 0;
+    float* srgb = nullptr;
+    double* sgrad = nullptr;
+    long long* ovf = nullptr;
+    long long cap_samples = 0;
+    float* img = nullptr;
+    long long cap_pix = 0;
+    AdjCC* cs = nullptr;
+    unsigned long long* ctr = nullptr;   // claim (2 passes), overflow (2 passes), rays, steps, events, failed, bad
+    double* red = nullptr;
+    unsigned long long* h_ctr = nullptr; // pinned: ctr, then red and the correlation sums
+    int blocks[2] = {0, 0};              // resident blocks of k_adj<double>, k_adj<float>
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
 struct gc_ctx {
     int device;
     int n_cu;
@@ -251,6 +272,7 @@ struct gc_ctx {
     double* d_part;
     double* d_ccout;
     WfStore wf;
+    AdjStore adj;
 };
 
 static thread_local std::string g_err;
@@ -397,6 +419,203 @@ static gc_status read_counters(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
     st->hot_ms = st->event_ms = st->total_ms = st->tail_ms = 0.0;
     st->tail_rays = 0;
     st->hot_steps = 0;
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint orchestration.
+// ---------------------------------------------------------------------------
+constexpr int kAdjCap = 256;                          // tape slots per lane, first pass
+constexpr size_t kAdjTapeBudget = (size_t)4 << 30;    // bytes of tape per pass
+constexpr int kAdjMaxC = 256;
+// Counters of the adjoint (unsigned long long, device): claims of passes
+// 0..2, hand-overs of passes 0..2, then rays, steps, events, failed and
+// inconsistent tapes of the first pass.
+enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_N = 11 };
+// FP32 samples handed to the FP64 second pass: paths of more steps, or
+// colours more sensitive to the initial direction (per unit seed) than this
+constexpr long long kAdjRerunSteps = 20000;
+constexpr double kAdjRerunSens = 60.0;
+
+static gc_status grow(void** p, size_t* have, size_t need, const char* what)
+{
+    if (need <= *have) return GC_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(p, need) != hipSuccess) return fail(GC_ENOMEM, "%s (%zu bytes): allocation failed", what, need);
+    *have = need;
+    return GC_OK;
+}
+
+static gc_status adj_reserve(gc_ctx* ctx, long long n, long long npix)
+{
+    AdjStore& a = ctx->adj;
+    if (!a.ctr) {
+        if (hipMalloc((void**)&a.ctr, sizeof(unsigned long long) * AC_N) != hipSuccess ||
+            hipMalloc((void**)&a.red, sizeof(double) * 2) != hipSuccess ||
+            hipMalloc((void**)&a.cs, sizeof(AdjCC)) != hipSuccess ||
+            hipHostMalloc((void**)&a.h_ctr, sizeof(unsigned long long) * 24) != hipSuccess)
+            return fail(GC_ENOMEM, "adjoint counters: allocation failed");
+        int nb = 0;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj<double>, 256, 0));
+        a.blocks[0] = (nb > 0 ? nb : 1) * ctx->n_cu;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj<float>, 256, 0));
+        a.blocks[1] = (nb > 0 ? nb : 1) * ctx->n_cu;
+        for (hipEvent_t& e : a.ev) HIP_OK(hipEventCreate(&e));
+    }
+    if (n > a.cap_samples) {
+        if (a.srgb) (void)hipFree(a.srgb);
+        if (a.sgrad) (void)hipFree(a.sgrad);
+        if (a.ovf) (void)hipFree(a.ovf);
+        a.srgb = nullptr;
+        a.sgrad = nullptr;
+        a.ovf = nullptr;
+        a.cap_samples = 0;
+        if (hipMalloc((void**)&a.srgb, sizeof(float) * 3 * (size_t)n) != hipSuccess ||
+            hipMalloc((void**)&a.sgrad, sizeof(double) * 2 * (size_t)n) != hipSuccess ||
+            hipMalloc((void**)&a.ovf, sizeof(long long) * 2 * (size_t)n) != hipSuccess)
+            return fail(GC_ENOMEM, "adjoint sample buffers (%lld samples): allocation failed", n);
+        a.cap_samples = n;
+    }
+    if (npix > a.cap_pix) {
+        if (a.img) (void)hipFree(a.img);
+        a.img = nullptr;
+        a.cap_pix = 0;
+        if (hipMalloc((void**)&a.img, sizeof(float) * 3 * (size_t)npix) != hipSuccess)
+            return fail(GC_ENOMEM, "adjoint image: allocation failed");
+        a.cap_pix = npix;
+    }
+    return GC_OK;
+}
+
+// One pass of k_adj over n samples (list: indices, or null for all) with
+// tapes of `cap` slots; samples it cannot finish go to out_list (null: they
+// are only counted).  `rerun`: apply the FP32 hand-over criteria.
+template <typename T>
+static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const OptsDev& o, int C, long long n,
+                          const long long* list, long long* out_list, int cap, bool rerun, double* sgrad, int pass,
+                          hipStream_t stream)
+{
+    AdjStore& a = ctx->adj;
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    long long lanes = (long long)a.blocks[prec] * 256;
+    const long long by_budget = (long long)(kAdjTapeBudget / ((size_t)cap * kTapeFields * sizeof(double)));
+    lanes = std::min(lanes, by_budget);
+    lanes = std::min(lanes, (n + 255) / 256 * 256);
+    lanes = std::max(256LL, lanes / 256 * 256);
+    gc_status r;
+    if ((r = grow((void**)&a.tape, &a.tape_bytes, (size_t)lanes * cap * kTapeFields * sizeof(double), "adjoint tape")) !=
+        GC_OK)
+        return r;
+    if ((r = grow(&a.seg, &a.seg_bytes, (size_t)lanes * C * seg_fields<T>() * sizeof(T), "adjoint segment buffer")) != GC_OK)
+        return r;
+    AdjIo io;
+    io.n = n;
+    io.list = list;
+    io.claim = a.ctr + AC_CLAIM + pass;
+    io.tape = a.tape;
+    io.cap = cap;
+    io.seg = a.seg;
+    io.srgb = a.srgb;
+    io.sgrad = sgrad;
+    io.ovf = out_list;
+    io.n_ovf = a.ctr + AC_OVF + pass;
+    io.cnt = a.ctr + AC_CNT;
+    io.rerun_steps = rerun ? kAdjRerunSteps : (1LL << 62);
+    io.rerun_sens = rerun ? kAdjRerunSens : HUGE_VAL;
+    const T wfb2 = (T)o.wfb2;
+    hipLaunchKernelGGL(k_adj<T>, dim3((unsigned)(lanes / 256)), dim3(256), 0, stream, s, c, o, wfb2, C, io);
+    HIP_OK(hipGetLastError());
+    return GC_OK;
+}
+
+static gc_status adj_count(gc_ctx* ctx, int idx, long long* v, hipStream_t stream)
+{
+    HIP_OK(hipMemcpyAsync(ctx->adj.h_ctr, ctx->adj.ctr, sizeof(unsigned long long) * AC_N, hipMemcpyDeviceToHost,
+                          stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    *v = (long long)ctx->adj.h_ctr[idx];
+    return GC_OK;
+}
+
+// Passes: (0) all samples in precision T with tapes of kAdjCap slots; (1)
+// FP32 only: the samples handed over, in FP64 with the same tapes; (2) the
+// samples whose tape overflowed, in FP64 with tapes long enough for any
+// trace the options allow.
+template <typename T>
+static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const OptsDev& o, int C,
+                         const float* ref, int kind, float* img, double* sgrad, double out[3], gc_stats* st,
+                         hipStream_t stream)
+{
+    AdjStore& a = ctx->adj;
+    const long long npix = (long long)c.W * c.H, n = npix * c.spp;
+    long long* lst[2] = {a.ovf, a.ovf + a.cap_samples};
+    gc_status r;
+    HIP_OK(hipEventRecord(a.ev[0], stream));
+    const long long nbm = std::min<long long>(kCCBlocks, (npix + 255) / 256);
+    HIP_OK(hipMemsetAsync(a.ctr, 0, sizeof(unsigned long long) * AC_N, stream));
+    HIP_OK(hipGetLastError());
+    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, lst[0], kAdjCap, sizeof(T) == 4, sgrad, 0, stream)) != GC_OK)
+        return r;
+    HIP_OK(hipEventRecord(a.ev[1], stream));
+    long long n1 = 0, n2 = 0, handed = 0;
+    if ((r = adj_count(ctx, AC_OVF + 0, &n1, stream)) != GC_OK) return r;
+    handed = n1;
+    const long long* last = lst[0];
+    if (sizeof(T) == 4 && n1 > 0) {
+        if ((r = adj_pass<double>(ctx, s, c, o, C, n1, lst[0], lst[1], kAdjCap, false, sgrad, 1, stream)) != GC_OK)
+            return r;
+        if ((r = adj_count(ctx, AC_OVF + 1, &n1, stream)) != GC_OK) return r;
+        last = lst[1];
+    }
+    if (n1 > 0) {
+        // every record a trace can write: one per C steps, three per event
+        const long long cap2 = o.max_steps / C + 3LL * (o.max_events + 1) + 8;
+        if (cap2 > (1LL << 30)) return fail(GC_EUNSUPPORTED, "max_steps / checkpoint_every too large for the tape");
+        if ((r = adj_pass<double>(ctx, s, c, o, C, n1, last, nullptr, (int)cap2, false, sgrad, 2, stream)) != GC_OK)
+            return r;
+        n2 = n1;
+    }
+    HIP_OK(hipEventRecord(a.ev[2], stream));
+    hipLaunchKernelGGL(k_adj_image, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, a.srgb, npix, c.spp,
+                       img);
+    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nbm), dim3(256), 0, stream, img, ref, npix, 3, ctx->d_part);
+    hipLaunchKernelGGL(k_adj_ccstat, dim3(1), dim3(64), 0, stream, ctx->d_part, (int)nbm, npix, img, ref, a.cs);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(1024), 0, stream, sgrad, n, c.spp, img, ref, a.cs, kind, a.red);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(a.ev[3], stream));
+    HIP_OK(hipMemcpyAsync(a.h_ctr, a.ctr, sizeof(unsigned long long) * AC_N, hipMemcpyDeviceToHost, stream));
+    AdjCC hc;
+    HIP_OK(hipMemcpyAsync((double*)(a.h_ctr + 12), a.red, sizeof(double) * 2, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(&hc, a.cs, sizeof hc, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    if (a.h_ctr[AC_OVF + 2] != 0)
+        return fail(GC_EDEVICE, "adjoint: %llu samples overflowed the full-length tape", a.h_ctr[AC_OVF + 2]);
+    if (a.h_ctr[AC_CNT + 4] != 0)
+        return fail(GC_EDEVICE, "adjoint: %llu samples with an inconsistent tape", a.h_ctr[AC_CNT + 4]);
+    const double* hd = (const double*)(a.h_ctr + 12);
+    if (!(hc.sff > 0)) return fail(GC_EINVAL, "reference image is constant: eq. (15) is undefined");
+    if (kind == 1 && !(hc.sgg > 0)) return fail(GC_EINVAL, "rendered image is constant: NCC is undefined");
+    out[0] = 1.0 - (kind == 0 ? hc.c0 : hc.ncc);
+    out[1] = hd[0];          // dL/dA
+    out[2] = hd[1];          // dL/dhw
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->rays = (int64_t)a.h_ctr[AC_CNT + 0];
+        st->accepted_steps = (int64_t)a.h_ctr[AC_CNT + 1];
+        st->events = (int64_t)a.h_ctr[AC_CNT + 2];
+        st->failed = (int64_t)a.h_ctr[AC_CNT + 3];
+        st->tail_rays = handed;
+        st->rounds = n2;
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, a.ev[0], a.ev[1]));
+        st->hot_ms = ms;
+        HIP_OK(hipEventElapsedTime(&ms, a.ev[1], a.ev[2]));
+        st->tail_ms = ms;
+        HIP_OK(hipEventElapsedTime(&ms, a.ev[0], a.ev[3]));
+        st->total_ms = ms;
+    }
     return GC_OK;
 }
 
@@ -732,6 +951,15 @@ void gc_destroy(gc_ctx* c)
     if (c->wf.ctr) (void)hipFree(c->wf.ctr);
     if (c->wf.tot) (void)hipFree(c->wf.tot);
     if (c->wf.h_ctr) (void)hipHostFree(c->wf.h_ctr);
+    for (hipEvent_t e : c->wf.ev)
+        if (e) (void)hipEventDestroy(e);
+    AdjStore& a = c->adj;
+    void* bufs[] = {a.tape, a.seg, a.srgb, a.sgrad, a.ovf, a.img, a.cs, a.ctr, a.red};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (a.h_ctr) (void)hipHostFree(a.h_ctr);
+    for (hipEvent_t e : a.ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -819,6 +1047,43 @@ gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes,
             if (r != GC_OK) return r;
         }
     }
+    return GC_OK;
+}
+
+gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
+                         const float* d_ref, int32_t loss_kind, int32_t checkpoint_every, float* d_rgb,
+                         double* d_sample_dm, double* loss, double* dL_dA, double* dL_dhw, gc_stats* st,
+                         hipStream_t stream)
+{
+    if (!ctx) return fail(GC_EINVAL, "ctx is null");
+    SceneDev s;
+    CamDev c;
+    OptsDev o;
+    gc_status r;
+    if ((r = make_scene(scene, &s)) != GC_OK) return r;
+    if ((r = make_camera(camera, &c)) != GC_OK) return r;
+    if ((r = make_opts(opts, &o)) != GC_OK) return r;
+    if (scene->mirror == 1) return fail(GC_EUNSUPPORTED, "the flat-mirror reference does not depend on A or half_width");
+    if (opts->integ != GC_RK4) return fail(GC_EUNSUPPORTED, "the adjoint differentiates the RK4 tracer (integ = GC_RK4)");
+    if (!std::isfinite(scene->sky_K)) return fail(GC_EUNSUPPORTED, "sky_K = inf has no gradient");
+    if (!d_ref) return fail(GC_EINVAL, "ref is null");
+    if (loss_kind != GC_LOSS_C0 && loss_kind != GC_LOSS_NCC) return fail(GC_EINVAL, "unknown loss_kind %d", loss_kind);
+    if (checkpoint_every < 1 || checkpoint_every > kAdjMaxC)
+        return fail(GC_EINVAL, "checkpoint_every must be in [1, %d]", kAdjMaxC);
+    HIP_OK(hipSetDevice(ctx->device));
+    const long long npix = (long long)c.W * c.H, n = npix * c.spp;
+    if ((r = adj_reserve(ctx, n, npix)) != GC_OK) return r;
+    float* img = d_rgb ? d_rgb : ctx->adj.img;
+    double* sgrad = d_sample_dm ? d_sample_dm : ctx->adj.sgrad;
+    double out[3];
+    if (opts->prec == GC_F64)
+        r = adj_run<double>(ctx, s, c, o, checkpoint_every, d_ref, loss_kind, img, sgrad, out, st, stream);
+    else
+        r = adj_run<float>(ctx, s, c, o, checkpoint_every, d_ref, loss_kind, img, sgrad, out, st, stream);
+    if (r != GC_OK) return r;
+    if (loss) *loss = out[0];
+    if (dL_dA) *dL_dA = out[1];
+    if (dL_dhw) *dL_dhw = out[2];
     return GC_OK;
 }
 

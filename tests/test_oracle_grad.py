@@ -114,25 +114,25 @@ def test_halfwidth_tangent_exactly_zero_without_side_faces():
     assert np.abs(t["d_A"]).max() > 0.0
 
 
-def test_loss_gradient_chain_rule_through_eq15():
-    """dL/dtheta = -sum f' dg/dtheta / sum f'^2: checked against central
-    differences of the oracle's own eq. (15) routine along the image
-    tangent (eq. (15) is linear in g, so the difference is exact up to
-    rounding)."""
+@pytest.mark.parametrize("loss", ["c0", "ncc"])
+def test_loss_gradient_chain_rule_through_eq15(loss):
+    """dL/dtheta = sum dL/dg dg/dtheta with the weights of loss_weights:
+    checked against central differences of the oracle's own correlation
+    routine (eq. (15) and its Pearson form, in C) along the image tangent."""
     sc, cam, op = W.grad_256()
     c = dict(cam, width=10, height=8, spp=2)
     ref, _ = O.render(W.reference_scene(sc), c, op)
-    g = O.render_grad(sc, c, op, ref)
+    g = O.render_grad(sc, c, op, ref, loss=loss)
     t = g["tan"]
+    k = 0 if loss == "c0" else 1
     for key, name in (("dA", "d_A"), ("dhw", "d_hw")):
         gt = t[name].mean(axis=1).reshape(8, 10, 3)
-        eps = 1e-3 / max(1.0, np.abs(gt).max())
-        cp, _ = O.cross_correlate(ref, g["image"] + eps * gt)
-        cm, _ = O.cross_correlate(ref, g["image"] - eps * gt)
+        eps = 1e-4 / max(1.0, np.abs(gt).max())
+        cp = O.cross_correlate(ref, g["image"] + eps * gt)[k]
+        cm = O.cross_correlate(ref, g["image"] - eps * gt)[k]
         fd = -(cp - cm) / (2 * eps)
-        assert abs(fd - g[key]) <= 1e-9 * max(1.0, abs(g[key]))
-    c0, _ = O.cross_correlate(ref, g["image"])
-    assert g["loss"] == pytest.approx(1.0 - c0, abs=1e-15)
+        assert abs(fd - g[key]) <= 1e-8 * max(1.0, abs(g[key]))
+    assert g["loss"] == pytest.approx(1.0 - O.cross_correlate(ref, g["image"])[k], abs=1e-15)
     # the colours of the tangent tracer are the oracle render's
     img, _ = O.render(sc, c, op)
     assert np.abs(img - g["image"]).max() < 1e-9
