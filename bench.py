@@ -6,6 +6,10 @@ Workloads (--workload):
   batch   64 scenes of uneven resolution (256^2 .. 1024^2), amplitude, cloak
           width and viewpoint, 4 spp, rendered in one FP32 pipeline launch
   stress  1024 x 1024, 8 spp, A = 0.15 (A k = 0.94), grazing camera
+  grad    256 x 256, 4 spp, A = 0.08, half-width 3, RK4 h = 1e-3: loss
+          1 - NCC against the flat-mirror reference and its derivatives with
+          respect to A and half-width by the adjoint (FP32, FP64 hand-over),
+          checkpoints every 64 steps
 
 One step = render the cloaked image(s) (FP32 path), render the flat-mirror
 reference(s) and correlate them (eqs. (14)-(15)).  Inputs are synthetic and
@@ -30,6 +34,10 @@ PEAK_FP64 = 78.6e12    # MI355X vector FP64, FLOP/s
 # evaluations with their complex Lambert-W update, the 7-stage combinations
 # and the error norm), in FLOP with FMA = 2
 FLOP_PER_STEP = {"dopri5": 680.0, "rk4": 354.0}
+# adjoint: a reversed RK4 step is recomputed (354) and its transposed
+# Jacobian applied: four stage Jacobians of the field (~113 FLOP each from
+# W), the stage rebuild (~33) and the adjoint combinations (~30)
+FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 
 
 def parse():
@@ -41,7 +49,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--workload", choices=["single", "batch", "stress"], default="single")
+    p.add_argument("--workload", choices=["single", "batch", "stress", "grad"], default="single")
     return p.parse_args()
 
 
@@ -54,6 +62,8 @@ def main():
         return main_batch(args)
     if args.workload == "stress":
         return main_stress(args)
+    if args.workload == "grad":
+        return main_grad(args)
     import numpy as np
     import torch
     from paper_1012_5107_amd import binding as B
@@ -301,6 +311,92 @@ def main_stress(args):
                       "rtol_fp32": op32["rtol"], "rays": st["rays"], "ray_steps": st["accepted_steps"]},
            "rays_per_s": st["rays"] / dt, "cc_fp32": c32, "fp32_counters": stk}
     print(json.dumps(out), flush=True)
+
+
+def main_grad(args):
+    import numpy as np
+    import torch
+    from paper_1012_5107_amd import binding as B
+    from paper_1012_5107_amd import workloads as W
+
+    sc, cam, op = W.grad_256()
+    ctx = B.context(0)
+    ref, _ = ctx.render(W.reference_scene(sc), cam, op)
+    r0 = ctx.render_grad(sc, cam, op, ref, prec="f32", loss="ncc")
+    print(f"# grad pass: {r0['stats']}", file=sys.stderr, flush=True)
+
+    def step():
+        ctx.render(W.reference_scene(sc), cam, op, out=ref, stats=False)
+        return ctx.render_grad(sc, cam, op, ref, prec="f32", loss="ncc")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = r["stats"]
+    fwd, rev = st["accepted_steps"], st["hot_steps"]
+    achieved = (fwd * FLOP_PER_STEP["rk4"] + rev * FLOP_PER_REVERSED_STEP) / (st["hot_ms"] * 1e-3)
+    out = {
+        "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
+        "value": fwd / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gradient: 256x256, 4 jittered spp (seed 3), Lambda=1, A=0.08, cloak |x|<=3, "
+                               "y<=1.5, RK4 h=1e-3, loss 1-NCC, adjoint with checkpoints every 64 steps",
+                   "rays": st["rays"], "ray_steps": fwd},
+        "rays_per_s": st["rays"] / dt,
+        "loss": r["loss"], "dL_dA": r["dA"], "dL_dhw": r["dhw"],
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_adj<float>",
+                     "kernel_ms": st["hot_ms"], "forward_steps": fwd, "reversed_steps": rev},
+        "adjoint_breakdown": {"fp32_pass_ms": st["hot_ms"], "fp64_passes_ms": st["tail_ms"],
+                              "total_ms": st["total_ms"], "fp64_samples": st["tail_rays"],
+                              "long_tape_samples": st["rounds"], "failed": st["failed"]},
+    }
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = ctx.render_grad(sc, cam, op, ref, prec="f64", loss="ncc")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        out["fp64_adjoint"] = {"ms": t64 * 1e3, "ray_steps_per_s": r64["stats"]["accepted_steps"] / t64,
+                               "loss": r64["loss"], "dL_dA": r64["dA"], "dL_dhw": r64["dhw"]}
+        out["loss_error_fp32_vs_fp64"] = abs(r["loss"] - r64["loss"])
+        out["grad_rel_error_fp32_vs_fp64"] = {
+            "dA": abs(r["dA"] - r64["dA"]) / max(abs(r64["dA"]), 1e-300),
+            "dhw": abs(r["dhw"] - r64["dhw"]) / max(abs(r64["dhw"]), 1e-300)}
+        out["speedup_fp32_vs_fp64"] = t64 / dt
+    if not args.no_cpu:
+        from oracle import oracle as O
+        out["cpu_baseline"] = _cpu_tangent_baseline(O, sc, cam, op, W, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_tangent_baseline(O, sc, cam, op, W, seconds):
+    """The oracle's forward-mode gradient (tangent tracer) on a growing
+    sample of pixels until it takes about `seconds`."""
+    H, Wd = cam["height"], cam["width"]
+    npix = 16
+    while True:
+        pix = W.sample_pixels(Wd, H, npix, seed=11)
+        t2 = time.perf_counter()
+        t = O.render_samples_tan(sc, cam, op, pixels=pix)
+        tc = time.perf_counter() - t2
+        if tc > seconds / 4 or npix >= Wd * H:
+            break
+        npix = min(Wd * H, int(npix * max(2.0, min(8.0, seconds / max(tc, 1e-3)))))
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count()
+    rays = t["status"].size
+    return {"value": rays / tc, "unit": "rays/s (value and gradient)", "cores": threads, "kind": "oracle",
+            "sample": f"{npix} seeded pixels x {cam['spp']} spp of the gradient workload, forward-mode tangents "
+                      f"(FP64), {rays} rays in {tc:.1f} s"}
 
 
 if __name__ == "__main__":

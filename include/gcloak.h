@@ -218,11 +218,13 @@ typedef enum {
  * spp pairs of doubles, sample s of pixel (i, j) at ((j width + i) spp + s);
  * zero for failed samples); loss / dL_dA / dL_dhw (host) the results; st
  * the forward counters (rays, accepted_steps, events, failed; tail_rays =
- * samples differentiated again in FP64 -- FP32 hand-overs and tapes longer
- * than 256 records; rounds = samples that needed a tape for the longest
- * trace the options allow; hot_ms / tail_ms / total_ms the device time of
- * the first pass, of the FP64 passes and of the call).  Device scratch
- * (tapes of up to 4 GiB) is owned by the context.  Synchronises the
+ * samples differentiated again in FP64 with tapes long enough for any
+ * trace the options allow -- tapes longer than 256 records, and in FP32 the
+ * long or sensitive traces; rounds = those of more than 8000 steps, which
+ * start first; hot_steps = steps reversed by the first pass;
+ * hot_ms / tail_ms / total_ms the device time of the first pass, of the
+ * FP64 passes and of the call).  Device scratch
+ * (tapes of up to 8 GiB) is owned by the context.  Synchronises the
  * stream.  GC_EUNSUPPORTED for DOPRI5, flat-mirror scenes or sky_K = inf;
  * GC_EINVAL for a constant reference (or, for NCC, a constant image). */
 gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,

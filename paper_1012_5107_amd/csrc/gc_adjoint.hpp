@@ -792,9 +792,11 @@ struct AdjIo {
     void* seg;                    // segment buffer, C x 12 values of T per lane
     float* srgb;                  // per-sample colour (first pass)
     double* sgrad;                // per-sample dm/dA, dm/dhw
-    long long* ovf;               // first pass: samples whose tape overflowed; second pass: null
-    unsigned long long* n_ovf;    // number of overflowing samples
-    unsigned long long* cnt;      // rays, steps, events, failed, inconsistent tapes
+    long long* ovf;               // first pass: samples handed to the second; second pass: null
+    long long ovf_cap;            // entries of ovf
+    unsigned long long* n_ovf;    // first pass: hand-overs at the front / back of ovf; second: overflows
+    long long long_steps;         // hand-overs of more steps go to the front
+    unsigned long long* cnt;      // rays, steps, events, failed, inconsistent tapes, steps reversed (first pass)
     // first FP32 pass: samples whose gradient is recomputed in FP64 -- paths
     // longer than rerun_steps, or whose sky parameter m is more sensitive to
     // the initial direction than rerun_sens per radian (FP32 rounding would
@@ -820,7 +822,7 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
     const AdjTape tp = {io.tape, stride, lane, io.cap};
     const AdjSeg<T> sg = {(T*)io.seg, stride, lane};
     const int wl = threadIdx.x & 63;
-    unsigned long long c_rays = 0, c_steps = 0, c_ev = 0, c_fail = 0;
+    unsigned long long c_rays = 0, c_steps = 0, c_ev = 0, c_fail = 0, c_rev = 0;
     for (;;) {
         unsigned long long base = 0;
         if (wl == 0) base = atomicAdd(io.claim, 64ull);
@@ -856,6 +858,7 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
                 int bad = 0;
                 double sens = 0.0;
                 adj_reverse<T>(s, o, wfb2, C, tp, nrec, sg, od, 1.0, gA, ghw, bad, sens);
+                if (!io.list) c_rev += (unsigned long long)steps;
                 if (bad) {
                     atomicAdd(&io.cnt[4], 1ull);
                     gA = ghw = 0.0;
@@ -863,13 +866,21 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
                 hand_over = sens > io.rerun_sens;
             }
             if (hand_over) {
-                // the first pass hands the sample to the second (FP64, long
-                // tapes); the second pass only counts a tape overflow
-                const unsigned long long k = atomicAdd(io.n_ovf, 1ull);
+                // the first pass hands the sample to the second (FP64,
+                // full-length tapes): long traces from the front of the list,
+                // so that they start first, the others from its back; the
+                // second pass only counts a tape overflow (it cannot happen)
                 if (io.ovf) {
-                    io.ovf[k] = sidx;
+                    if (steps > io.long_steps) {
+                        const unsigned long long k = atomicAdd(io.n_ovf, 1ull);
+                        io.ovf[k] = sidx;
+                    } else {
+                        const unsigned long long k = atomicAdd(io.n_ovf + 1, 1ull);
+                        io.ovf[io.ovf_cap - 1 - (long long)k] = sidx;
+                    }
                     continue;
                 }
+                atomicAdd(io.n_ovf, 1ull);
                 gA = ghw = 0.0;
             }
         }
@@ -880,11 +891,13 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
     c_steps = adj_wave_sum(c_steps);
     c_ev = adj_wave_sum(c_ev);
     c_fail = adj_wave_sum(c_fail);
+    c_rev = adj_wave_sum(c_rev);
     if (wl == 0) {
         atomicAdd(&io.cnt[0], c_rays);
         atomicAdd(&io.cnt[1], c_steps);
         atomicAdd(&io.cnt[2], c_ev);
         atomicAdd(&io.cnt[3], c_fail);
+        atomicAdd(&io.cnt[5], c_rev);
     }
 }
 

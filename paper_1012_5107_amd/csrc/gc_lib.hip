@@ -426,15 +426,18 @@ static gc_status read_counters(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
 // Adjoint orchestration.
 // ---------------------------------------------------------------------------
 constexpr int kAdjCap = 256;                          // tape slots per lane, first pass
-constexpr size_t kAdjTapeBudget = (size_t)4 << 30;    // bytes of tape per pass
+constexpr size_t kAdjTapeBudget = (size_t)8 << 30;    // bytes of tape per pass
 constexpr int kAdjMaxC = 256;
-// Counters of the adjoint (unsigned long long, device): claims of passes
-// 0..2, hand-overs of passes 0..2, then rays, steps, events, failed and
-// inconsistent tapes of the first pass.
-enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_N = 11 };
+// Counters of the adjoint (unsigned long long, device): claims of the two
+// passes, hand-overs of the first pass (front, back of the list), overflows
+// of the second, then rays, steps, events, failed, inconsistent tapes and
+// steps reversed in the first pass.
+enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_N = 12 };
 // FP32 samples handed to the FP64 second pass: paths of more steps, or
 // colours more sensitive to the initial direction (per unit seed) than this
 constexpr long long kAdjRerunSteps = 20000;
+// hand-overs of more steps than this are queued first in the second pass
+constexpr long long kAdjLongSteps = 8000;
 constexpr double kAdjRerunSens = 60.0;
 
 static gc_status grow(void** p, size_t* have, size_t need, const char* what)
@@ -474,7 +477,7 @@ static gc_status adj_reserve(gc_ctx* ctx, long long n, long long npix)
         a.cap_samples = 0;
         if (hipMalloc((void**)&a.srgb, sizeof(float) * 3 * (size_t)n) != hipSuccess ||
             hipMalloc((void**)&a.sgrad, sizeof(double) * 2 * (size_t)n) != hipSuccess ||
-            hipMalloc((void**)&a.ovf, sizeof(long long) * 2 * (size_t)n) != hipSuccess)
+            hipMalloc((void**)&a.ovf, sizeof(long long) * (size_t)n) != hipSuccess)
             return fail(GC_ENOMEM, "adjoint sample buffers (%lld samples): allocation failed", n);
         a.cap_samples = n;
     }
@@ -520,7 +523,9 @@ static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const
     io.srgb = a.srgb;
     io.sgrad = sgrad;
     io.ovf = out_list;
-    io.n_ovf = a.ctr + AC_OVF + pass;
+    io.ovf_cap = a.cap_samples;
+    io.n_ovf = a.ctr + AC_OVF + 2 * pass;
+    io.long_steps = kAdjLongSteps;
     io.cnt = a.ctr + AC_CNT;
     io.rerun_steps = rerun ? kAdjRerunSteps : (1LL << 62);
     io.rerun_sens = rerun ? kAdjRerunSens : HUGE_VAL;
@@ -530,19 +535,10 @@ static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const
     return GC_OK;
 }
 
-static gc_status adj_count(gc_ctx* ctx, int idx, long long* v, hipStream_t stream)
-{
-    HIP_OK(hipMemcpyAsync(ctx->adj.h_ctr, ctx->adj.ctr, sizeof(unsigned long long) * AC_N, hipMemcpyDeviceToHost,
-                          stream));
-    HIP_OK(hipStreamSynchronize(stream));
-    *v = (long long)ctx->adj.h_ctr[idx];
-    return GC_OK;
-}
-
-// Passes: (0) all samples in precision T with tapes of kAdjCap slots; (1)
-// FP32 only: the samples handed over, in FP64 with the same tapes; (2) the
-// samples whose tape overflowed, in FP64 with tapes long enough for any
-// trace the options allow.
+// Two passes: (0) all samples in precision T with tapes of kAdjCap slots;
+// (1) the samples it handed over -- tapes too short, and in FP32 the long
+// or sensitive traces -- in FP64 with tapes long enough for any trace the
+// options allow, the longest traces first.
 template <typename T>
 static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const OptsDev& o, int C,
                          const float* ref, int kind, float* img, double* sgrad, double out[3], gc_stats* st,
@@ -550,32 +546,28 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
 {
     AdjStore& a = ctx->adj;
     const long long npix = (long long)c.W * c.H, n = npix * c.spp;
-    long long* lst[2] = {a.ovf, a.ovf + a.cap_samples};
     gc_status r;
     HIP_OK(hipEventRecord(a.ev[0], stream));
     const long long nbm = std::min<long long>(kCCBlocks, (npix + 255) / 256);
     HIP_OK(hipMemsetAsync(a.ctr, 0, sizeof(unsigned long long) * AC_N, stream));
-    HIP_OK(hipGetLastError());
-    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, lst[0], kAdjCap, sizeof(T) == 4, sgrad, 0, stream)) != GC_OK)
+    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, a.ovf, kAdjCap, sizeof(T) == 4, sgrad, 0, stream)) != GC_OK)
         return r;
     HIP_OK(hipEventRecord(a.ev[1], stream));
-    long long n1 = 0, n2 = 0, handed = 0;
-    if ((r = adj_count(ctx, AC_OVF + 0, &n1, stream)) != GC_OK) return r;
-    handed = n1;
-    const long long* last = lst[0];
-    if (sizeof(T) == 4 && n1 > 0) {
-        if ((r = adj_pass<double>(ctx, s, c, o, C, n1, lst[0], lst[1], kAdjCap, false, sgrad, 1, stream)) != GC_OK)
-            return r;
-        if ((r = adj_count(ctx, AC_OVF + 1, &n1, stream)) != GC_OK) return r;
-        last = lst[1];
-    }
-    if (n1 > 0) {
+    HIP_OK(hipMemcpyAsync(a.h_ctr, a.ctr, sizeof(unsigned long long) * AC_N, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    const long long n_front = (long long)a.h_ctr[AC_OVF + 0], n_back = (long long)a.h_ctr[AC_OVF + 1];
+    const long long handed = n_front + n_back;
+    if (handed > 0) {
+        // make the list contiguous: the back part follows the front part
+        if (n_back > 0 && a.cap_samples - n_back != n_front)
+            HIP_OK(hipMemcpyAsync(a.ovf + n_front, a.ovf + (a.cap_samples - n_back), sizeof(long long) * n_back,
+                                  hipMemcpyDeviceToDevice, stream));
         // every record a trace can write: one per C steps, three per event
         const long long cap2 = o.max_steps / C + 3LL * (o.max_events + 1) + 8;
         if (cap2 > (1LL << 30)) return fail(GC_EUNSUPPORTED, "max_steps / checkpoint_every too large for the tape");
-        if ((r = adj_pass<double>(ctx, s, c, o, C, n1, last, nullptr, (int)cap2, false, sgrad, 2, stream)) != GC_OK)
+        if ((r = adj_pass<double>(ctx, s, c, o, C, handed, a.ovf, nullptr, (int)cap2, false, sgrad, 1, stream)) !=
+            GC_OK)
             return r;
-        n2 = n1;
     }
     HIP_OK(hipEventRecord(a.ev[2], stream));
     hipLaunchKernelGGL(k_adj_image, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, a.srgb, npix, c.spp,
@@ -607,7 +599,8 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
         st->events = (int64_t)a.h_ctr[AC_CNT + 2];
         st->failed = (int64_t)a.h_ctr[AC_CNT + 3];
         st->tail_rays = handed;
-        st->rounds = n2;
+        st->rounds = n_front;
+        st->hot_steps = (int64_t)a.h_ctr[AC_CNT + 5];
         float ms = 0.0f;
         HIP_OK(hipEventElapsedTime(&ms, a.ev[0], a.ev[1]));
         st->hot_ms = ms;
