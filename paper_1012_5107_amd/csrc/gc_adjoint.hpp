@@ -356,36 +356,62 @@ __device__ inline void rk4_vjp(const SceneDev& s, const AS<T>& u, const cx<T> Ws
 // Event functions inside the cloak (>= 0 inside): 0 top, 1 right, 2 left,
 // 3 grating (virtual coordinate v = y + Re W / k, zero on the trochoid).
 // ---------------------------------------------------------------------------
+// (evaluated with the low parts of the FP32 state, so that the faces are
+// exact to rounding of the difference itself)
 template <typename T>
 __device__ __forceinline__ T adj_event(const SceneDev& s, int ev, const AS<T>& u)
 {
     switch (ev) {
-    case 0: return (T)s.ytop - u.y;
-    case 1: return (T)s.hw - u.x;
-    case 2: return (T)s.hw + u.x;
-    default: return u.y + u.W.re * (T)(1.0 / s.k);
+    case 0: return ((T)s.ytop - u.y) - u.yl;
+    case 1: return ((T)s.hw - u.x) - u.xl;
+    case 2: return ((T)s.hw + u.x) + u.xl;
+    default: return (u.y + u.W.re * (T)(1.0 / s.k)) + u.yl;
+    }
+}
+
+// Rounding level of event ev: in FP64 the coordinates themselves (as large
+// as y_top or half_width) set it; in FP32 the faces are differences of an
+// exact constant and a compensated coordinate, and the grating carries the
+// FP32 error of W.
+template <typename T>
+__device__ __forceinline__ T adj_event_noise(const SceneDev& s, int ev)
+{
+    if constexpr (sizeof(T) == 8) {
+        return (T)(4.0 * 1.1102230246251565e-16 *
+                   (1.0 + (isfinite(s.ytop) ? fabs(s.ytop) : 0.0) + (isfinite(s.hw) ? fabs(s.hw) : 0.0)));
+    } else {
+        return ev == 3 ? (T)(4.0 * 5.9604645e-8) : (T)0;
     }
 }
 
 // Smallest theta in (0, 1] at which event ev of the partial step Phi(u,
 // theta h) reaches zero (f0 >= 0 at the start, f1 < 0 at the full step):
-// regula falsi with the Illinois modification on the bracket, closed to
-// tol by a trial placed just across the converged root.  Returns the upper
-// end of the bracket (e < 0 there) and its state in uh.
+// regula falsi with the Illinois modification on the bracket.  It ends when
+// the bracket is `tol` wide or when its upper end is on the surface to
+// rounding (-noise <= e < 0; the event functions are differences of
+// coordinates as large as y_top or half_width); a trial on the surface to
+// rounding from the inside is followed by one just across it.  Returns the
+// upper end of the bracket (e < 0 there) and its state in uh.
 template <typename T>
 __device__ __noinline__ T adj_locate(const SceneDev& s, T wfb2, int ev, const AS<T>& u, T h, T f0, T f1,
                                      const AS<T>& u_end, AS<T>& uh)
 {
     const T tol = sizeof(T) == 8 ? (T)1e-14 : (T)2e-7;
+    const T noise = adj_event_noise<T>(s, ev);
     T lo = (T)0, hi = (T)1, flo = f0, fhi = f1;
     uh = u_end;
     int side = 0;
     T x = (T)1;
     for (int it = 0; it < 100 && hi - lo > tol; ++it) {
-        T t = (flo - fhi > (T)0) ? (flo * hi - fhi * lo) / (flo - fhi) : (T)0.5 * (lo + hi);
+        T t;
+        if (side > 0 && flo <= noise && noise > (T)0) {
+            // the last trial (lo) is on the surface to rounding: step across
+            const T sl = (fhi - flo) / (hi - lo);
+            t = lo + fmax((T)2 * noise / fabs(sl), tol);
+        } else {
+            t = (flo - fhi > (T)0) ? (flo * hi - fhi * lo) / (flo - fhi) : (T)0.5 * (lo + hi);
+        }
         if (it >= 40 || !(t > lo && t < hi)) t = (T)0.5 * (lo + hi);
-        if (fabs(t - x) < (T)0.5 * tol) t = (side < 0) ? fmax(hi - (T)0.9 * tol, (T)0.5 * (lo + hi))
-                                                         : fmin(lo + (T)0.9 * tol, (T)0.5 * (lo + hi));
         AS<T> ut;
         adj_rk4<T>(s, wfb2, u, t * h, ut, nullptr);
         const T ft = adj_event<T>(s, ev, ut);
@@ -393,6 +419,7 @@ __device__ __noinline__ T adj_locate(const SceneDev& s, T wfb2, int ev, const AS
             hi = t;
             fhi = ft;
             uh = ut;
+            if (ft >= -noise) break;
             if (side < 0) flo *= (T)0.5;
             side = -1;
         } else {
@@ -403,6 +430,7 @@ __device__ __noinline__ T adj_locate(const SceneDev& s, T wfb2, int ev, const AS
         }
         x = t;
     }
+    (void)x;
     return hi;
 }
 

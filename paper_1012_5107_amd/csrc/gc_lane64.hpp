@@ -376,39 +376,56 @@ __device__ inline double hermite_root(double f0, double f1, double m0, double m1
     return t;
 }
 
+// Rounding level of the event functions: they are differences of
+// coordinates as large as y_top or half_width, so values within a few ulps
+// of those are zero to working precision.
+__device__ inline double event_noise64(const SceneDev& s)
+{
+    const double scale = 1.0 + (isfinite(s.ytop) ? fabs(s.ytop) : 0.0) + (isfinite(s.hw) ? fabs(s.hw) : 0.0);
+    return 4.0 * 1.1102230246251565e-16 * scale;
+}
+
 // Smallest theta in (0, 1] at which event `ev` of the partial step Phi(theta h)
 // crosses zero.  f0 / f1: event values at the step start / full-step end
 // (f1 < 0), rates d0 / d1 their tau-derivatives.  The first trial is the
-// root of the cubic Hermite interpolant; then a secant iteration safeguarded
-// by the bracket [lo, hi] (e >= 0 at lo, e < 0 at hi), which is closed to
-// 1e-14 by a last trial placed just across the converged root.  Returns hi.
+// root of the cubic Hermite interpolant; then Newton / secant steps
+// safeguarded by the bracket [lo, hi] (e >= 0 at lo, e < 0 at hi).  It ends
+// when the bracket is 1e-14 wide or when the upper end is on the surface to
+// rounding (-noise <= e < 0); a trial that lands on the surface to rounding
+// from the inside is followed by one placed just across it.  Returns hi.
 __device__ inline double locate_event(const SceneDev& s, const OptsDev& o, int ev, const St64& u,
                                       const Rhs64& r1, double h, double f0, double f1, double d0, double d1,
                                       const St64& u_end, const Rhs64& r_end, St64& u_hi, Rhs64& r_hi)
 {
     u_hi = u_end;
     r_hi = r_end;
+    const double fnoise = event_noise64(s);
     double lo = 0.0, hi = 1.0;
     double slope = 0.0;
     double x = hermite_root(fmax(f0, 0.0), f1, h * d0, h * d1, &slope);
-    double fx = 0.0, xprev = -1.0, fprev = 0.0;
+    double xprev = -1.0, fprev = 0.0;
     for (int it = 0; it < 60; ++it) {
         St64 ue;
         Rhs64 re;
         partial_step64(s, o, u, r1, x * h, ue, re);
-        fx = event_fn(s, ev, ue, re);
-        if (fx < 0.0) { hi = x; u_hi = ue; r_hi = re; } else lo = x;
-        if (hi - lo <= 1e-14) break;
-        double t;
-        if (xprev < 0.0) {
-            t = (slope != 0.0) ? x - fx / slope : 0.5 * (lo + hi);
-        } else if (fx != fprev) {
-            t = x - fx * (x - xprev) / (fx - fprev);
+        const double fx = event_fn(s, ev, ue, re);
+        if (fx < 0.0) {
+            hi = x;
+            u_hi = ue;
+            r_hi = re;
+            if (fx >= -fnoise) break;
         } else {
-            t = 0.5 * (lo + hi);
+            lo = x;
         }
+        if (hi - lo <= 1e-14) break;
+        double sl = slope;
+        if (xprev >= 0.0 && x != xprev && fx != fprev) sl = (fx - fprev) / (x - xprev);
+        double t;
+        if (fx >= 0.0 && fx <= fnoise && sl != 0.0)
+            t = x + fmax(2.0 * fnoise / fabs(sl), 1e-14);
+        else
+            t = (sl != 0.0) ? x - fx / sl : 0.5 * (lo + hi);
         if (it >= 20 || !(t > lo && t < hi)) t = 0.5 * (lo + hi);
-        if (fabs(t - x) < 0.5e-14) t = (fx < 0.0) ? fmax(hi - 0.9e-14, 0.5 * (lo + hi)) : fmin(lo + 0.9e-14, 0.5 * (lo + hi));
         xprev = x;
         fprev = fx;
         x = t;
