@@ -11,8 +11,7 @@
 // loses digits there), or an evaluation path that crosses the branch cut
 // (a crest line x = N Lambda below the branch-point height, where a warm
 // start could land on another branch) -- only raises a flag; the caller then
-// hands the whole step to the FP64 event path, as it does for face and
-// grating crossings.
+// hands the whole step to the FP64 path.
 #pragma once
 #include "gc_math.hpp"
 
@@ -85,7 +84,7 @@ __device__ __forceinline__ float accel32(const Sc32& c, Rhs32& r)
 // RHS at offset fx and height y, warm-started from the evaluation `prev`
 // taken at (xp, yp) (offsets in the same period): predictor, NITER Halley
 // steps (0: iterate until the update is below FP32 resolution), acceleration.
-// Sets `bad` when the point needs the FP64 path.
+// Sets `bad` when the point needs FP64.
 template <int NITER>
 __device__ __forceinline__ void eval32(const Sc32& c, float fx, float y, float xp, float yp, const Rhs32& prev,
                                        Rhs32& r, bool& bad)
@@ -102,17 +101,11 @@ __device__ __forceinline__ void eval32(const Sc32& c, float fx, float y, float x
         float d2 = halley32(c, fx, y, r.W);
         for (int it = 0; it < 5 && d2 > 1e-6f * (1.0f + norm2(r.W)); ++it) d2 = halley32(c, fx, y, r.W);
     }
-    float d2 = accel32(c, r);
+    const float d2 = accel32(c, r);
     // the crest line of this period is fx = 0
     bad |= !(d2 >= c.wfb2) || (fminf(y, yp) < c.ybp && fx * xp <= 0.0f);
 }
 
-// RHS at the point where r.W was itself obtained (re-convergence after a load).
-__device__ __forceinline__ void refresh32(const Sc32& c, float fx, float y, Rhs32& r)
-{
-    halley32(c, fx, y, r.W);
-    accel32(c, r);
-}
 
 __device__ __forceinline__ void comp_add(float& hi, float& lo, float inc)
 {
@@ -157,7 +150,6 @@ __device__ __forceinline__ void rk4_step32(const Sc32& c, const St32& u, const R
 }
 
 // DOPRI5 step in FP32; returns the scaled RMS error over (x, y, px, py).
-// xabs0 = |x| at the step start (for the error scale).
 __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const Rhs32& r1, float h, float rtol,
                                             float atol, St32& ue, Rhs32& re, bool& bad)
 {
@@ -235,6 +227,38 @@ __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const 
 __device__ __forceinline__ bool st32_finite(const St32& u)
 {
     return isfinite(u.fx) && isfinite(u.y) && isfinite(u.px) && isfinite(u.py);
+}
+
+// Event values of an in-box state (>= 0 inside): 0 top, 1 right, 2 left,
+// 3 grating (virtual coordinate y + Re W / k, zero on the trochoid).  xh /
+// xl: the side faces as offsets in v's period.  Evaluated with the
+// compensation terms, so that the faces are resolved to the rounding of the
+// difference itself.
+__device__ __forceinline__ void ev_values32(const Sc32& c, const St32& v, const Rhs32& r, float ytop, float xh,
+                                            float xl, int mirror, float e[4])
+{
+    e[0] = (ytop - v.y) - v.ly;
+    e[1] = (xh - v.fx) - v.lx;
+    e[2] = (v.fx - xl) + v.lx;
+    e[3] = mirror ? 1.0f : (v.y + r.W.re * c.invk) + v.ly;
+}
+
+// smallest of the event values selected by mask, and which one it is
+__device__ __forceinline__ float ev_min32(const float e[4], int mask, int* code)
+{
+    float m = 3.0e38f;
+    int k = -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (((mask >> i) & 1) && e[i] < m) { m = e[i]; k = i; }
+    *code = k;
+    return m;
+}
+
+__device__ __forceinline__ void split32(double v, float& hi, float& lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
 }
 
 // err^(-1/5) through the hardware log2/exp2

@@ -233,7 +233,7 @@ struct WfStore {
     long long cap_rays = 0;
     int cap_scenes = 0;
     void* rays = nullptr;       // one allocation for all per-ray arrays
-    int* queues = nullptr;      // 3 x cap_rays
+    int* queues = nullptr;      // 4 x cap_rays
     void* tables = nullptr;     // scenes, cameras, offsets, image pointers
     QCtr* ctr = nullptr;
     WfTotals* tot = nullptr;
@@ -716,34 +716,14 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
     HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     unsigned len = w.h_ctr->box_len[0];
-    const unsigned tail_max = 128u * (unsigned)ctx->n_cu;
+    // one round per visit of the box: the in-box kernel takes every ray of
+    // the queue through its visit (or to a step that needs FP64), the FP64
+    // kernel takes those steps, the air kernel walks the rays that left
     for (int round = 0; len > 0; ++round) {
         const int cur = round & 1;
-        if (len <= tail_max) {
-            // finish the remaining rays without round barriers
-            const int n_simd = 4 * ctx->n_cu;
-            int lanes = (int)std::min<unsigned>(64u, std::max<unsigned>(1u, (len + 2 * n_simd - 1) / (2 * n_simd)));
-            unsigned blocks = (len + lanes - 1) / lanes;
-            HIP_OK(hipEventRecord(w.ev[1], stream));
-            if (integ == 0)
-                hipLaunchKernelGGL(k_wf_tail<0>, dim3(blocks), dim3(64), 0, stream, a, cur, lanes);
-            else
-                hipLaunchKernelGGL(k_wf_tail<1>, dim3(blocks), dim3(64), 0, stream, a, cur, lanes);
-            HIP_OK(hipEventRecord(w.ev[2], stream));
-            HIP_OK(hipGetLastError());
-            HIP_OK(hipStreamSynchronize(stream));
-            float t1 = 0.f;
-            HIP_OK(hipEventElapsedTime(&t1, w.ev[1], w.ev[2]));
-            w.tail_ms += t1;
-            w.tail_rays = len;
-            w.rounds = round + 1;
-            break;
-        }
-        // grids sized by the rays in flight: every ray flags at most one
-        // event per round and every event yields at most one ray in air
         const unsigned need = (len + 255) / 256;
         const unsigned box_g = std::min<unsigned>(need, (unsigned)w.box_blocks[integ]);
-        const unsigned ev_g = std::min<unsigned>(need, (unsigned)(8 * ctx->n_cu));
+        const unsigned air_g = std::min<unsigned>(need, (unsigned)(8 * ctx->n_cu));
         hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
         HIP_OK(hipEventRecord(w.ev[1], stream));
         if (integ == 0)
@@ -752,10 +732,10 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
             hipLaunchKernelGGL(k_wf_box<1>, dim3(box_g), dim3(256), 0, stream, a, cur);
         HIP_OK(hipEventRecord(w.ev[2], stream));
         if (integ == 0)
-            hipLaunchKernelGGL(k_wf_event<0>, dim3(ev_g), dim3(256), 0, stream, a, cur);
+            hipLaunchKernelGGL(k_wf_event<0>, dim3(air_g), dim3(256), 0, stream, a, cur);
         else
-            hipLaunchKernelGGL(k_wf_event<1>, dim3(ev_g), dim3(256), 0, stream, a, cur);
-        hipLaunchKernelGGL(k_wf_air, dim3(ev_g), dim3(256), 0, stream, a, cur);
+            hipLaunchKernelGGL(k_wf_event<1>, dim3(air_g), dim3(256), 0, stream, a, cur);
+        hipLaunchKernelGGL(k_wf_air, dim3(air_g), dim3(256), 0, stream, a, cur);
         HIP_OK(hipEventRecord(w.ev[3], stream));
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
@@ -768,7 +748,7 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
         w.fp64_steps += w.h_ctr->ev_len;
         w.rounds = round + 1;
         len = w.h_ctr->box_len[cur ^ 1];
-        if (round > 1000000) return fail(GC_EDEVICE, "pipeline did not drain");
+        if (round > 100000) return fail(GC_EDEVICE, "pipeline did not drain");
     }
     return GC_OK;
 }

@@ -1,27 +1,31 @@
 // gc_wave.hpp -- the FP32 render/trace pipeline as queue-driven kernels.
 //
-// A sample's path alternates between long stretches of integration inside
-// the cloak and rare events (box faces, grating contacts, FP64 fallbacks).
-// Keeping both in one kernel gives every lane the register footprint of the
-// FP64 event code, so they are separate kernels that pass rays through
+// A sample's path alternates between flights through air (FP64: straight
+// lines to the cloak box, contacts with the bare grating by root finding)
+// and visits of the box (FP32 integration).  The two have very different
+// register footprints, so they are separate kernels that pass rays through
 // queues of ray indices:
 //
 //   k_wf_init    one lane per sample: camera ray (or given ray), flight
-//                through air (FP64) to the box, the sky, or a failure;
+//                through air to the box, the sky, or a failure;
 //   k_wf_box     persistent FP32 kernel: each wave claims rays from the box
-//                queue (one atomic per wave, ballot + rank for the lanes),
-//                integrates each until its next step crosses a surface or
-//                needs FP64, writes the ray back and pushes it to the event
-//                queue, then refills the idle lane;
-//   k_wf_event   FP64: redoes the flagged step from its start with step
-//                control, locates and applies the event (partial-step root
-//                solve); rays still inside go to the next box queue, rays
-//                that left the box to the air queue;
-//   k_wf_air     FP64: flight through air to the box, the sky or a failure;
+//                queue (one atomic per wave, ballot + rank for the lanes)
+//                and integrates each through its whole visit of the box:
+//                steps, the location of each event on the partial steps of
+//                the same integrator, grating reflections and total
+//                internal reflections; a ray that leaves the box goes to the
+//                air queue, a ray whose next step needs FP64 (a stage point
+//                near the branch point or a path across the branch cut) to
+//                the FP64 queue, and the lane takes a new ray;
+//   k_wf_event   FP64: that step (with step control and any event in it);
+//                the ray goes on in the next round's box queue;
+//   k_wf_air     FP64: flight through air to the box (next box queue), the
+//                sky or a failure;
 //   k_wf_finish  averages each pixel's samples and folds the counters.
 //
 // Rounds of (k_wf_box, k_wf_event, k_wf_air) repeat until the box queue is
-// empty.
+// empty; a ray needs one round per visit of the box (one or two for almost
+// all), plus one per FP64 step.
 // Samples of several scenes can share one launch: every ray carries its
 // scene index and the scene / camera tables live in device memory.
 #pragma once
@@ -211,9 +215,21 @@ __global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
     continue_in_air(a, q, s, r, p, cnt, a.qbox[0], &a.ctr->box_len[0]);
 }
 
-// The hot kernel.  INTEG: 0 RK4, 1 DOPRI5.
+// In-box event location in FP32: regula falsi with the Illinois
+// modification on the step fraction theta, on the partial steps of the same
+// integrator.  It ends at the FP32 resolution of theta or, for the grating,
+// when the upper end of the bracket is on the surface to the FP32 error of W
+// (a trial that lands on the surface to that error from the inside is
+// followed by one just across it).
+constexpr float kLocTol = 2.0e-7f;
+constexpr float kLocNoiseW = 2.4e-7f;
+constexpr int kLocMaxIt = 40;
 constexpr int kRefill = 8;
 
+// The hot kernel.  INTEG: 0 RK4, 1 DOPRI5.  Every iteration evaluates one
+// step per lane: a normal step of length h, or a trial of the location of
+// the event that the lane's last accepted step crossed (length theta h), so
+// that lanes locating an event do not hold the others up.
 template <int INTEG>
 __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
 {
@@ -223,18 +239,25 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
     const float rtol = (float)a.o.rtol, atol = (float)a.o.atol;
     const float hmax = (float)a.o.h_max, hmin = (float)a.o.h_min;
     const int max_steps = a.o.max_steps > 0x7fffffffll ? 0x7fffffff : (int)a.o.max_steps;
+    const int max_ev = a.o.max_events;
 
     bool active = false;
     // a wave that finds the queue already drained does not touch the counter
     bool exhausted = *((volatile unsigned*)&a.ctr->box_head[cur]) >= qlen;
     int q = 0;
+    const SceneDev* sp = a.scenes;
     Sc32 c;
     float ytop = 0.f, xhi = 0.f, xlo = 0.f, pz = 0.f, h = 0.f, tau = 0.f, ltau = 0.f;
     St32 u;
     Rhs32 r1;
-    int steps = 0, rej = 0, mirror = 0;
+    int steps = 0, rej = 0, nev = 0, fbk = 0, mirror = 0;
     bool last_rej = false;
-    double hw = 0.0, L = 1.0;
+    double z0 = 0.0;
+    // event location
+    bool loc = false, lfin = false;
+    float th = 0.f, tlo = 0.f, thi = 1.f, flo = 0.f, fhi = 0.f, hacc = 0.f, hnx = 0.f;
+    int side = 0, emask = 0, lit = 0, hicode = -1;
+    bool need64 = false;   // the next step from u needs FP64
     unsigned my_steps = 0;
 
     for (;;) {
@@ -256,11 +279,10 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                     if (qi < qlen) {
                         q = queue[qi];
                         const WfRays& R = a.R;
-                        const SceneDev& s = a.scenes[R.scene[q]];
+                        sp = a.scenes + R.scene[q];
+                        const SceneDev& s = *sp;
                         c = make_sc32(s, a.o.wfb2);
                         ytop = (float)s.ytop;
-                        hw = s.hw;
-                        L = s.L;
                         mirror = s.mirror;
                         u.cell = R.cell[q];
                         u.fx = R.fx[q]; u.lx = R.lx[q];
@@ -268,16 +290,21 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                         u.px = R.px[q]; u.lpx = R.lpx[q];
                         u.py = R.py[q]; u.lpy = R.lpy[q];
                         pz = R.pz[q];
+                        z0 = R.z0[q];
                         h = R.h[q];
                         tau = R.tau[q];
                         ltau = R.ltau[q];
                         steps = R.steps[q];
                         rej = R.rej[q];
+                        nev = R.events[q];
+                        fbk = R.fbk[q];
                         last_rej = (R.flags[q] & WF_LAST_REJ) != 0;
-                        xhi = (float)(hw - (double)u.cell * L);
-                        xlo = (float)(-hw - (double)u.cell * L);
+                        xhi = (float)(s.hw - (double)u.cell * s.L);
+                        xlo = (float)(-s.hw - (double)u.cell * s.L);
                         r1.W = {R.Wr[q], R.Wi[q]};
-                        refresh32(c, u.fx, u.y, r1);
+                        halley32(c, u.fx, u.y, r1.W);
+                        need64 = !(accel32(c, r1) >= c.wfb2);
+                        loc = false;
                         active = true;
                     }
                 }
@@ -286,47 +313,169 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
         if (__ballot(active) == 0ull) break;
         if (!active) continue;
 
-        St32 ue;
-        Rhs32 re;
-        bool bad = false;
-        float hnext = h;
-        bool flag = false;
-        if (INTEG == 0) {
-            rk4_step32(c, u, r1, h, ue, re, bad);
-            flag = bad;
-        } else {
-            float err = dp5_step32(c, u, r1, h, rtol, atol, ue, re, bad);
-            if (bad || !isfinite(err)) {
-                flag = true;
-            } else if (err > 1.0f) {
-                h *= fmaxf(0.2f, 0.9f * pow_m02(err));
-                last_rej = true;
-                ++rej;
-                if (h < hmin) {
-                    // let the FP64 path take over the step control
-                    h = hmin;
-                    flag = true;
-                } else {
-                    continue;
-                }
+        int fin = -1;           // >= 0: the ray finishes with this status
+        bool leaves = false;    // the ray left the box
+        double p3[3] = {0.0, 0.0, 0.0};
+        if (!loc && steps >= max_steps) {
+            fin = RS_MAX_STEPS;
+        } else if (!need64) {
+            const float tstep = loc ? th * hacc : h;
+            St32 ue;
+            Rhs32 re;
+            float err = 0.0f;
+            bool bad = false;
+            if (INTEG == 0)
+                rk4_step32(c, u, r1, tstep, ue, re, bad);
+            else
+                err = dp5_step32(c, u, r1, tstep, rtol, atol, ue, re, bad);
+            if (bad || !st32_finite(ue) || (INTEG == 1 && !loc && !isfinite(err))) {
+                // this step (from u, of length h; the accepted length when
+                // locating) goes to the FP64 path
+                if (loc) h = hacc;
+                loc = false;
+                need64 = true;
+                ++fbk;
             } else {
-                float fac = (err == 0.0f) ? 5.0f : 0.9f * pow_m02(err);
-                fac = fminf(5.0f, fmaxf(0.2f, fac));
-                if (last_rej) fac = fminf(fac, 1.0f);
-                hnext = fminf(h * fac, hmax);
+                float xh = xhi, xl = xlo;
+                if (ue.cell != u.cell) {
+                    xh = (float)(sp->hw - (double)ue.cell * sp->L);
+                    xl = (float)(-sp->hw - (double)ue.cell * sp->L);
+                }
+                float e[4];
+                ev_values32(c, ue, re, ytop, xh, xl, mirror, e);
+                bool apply = false;
+                int evc = -1;
+                if (!loc) {
+                    float hnext = h;
+                    bool accepted = true;
+                    if (INTEG == 1) {
+                        if (err > 1.0f) {
+                            h *= fmaxf(0.2f, 0.9f * pow_m02(err));
+                            last_rej = true;
+                            ++rej;
+                            accepted = false;
+                            if (h < hmin) fin = RS_UNDERFLOW;
+                        } else {
+                            float fac = (err == 0.0f) ? 5.0f : 0.9f * pow_m02(err);
+                            fac = fminf(5.0f, fmaxf(0.2f, fac));
+                            if (last_rej) fac = fminf(fac, 1.0f);
+                            last_rej = false;
+                            hnext = fminf(h * fac, hmax);
+                        }
+                    }
+                    if (accepted) {
+                        ++steps;
+                        ++my_steps;
+                        emask = (e[0] < 0.0f ? 1 : 0) | (e[1] < 0.0f ? 2 : 0) | (e[2] < 0.0f ? 4 : 0) |
+                                (e[3] < 0.0f ? 8 : 0);
+                        if (!emask) {
+                            comp_add(tau, ltau, h);
+                            u = ue;
+                            r1 = re;
+                            h = hnext;
+                            xhi = xh;
+                            xlo = xl;
+                        } else {
+                            // the step crossed an event: locate it on the
+                            // partial steps of the next iterations
+                            float e0[4];
+                            int c0;
+                            ev_values32(c, u, r1, ytop, xhi, xlo, mirror, e0);
+                            flo = fmaxf(ev_min32(e0, emask, &c0), 0.0f);
+                            fhi = ev_min32(e, emask, &hicode);
+                            tlo = 0.0f;
+                            thi = 1.0f;
+                            side = 0;
+                            lit = 0;
+                            lfin = false;
+                            hacc = h;
+                            hnx = hnext;
+                            th = (flo - fhi > 0.0f) ? flo / (flo - fhi) : 0.5f;
+                            if (!(th > 0.0f && th < 1.0f)) th = 0.5f;
+                            loc = true;
+                        }
+                    }
+                } else {
+                    // a trial of the location at theta = th
+                    int code;
+                    const float f = ev_min32(e, emask, &code);
+                    if (lfin) {
+                        apply = true;   // the recomputed upper end of the bracket
+                        evc = f < 0.0f ? code : hicode;
+                    } else {
+                        if (f < 0.0f) {
+                            thi = th;
+                            fhi = f;
+                            hicode = code;
+                            if (side < 0) flo *= 0.5f;
+                            side = -1;
+                            apply = (code == 3 && f >= -kLocNoiseW);
+                        } else {
+                            tlo = th;
+                            flo = f;
+                            if (side > 0) fhi *= 0.5f;
+                            side = 1;
+                        }
+                        ++lit;
+                        if (!apply && (thi - tlo <= kLocTol || lit >= kLocMaxIt)) {
+                            if (side < 0) {
+                                apply = true;   // this trial is the upper end
+                            } else {
+                                th = thi;       // recompute the upper end next
+                                lfin = true;
+                            }
+                        } else if (!apply) {
+                            float t;
+                            if (side > 0 && hicode == 3 && flo <= kLocNoiseW) {
+                                const float sl = (fhi - flo) / (thi - tlo);
+                                t = tlo + fmaxf(2.0f * kLocNoiseW / fabsf(sl), kLocTol);
+                            } else {
+                                t = (flo - fhi > 0.0f) ? (flo * thi - fhi * tlo) / (flo - fhi) : 0.5f * (tlo + thi);
+                            }
+                            if (lit >= 20 || !(t > tlo && t < thi)) t = 0.5f * (tlo + thi);
+                            th = t;
+                        }
+                        evc = code;
+                    }
+                }
+                if (apply) {
+                    // the event at the trial state ue (theta = th)
+                    comp_add(tau, ltau, th * hacc);
+                    u = ue;
+                    r1 = re;
+                    xhi = xh;
+                    xlo = xl;
+                    h = hnx;
+                    loc = false;
+                    if (++nev > max_ev) {
+                        fin = RS_MAX_EVENTS;
+                    } else {
+                        p3[0] = (double)u.px + (double)u.lpx;
+                        p3[1] = (double)u.py + (double)u.lpy;
+                        p3[2] = (double)pz;
+                        if (evc == 3) {
+                            // grating: the upward normal is (-Im W, 1 + Re W) on the surface
+                            const double nx = -(double)re.W.im, ny = 1.0 + (double)re.W.re;
+                            const double inv = 1.0 / sqrt(nx * nx + ny * ny);
+                            reflect2(p3[0], p3[1], nx * inv, ny * inv);
+                            split32(p3[0], u.px, u.lpx);
+                            split32(p3[1], u.py, u.lpy);
+                        } else {
+                            double nf[3] = {0.0, 0.0, 0.0};
+                            if (evc == 0) nf[1] = 1.0; else if (evc == 1) nf[0] = 1.0; else nf[0] = -1.0;
+                            if (snell(p3, nf, 1.0)) {
+                                leaves = true;
+                            } else {
+                                split32(p3[0], u.px, u.lpx);
+                                split32(p3[1], u.py, u.lpy);
+                            }
+                        }
+                    }
+                }
             }
         }
-        if (!flag) {
-            if (ue.cell != u.cell) {
-                xhi = (float)(hw - (double)ue.cell * L);
-                xlo = (float)(-hw - (double)ue.cell * L);
-            }
-            float xr = ue.fx + ue.lx;
-            flag = !st32_finite(ue) || (ue.y + ue.ly > ytop) || (xr > xhi) || (xr < xlo) ||
-                   (mirror == 0 && ue.y + re.W.re * c.invk < 0.0f);
-        }
-        if (flag) {
-            // hand the step (from its start u, size h) to the FP64 path
+        if (need64 && fin < 0) {
+            // store the state at the step start; the FP64 kernel takes it
             const WfRays& R = a.R;
             R.cell[q] = u.cell;
             R.fx[q] = u.fx; R.lx[q] = u.lx;
@@ -338,27 +487,33 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             R.tau[q] = tau; R.ltau[q] = ltau;
             R.steps[q] = steps;
             R.rej[q] = rej;
+            R.events[q] = nev;
+            R.fbk[q] = fbk;
             R.flags[q] = last_rej ? WF_LAST_REJ : 0;
-            if (bad) R.fbk[q] += 1;
             push(a.qev, &a.ctr->ev_len, q);
             active = false;
+            need64 = false;
             continue;
         }
-        comp_add(tau, ltau, h);
-        u = ue;
-        r1 = re;
-        h = hnext;
-        last_rej = false;
-        ++my_steps;
-        if (++steps >= max_steps) {
-            const WfRays& R = a.R;
-            R.steps[q] = steps;
-            R.rej[q] = rej;
-            R.status[q] = RS_MAX_STEPS;
-            R.qx[q] = 0.0; R.qy[q] = 0.0; R.qz[q] = 0.0;
-            R.rgb[3 * q + 0] = 0.0f; R.rgb[3 * q + 1] = 0.0f; R.rgb[3 * q + 2] = 0.0f;
-            active = false;
+        if (fin < 0 && !leaves) continue;
+        // the ray ends its visit of the box: as a point and direction in air
+        const WfRays& R = a.R;
+        double r[3] = {(double)u.cell * sp->L + ((double)u.fx + (double)u.lx), (double)u.y + (double)u.ly,
+                       z0 + (double)pz * ((double)tau + (double)ltau)};
+        R.steps[q] = steps;
+        R.rej[q] = rej;
+        R.events[q] = nev;
+        R.fbk[q] = fbk;
+        if (fin >= 0) {
+            const double zero[3] = {0.0, 0.0, 0.0};
+            finish_ray(a, q, *sp, fin, r, zero);
+        } else {
+            R.rx[q] = r[0]; R.ry[q] = r[1]; R.rz[q] = r[2];
+            R.qx[q] = p3[0]; R.qy[q] = p3[1]; R.qz[q] = p3[2];
+            push(a.qair, &a.ctr->air_len, q);
         }
+        active = false;
+        loc = false;
     }
     unsigned long long total = my_steps;
 #pragma unroll
@@ -366,7 +521,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
     if (lane == 0) atomicAdd(&a.ctr->hot_steps, total);
 }
 
-// One flagged step of ray q in FP64 (step control, event location and
+// Flagged steps of ray q in FP64 (step control, event location and
 // handling).  Returns 0 if the ray is still inside the box (state stored),
 // 1 if it left the box (air state stored in rx..qz), 2 if it finished.
 template <int INTEG>
@@ -378,8 +533,17 @@ __device__ __forceinline__ int event_body(const WfArgs& a, long long q, const Sc
     LaneCount cnt = {a.R.steps[q], a.R.rej[q], a.R.events[q], 0};
     double r[3], p[3], mc = 1.0;
     int st = RS_OK;
-    int so = box_step64(s, o, b, cnt, &mc, r, p, &st);
-    if (so == SO_INSIDE && cnt.steps >= o.max_steps) { so = SO_FAIL; st = RS_MAX_STEPS; }
+    int so = SO_INSIDE;
+    // FP64 steps while the ray stays where FP32 cannot resolve W (with a
+    // margin), so that a ray lingering near the branch point does not cost
+    // a round per step
+    for (int n = 0; n < 256; ++n) {
+        so = box_step64(s, o, b, cnt, &mc, r, p, &st);
+        if (so == SO_INSIDE && cnt.steps >= o.max_steps) { so = SO_FAIL; st = RS_MAX_STEPS; }
+        if (so != SO_INSIDE) break;
+        const double d2 = (1.0 + b.r1.W.re) * (1.0 + b.r1.W.re) + b.r1.W.im * b.r1.W.im;
+        if (d2 >= 4.0 * o.wfb2) break;
+    }
     a.R.steps[q] = (int)cnt.steps;
     a.R.rej[q] = (int)cnt.rejected;
     a.R.events[q] = cnt.events;
@@ -442,116 +606,6 @@ __global__ void __launch_bounds__(256) k_wf_air(WfArgs a, int cur)
         const long long q = a.qair[qi];
         const SceneDev s = a.scenes[a.R.scene[q]];
         if (air_body(a, q, s) == 0) push(qnext, qnext_len, (int)q);
-    }
-}
-
-// FP32 in-cloak steps of one ray from its stored state until a step needs
-// the FP64 path (returns 0, state of the step start stored) or the step cap
-// is reached (returns 2, ray finished).
-template <int INTEG>
-__device__ __forceinline__ int hot_body(const WfArgs& a, long long q, const SceneDev& s)
-{
-    const WfRays& R = a.R;
-    const Sc32 c = make_sc32(s, a.o.wfb2);
-    const float rtol = (float)a.o.rtol, atol = (float)a.o.atol;
-    const float hmax = (float)a.o.h_max, hmin = (float)a.o.h_min;
-    const int max_steps = a.o.max_steps > 0x7fffffffll ? 0x7fffffff : (int)a.o.max_steps;
-    const float ytop = (float)s.ytop;
-    St32 u;
-    u.cell = R.cell[q];
-    u.fx = R.fx[q]; u.lx = R.lx[q];
-    u.y = R.y[q]; u.ly = R.ly[q];
-    u.px = R.px[q]; u.lpx = R.lpx[q];
-    u.py = R.py[q]; u.lpy = R.lpy[q];
-    float h = R.h[q], tau = R.tau[q], ltau = R.ltau[q];
-    int steps = R.steps[q], rej = R.rej[q];
-    bool last_rej = (R.flags[q] & WF_LAST_REJ) != 0;
-    float xhi = (float)(s.hw - (double)u.cell * s.L), xlo = (float)(-s.hw - (double)u.cell * s.L);
-    Rhs32 r1;
-    r1.W = {R.Wr[q], R.Wi[q]};
-    refresh32(c, u.fx, u.y, r1);
-    for (;;) {
-        St32 ue;
-        Rhs32 re;
-        bool bad = false, flag = false;
-        float hnext = h;
-        if (INTEG == 0) {
-            rk4_step32(c, u, r1, h, ue, re, bad);
-            flag = bad;
-        } else {
-            float err = dp5_step32(c, u, r1, h, rtol, atol, ue, re, bad);
-            if (bad || !isfinite(err)) {
-                flag = true;
-            } else if (err > 1.0f) {
-                h *= fmaxf(0.2f, 0.9f * pow_m02(err));
-                last_rej = true;
-                ++rej;
-                if (h < hmin) { h = hmin; flag = true; } else continue;
-            } else {
-                float fac = (err == 0.0f) ? 5.0f : 0.9f * pow_m02(err);
-                fac = fminf(5.0f, fmaxf(0.2f, fac));
-                if (last_rej) fac = fminf(fac, 1.0f);
-                hnext = fminf(h * fac, hmax);
-            }
-        }
-        if (!flag) {
-            if (ue.cell != u.cell) {
-                xhi = (float)(s.hw - (double)ue.cell * s.L);
-                xlo = (float)(-s.hw - (double)ue.cell * s.L);
-            }
-            float xr = ue.fx + ue.lx;
-            flag = !st32_finite(ue) || (ue.y + ue.ly > ytop) || (xr > xhi) || (xr < xlo) ||
-                   (s.mirror == 0 && ue.y + re.W.re * c.invk < 0.0f);
-        }
-        if (flag) {
-            R.cell[q] = u.cell;
-            R.fx[q] = u.fx; R.lx[q] = u.lx;
-            R.y[q] = u.y; R.ly[q] = u.ly;
-            R.px[q] = u.px; R.lpx[q] = u.lpx;
-            R.py[q] = u.py; R.lpy[q] = u.lpy;
-            R.Wr[q] = r1.W.re; R.Wi[q] = r1.W.im;
-            R.h[q] = h;
-            R.tau[q] = tau; R.ltau[q] = ltau;
-            R.steps[q] = steps;
-            R.rej[q] = rej;
-            R.flags[q] = last_rej ? WF_LAST_REJ : 0;
-            if (bad) R.fbk[q] += 1;
-            return 0;
-        }
-        comp_add(tau, ltau, h);
-        u = ue;
-        r1 = re;
-        h = hnext;
-        last_rej = false;
-        if (++steps >= max_steps) {
-            R.steps[q] = steps;
-            R.rej[q] = rej;
-            R.status[q] = RS_MAX_STEPS;
-            R.qx[q] = 0.0; R.qy[q] = 0.0; R.qz[q] = 0.0;
-            R.rgb[3 * q + 0] = 0.0f; R.rgb[3 * q + 1] = 0.0f; R.rgb[3 * q + 2] = 0.0f;
-            return 2;
-        }
-    }
-}
-
-// The last rays of a launch: few enough that round barriers would leave most
-// of the GPU idle while the slowest of them sets each round's length.  Each
-// is finished here in one go (FP32 steps, FP64 events, air), spread over
-// `lanes` lanes per wave so that they occupy all SIMDs.
-template <int INTEG>
-__global__ void __launch_bounds__(64) k_wf_tail(WfArgs a, int cur, int lanes)
-{
-    if ((int)threadIdx.x >= lanes) return;
-    const unsigned qlen = a.ctr->box_len[cur];
-    const unsigned qi = blockIdx.x * (unsigned)lanes + threadIdx.x;
-    if (qi >= qlen) return;
-    const long long q = a.qbox[cur][qi];
-    const SceneDev s = a.scenes[a.R.scene[q]];
-    for (int guard = 0; guard < (1 << 20); ++guard) {
-        if (hot_body<INTEG>(a, q, s) == 2) return;
-        int r = event_body<INTEG>(a, q, s);
-        if (r == 2) return;
-        if (r == 1 && air_body(a, q, s) == 2) return;
     }
 }
 
