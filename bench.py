@@ -50,6 +50,9 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--workload", choices=["single", "batch", "stress", "grad"], default="single")
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="first copy this many MiB device to device (a reference kernel of known traffic for "
+                        "hardware counters)")
     return p.parse_args()
 
 
@@ -58,6 +61,16 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this path has no multi-GPU mode (pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_mib > 0:
+        import torch
+        n = args.copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# reference copy: {args.copy_mib} MiB read, {args.copy_mib} MiB written", file=sys.stderr, flush=True)
+        del src, dst
     if args.workload == "batch":
         return main_batch(args)
     if args.workload == "stress":

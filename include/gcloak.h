@@ -137,6 +137,30 @@ typedef struct {
 
 typedef struct gc_ctx gc_ctx;
 
+/* Scheduling of the FP32 pipeline's in-cloak kernel, per context.  It
+ * changes only which lane integrates which ray and when: every ray's result
+ * is the same for any setting.  The in-cloak kernel is persistent: each
+ * wave takes rays from queues of box entries, one visit of the box at a
+ * time, and a visit cannot be split, so the longest visits bound the
+ * length of a launch unless they start early and run fast.
+ *   slow_pxy        a box entry whose unit direction has an in-plane part
+ *                   |(d_x, d_y)| below this goes to the slow queue (it
+ *                   crosses the box slowly in tau); 0: a single queue
+ *   slow_wave_div   every slow_wave_div-th wave takes the slow queue first;
+ *                   a wave holding slow rays raises its issue priority on
+ *                   its SIMD; 0: no wave prefers the slow queue
+ *   refill          a wave claims new rays once at least this many of its
+ *                   64 lanes are idle (1 .. 64)
+ *   waves_per_simd  resident waves per SIMD of the in-cloak kernel
+ *                   (1 .. 8; 0: as many as fit) */
+typedef struct {
+    double slow_pxy;
+    int32_t slow_wave_div;
+    int32_t refill;
+    int32_t waves_per_simd;
+    int32_t reserved;
+} gc_tune;
+
 /* Create a context on HIP device `hip_device` (made current for the call).
  * Returns GC_EINVAL for a null `out` or a bad device, GC_EDEVICE on HIP
  * failure. */
@@ -152,6 +176,15 @@ const char* gc_last_error(void);
  * h_max = 0.02, h0 = 1e-3, h_min = 1e-12, w_fallback = 1e-2,
  * max_events = 32, max_steps = 10^5. */
 void gc_default_opts(gc_opts* opts);
+
+/* Fill `tune` with the defaults (the setting a new context starts with). */
+void gc_default_tune(gc_tune* tune);
+
+/* Set / read the context's scheduling.  GC_EINVAL for a null pointer or a
+ * value out of range (slow_pxy outside [0, 1], slow_wave_div < 0, refill
+ * outside 1 .. 64, waves_per_simd outside 0 .. 8). */
+gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* tune);
+gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* tune);
 
 /* Trace n rays (Sec. 3) from origins d_org and directions d_dir (n x 3
  * doubles, row-major; directions need not be unit) until they escape.

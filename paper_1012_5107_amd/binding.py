@@ -60,9 +60,18 @@ class Stats(ctypes.Structure):
                 for k, t in self._fields_}
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("slow_pxy", ctypes.c_double), ("slow_wave_div", ctypes.c_int32), ("refill", ctypes.c_int32),
+                ("waves_per_simd", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # every symbol the header declares
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
-           "gc_render_batch", "gc_render_grad", "gc_cross_correlate"]
+           "gc_render_batch", "gc_render_grad", "gc_cross_correlate", "gc_default_tune", "gc_set_tune",
+           "gc_get_tune"]
 
 _lib = None
 
@@ -100,6 +109,12 @@ def load():
     L.gc_cross_correlate.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), vp]
     L.gc_cross_correlate.restype = ctypes.c_int
+    L.gc_default_tune.argtypes = [ctypes.POINTER(Tune)]
+    L.gc_default_tune.restype = None
+    L.gc_set_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    L.gc_set_tune.restype = ctypes.c_int
+    L.gc_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    L.gc_get_tune.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -184,6 +199,20 @@ class Context:
                                     dirs.data_ptr(), oo.data_ptr(), od.data_ptr(), st.data_ptr(), steps.data_ptr(),
                                     ev.data_ptr(), _stream_handle(stream)))
         return oo, od, st, steps, ev
+
+    def tune(self, **kw):
+        """Read the context's scheduling of the FP32 pipeline (gc_tune as a
+        dict); keyword arguments set those fields first."""
+        L = load()
+        t = Tune()
+        _check(L.gc_get_tune(self._h, ctypes.byref(t)))
+        if kw:
+            for k, v in kw.items():
+                if k not in t.as_dict():
+                    raise KeyError(k)
+                setattr(t, k, v)
+            _check(L.gc_set_tune(self._h, ctypes.byref(t)))
+        return t.as_dict()
 
     def render(self, scene, camera, opts, prec="f64", out=None, stats=True, stream=None):
         """Render an H x W x 3 float32 image on the device.  Returns

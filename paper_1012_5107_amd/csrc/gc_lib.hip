@@ -233,7 +233,7 @@ struct WfStore {
     long long cap_rays = 0;
     int cap_scenes = 0;
     void* rays = nullptr;       // one allocation for all per-ray arrays
-    int* queues = nullptr;      // 4 x cap_rays
+    int* queues = nullptr;      // 5 x cap_rays: box (2 rounds), FP64, slow box (2 rounds)
     void* tables = nullptr;     // scenes, cameras, offsets, image pointers
     QCtr* ctr = nullptr;
     WfTotals* tot = nullptr;
@@ -268,6 +268,7 @@ struct AdjStore {
 struct gc_ctx {
     int device;
     int n_cu;
+    gc_tune tune;
     DevCounters* d_cnt;
     double* d_part;
     double* d_ccout;
@@ -659,7 +660,7 @@ static gc_status wf_reserve(gc_ctx* ctx, long long n_rays, int n_scenes)
         w.cap_rays = 0;
         long long cap = n_rays + n_rays / 8;
         if (hipMalloc(&w.rays, wf_ray_bytes(cap) + 64 * 256) != hipSuccess ||
-            hipMalloc((void**)&w.queues, sizeof(int) * 4 * (size_t)cap) != hipSuccess)
+            hipMalloc((void**)&w.queues, sizeof(int) * 5 * (size_t)cap) != hipSuccess)
             return fail(GC_ENOMEM, "pipeline ray buffers (%lld rays): allocation failed", cap);
         w.cap_rays = cap;
     }
@@ -715,15 +716,18 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
-    unsigned len = w.h_ctr->box_len[0];
+    unsigned len = w.h_ctr->box_len[0] + w.h_ctr->slow_len[0];
+    int box_max = w.box_blocks[integ];
+    if (ctx->tune.waves_per_simd > 0) box_max = std::min(box_max, ctx->tune.waves_per_simd * ctx->n_cu);
     // one round per visit of the box: the in-box kernel takes every ray of
     // the queue through its visit (or to a step that needs FP64), the FP64
     // kernel takes those steps, the air kernel walks the rays that left
     for (int round = 0; len > 0; ++round) {
         const int cur = round & 1;
         const unsigned need = (len + 255) / 256;
-        const unsigned box_g = std::min<unsigned>(need, (unsigned)w.box_blocks[integ]);
+        const unsigned box_g = std::min<unsigned>(need, (unsigned)box_max);
         const unsigned air_g = std::min<unsigned>(need, (unsigned)(8 * ctx->n_cu));
+        const unsigned scan_g = (unsigned)std::min<long long>((a.n_rays + 255) / 256, 8ll * ctx->n_cu);
         hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
         HIP_OK(hipEventRecord(w.ev[1], stream));
         if (integ == 0)
@@ -735,7 +739,7 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
             hipLaunchKernelGGL(k_wf_event<0>, dim3(air_g), dim3(256), 0, stream, a, cur);
         else
             hipLaunchKernelGGL(k_wf_event<1>, dim3(air_g), dim3(256), 0, stream, a, cur);
-        hipLaunchKernelGGL(k_wf_air, dim3(air_g), dim3(256), 0, stream, a, cur);
+        hipLaunchKernelGGL(k_wf_air, dim3(scan_g), dim3(256), 0, stream, a, cur);
         HIP_OK(hipEventRecord(w.ev[3], stream));
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
@@ -747,7 +751,7 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
         w.event_ms += t2;
         w.fp64_steps += w.h_ctr->ev_len;
         w.rounds = round + 1;
-        len = w.h_ctr->box_len[cur ^ 1];
+        len = w.h_ctr->box_len[cur ^ 1] + w.h_ctr->slow_len[cur ^ 1];
         if (round > 100000) return fail(GC_EDEVICE, "pipeline did not drain");
     }
     return GC_OK;
@@ -762,7 +766,11 @@ static WfArgs wf_args(gc_ctx* ctx, const OptsDev& o, int ns, long long n_rays)
     a.qbox[0] = w.queues;
     a.qbox[1] = w.queues + w.cap_rays;
     a.qev = w.queues + 2 * w.cap_rays;
-    a.qair = w.queues + 3 * w.cap_rays;
+    a.qslow[0] = w.queues + 3 * w.cap_rays;
+    a.qslow[1] = w.queues + 4 * w.cap_rays;
+    a.sch.slow_pxy2 = (float)(ctx->tune.slow_pxy * ctx->tune.slow_pxy);
+    a.sch.slow_div = ctx->tune.slow_wave_div;
+    a.sch.refill = ctx->tune.refill;
     a.ctr = w.ctr;
     WfTables t = wf_tables(w.tables, ns);
     a.scenes = t.scenes;
@@ -885,6 +893,35 @@ void gc_default_opts(gc_opts* o)
     o->max_steps = 100000;
 }
 
+void gc_default_tune(gc_tune* t)
+{
+    if (!t) return;
+    std::memset(t, 0, sizeof *t);
+    t->slow_pxy = 0.0;
+    t->slow_wave_div = 0;
+    t->refill = 8;
+    t->waves_per_simd = 0;
+}
+
+gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* t)
+{
+    if (!ctx || !t) return fail(GC_EINVAL, "ctx and tune must be non-null");
+    if (!(t->slow_pxy >= 0.0 && t->slow_pxy <= 1.0)) return fail(GC_EINVAL, "slow_pxy must be in [0, 1]");
+    if (t->slow_wave_div < 0) return fail(GC_EINVAL, "slow_wave_div must be >= 0");
+    if (t->refill < 1 || t->refill > 64) return fail(GC_EINVAL, "refill must be in 1 .. 64");
+    if (t->waves_per_simd < 0 || t->waves_per_simd > 8) return fail(GC_EINVAL, "waves_per_simd must be in 0 .. 8");
+    ctx->tune = *t;
+    ctx->tune.reserved = 0;
+    return GC_OK;
+}
+
+gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* t)
+{
+    if (!ctx || !t) return fail(GC_EINVAL, "ctx and tune must be non-null");
+    *t = ctx->tune;
+    return GC_OK;
+}
+
 gc_status gc_create(gc_ctx** out, int hip_device)
 {
     if (!out) return fail(GC_EINVAL, "out is null");
@@ -896,6 +933,7 @@ gc_status gc_create(gc_ctx** out, int hip_device)
     gc_ctx* c = new (std::nothrow) gc_ctx();
     if (!c) return fail(GC_ENOMEM, "host allocation failed");
     c->device = hip_device;
+    gc_default_tune(&c->tune);
     {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return fail(GC_EDEVICE, "hipGetDeviceProperties failed"); }

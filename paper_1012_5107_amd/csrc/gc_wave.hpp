@@ -13,14 +13,15 @@
 //                and integrates each through its whole visit of the box:
 //                steps, the location of each event on the partial steps of
 //                the same integrator, grating reflections and total
-//                internal reflections; a ray that leaves the box goes to the
-//                air queue, a ray whose next step needs FP64 (a stage point
-//                near the branch point or a path across the branch cut) to
-//                the FP64 queue, and the lane takes a new ray;
+//                internal reflections; a ray that leaves the box is flagged
+//                for the air kernel, a ray whose next step needs FP64 (a
+//                stage point near the branch point or a path across the
+//                branch cut) goes to the FP64 queue, and the lane takes a
+//                new ray;
 //   k_wf_event   FP64: that step (with step control and any event in it);
 //                the ray goes on in the next round's box queue;
-//   k_wf_air     FP64: flight through air to the box (next box queue), the
-//                sky or a failure;
+//   k_wf_air     FP64: the flagged rays' flight through air to the box
+//                (next box queue), the sky or a failure;
 //   k_wf_finish  averages each pixel's samples and folds the counters.
 //
 // Rounds of (k_wf_box, k_wf_event, k_wf_air) repeat until the box queue is
@@ -37,10 +38,10 @@ namespace gc {
 struct QCtr {
     unsigned box_len[2];
     unsigned box_head[2];
+    unsigned slow_len[2];           // the slow box queue of each round
+    unsigned slow_head[2];
     unsigned ev_len;
     unsigned ev_head;
-    unsigned air_len;
-    unsigned air_head;
     unsigned long long hot_steps;   // accepted steps taken by k_wf_box (all rounds)
 };
 
@@ -54,13 +55,22 @@ struct WfRays {
     float* rgb;   // 3 per ray
 };
 
-enum WfFlag { WF_LAST_REJ = 1 };
+// WF_IN_AIR: the ray left the box (state in rx..qz); the air kernel takes it
+enum WfFlag { WF_LAST_REJ = 1, WF_IN_AIR = 2 };
+
+// Scheduling of the in-box kernel (what is computed does not depend on it).
+struct WfSched {
+    float slow_pxy2;   // a box entry with d_x^2 + d_y^2 below this goes to the slow queue
+    int slow_div;      // every slow_div-th wave takes the slow queue first (0: none)
+    int refill;        // idle lanes that make a wave claim new rays
+};
 
 struct WfArgs {
     WfRays R;
     int* qbox[2];
+    int* qslow[2];     // box entries predicted to take many steps
+    WfSched sch;
     int* qev;
-    int* qair;
     QCtr* ctr;
     const SceneDev* scenes;
     const CamDev* cams;
@@ -137,6 +147,36 @@ __device__ __forceinline__ void push(int* queue, unsigned* len, int q)
     queue[at] = q;
 }
 
+// The box queue a ray entering the box goes to (0 fast, 1 slow).  Its
+// direction at the entry predicts the length of the visit: with a small
+// in-plane part the ray crosses the box slowly in tau (p_z is conserved and
+// the step is capped in tau).
+__device__ __forceinline__ int box_dest(const WfArgs& a, const double p[3])
+{
+    const double pxy2 = p[0] * p[0] + p[1] * p[1];
+    return pxy2 < (double)a.sch.slow_pxy2 * (pxy2 + p[2] * p[2]) ? 1 : 0;
+}
+
+// Append q to the next round's fast (dest 0) or slow (dest 1) box queue,
+// one atomic per wave and queue.  Every active lane of the wave calls it
+// together (dest < 0: nothing to append).
+__device__ __forceinline__ void push_box_wave(const WfArgs& a, int nxt, int dest, int q)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long m0 = __ballot(dest == 0), m1 = __ballot(dest == 1);
+    const int leader = __ffsll((long long)__ballot(1)) - 1;
+    unsigned b0 = 0, b1 = 0;
+    if (lane == leader) {
+        if (m0) b0 = atomicAdd(&a.ctr->box_len[nxt], (unsigned)__popcll(m0));
+        if (m1) b1 = atomicAdd(&a.ctr->slow_len[nxt], (unsigned)__popcll(m1));
+    }
+    b0 = __shfl(b0, leader, 64);
+    b1 = __shfl(b1, leader, 64);
+    if (dest == 0) a.qbox[nxt][b0 + (unsigned)__popcll(m0 & below)] = q;
+    else if (dest == 1) a.qslow[nxt][b1 + (unsigned)__popcll(m1 & below)] = q;
+}
+
 // terminal state: exit ray in air, or a failure (black)
 __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const SceneDev& s, int status,
                                            const double r[3], const double p[3])
@@ -156,21 +196,21 @@ __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const S
     R.rgb[3 * q + 2] = c3[2];
 }
 
-// Walk through air from (r, p) and either finish the ray or set up its
-// in-box state and queue it.
-__device__ __forceinline__ void continue_in_air(const WfArgs& a, long long q, const SceneDev& s, double r[3],
-                                                double p[3], LaneCount& cnt, int* qnext, unsigned* qnext_len)
+// Walk through air from (r, p) and either finish the ray (returns -1) or
+// set up its in-box state (returns the box queue it goes to).
+__device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, const SceneDev& s, double r[3],
+                                               double p[3], LaneCount& cnt)
 {
     double mc = 1.0;
     int st = RS_OK;
     int ao = air_walk(s, a.o, r, p, cnt, &mc, &st);
     a.R.events[q] = cnt.events;
-    if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return; }
-    if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return; }
+    if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return -1; }
+    if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return -1; }
     Box64 b = box_enter64(s, a.o, r, p);
     store_box64(a, q, s, b);
     a.R.status[q] = RS_OK;
-    push(qnext, qnext_len, (int)q);
+    return box_dest(a, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,17 +220,16 @@ __global__ void __launch_bounds__(256) k_wf_reset(QCtr* c, int cur)
         c->box_head[cur] = 0;
         c->box_len[cur ^ 1] = 0;
         c->box_head[cur ^ 1] = 0;
+        c->slow_head[cur] = 0;
+        c->slow_len[cur ^ 1] = 0;
+        c->slow_head[cur ^ 1] = 0;
         c->ev_len = 0;
         c->ev_head = 0;
-        c->air_len = 0;
-        c->air_head = 0;
     }
 }
 
-__global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
+__device__ __forceinline__ int init_ray(const WfArgs& a, long long q)
 {
-    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.n_rays) return;
     int si = scene_of(a, q);
     const SceneDev s = a.scenes[si];
     double r[3], p[3];
@@ -208,11 +247,21 @@ __global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
         for (int k = 0; k < 3; ++k) r[k] = c.eye[k];
     }
     a.R.scene[q] = si;
+    a.R.flags[q] = 0;
     a.R.fbk[q] = 0;
     a.R.steps[q] = 0;
     a.R.rej[q] = 0;
     LaneCount cnt = {0, 0, 0, 0};
-    continue_in_air(a, q, s, r, p, cnt, a.qbox[0], &a.ctr->box_len[0]);
+    return continue_in_air(a, q, s, r, p, cnt);
+}
+
+// One lane per sample: camera (or given) ray, flight to the box.
+__global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int dest = -1;
+    if (q < a.n_rays) dest = init_ray(a, q);
+    push_box_wave(a, 0, dest, (int)q);
 }
 
 // In-box event location in FP32: regula falsi with the Illinois
@@ -224,28 +273,41 @@ __global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
 constexpr float kLocTol = 2.0e-7f;
 constexpr float kLocNoiseW = 2.4e-7f;
 constexpr int kLocMaxIt = 40;
-constexpr int kRefill = 8;
 
 // The hot kernel.  INTEG: 0 RK4, 1 DOPRI5.  Every iteration evaluates one
 // step per lane: a normal step of length h, or a trial of the location of
 // the event that the lane's last accepted step crossed (length theta h), so
 // that lanes locating an event do not hold the others up.
+//
+// Rays come from two queues, the slow one holding the box entries that are
+// predicted to take many steps.  A visit cannot be split, so the longest
+// visits set the length of the launch unless they start early and run
+// fast: every slow_div-th wave takes the slow queue first, and a wave that
+// holds slow rays raises its issue priority on its SIMD.
 template <int INTEG>
 __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
 {
-    const unsigned qlen = a.ctr->box_len[cur];
-    const int* queue = a.qbox[cur];
+    const unsigned qlen0 = a.ctr->box_len[cur], qlen1 = a.ctr->slow_len[cur];
     const int lane = threadIdx.x & 63;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const unsigned kRefill = (unsigned)a.sch.refill;
     const float rtol = (float)a.o.rtol, atol = (float)a.o.atol;
     const float hmax = (float)a.o.h_max, hmin = (float)a.o.h_min;
     const int max_steps = a.o.max_steps > 0x7fffffffll ? 0x7fffffff : (int)a.o.max_steps;
     const int max_ev = a.o.max_events;
 
     bool active = false;
-    // a wave that finds the queue already drained does not touch the counter
-    bool exhausted = *((volatile unsigned*)&a.ctr->box_head[cur]) >= qlen;
+    // a wave that finds a queue already drained does not touch its counter
+    bool ex0 = *((volatile unsigned*)&a.ctr->box_head[cur]) >= qlen0;
+    bool ex1 = *((volatile unsigned*)&a.ctr->slow_head[cur]) >= qlen1;
+    bool exhausted = ex0 && ex1;
+    // the queue this wave claims from (1: slow)
+    int src = (a.sch.slow_div > 0 && wave % a.sch.slow_div == 0) ? 1 : 0;
+    if (src == 1 ? ex1 : ex0) src ^= 1;
+    bool slow_ray = false, prio = false;
     int q = 0;
     const SceneDev* sp = a.scenes;
+    double s_hw = 0.0, s_L = 1.0;   // the lane's scene: half-width and period, kept in registers
     Sc32 c;
     float ytop = 0.f, xhi = 0.f, xlo = 0.f, pz = 0.f, h = 0.f, tau = 0.f, ltau = 0.f;
     St32 u;
@@ -266,21 +328,33 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             // claim in batches: one atomic per wave for at least kRefill lanes
             // (or for all of them once the wave has run dry)
             const unsigned long long busy = __ballot(active);
-            if (idle && (__popcll(idle) >= kRefill || busy == 0ull)) {
+            if (idle && ((unsigned)__popcll(idle) >= kRefill || busy == 0ull)) {
                 int n = __popcll(idle);
                 int leader = __ffsll((long long)idle) - 1;
+                const int from = src;
+                const unsigned qlen = from ? qlen1 : qlen0;
+                const int* queue = from ? a.qslow[cur] : a.qbox[cur];
                 unsigned base = 0;
-                if (lane == leader) base = atomicAdd(&a.ctr->box_head[cur], (unsigned)n);
+                if (lane == leader) base = atomicAdd(from ? &a.ctr->slow_head[cur] : &a.ctr->box_head[cur], (unsigned)n);
                 base = __shfl(base, leader, 64);
-                if (base + (unsigned)n >= qlen) exhausted = true;
+                if (base + (unsigned)n >= qlen) {
+                    // this queue is drained: the idle lanes left over claim
+                    // from the other one on the next iteration
+                    if (from) ex1 = true; else ex0 = true;
+                    exhausted = ex0 && ex1;
+                    src ^= 1;
+                }
                 if (!active) {
                     unsigned rank = __popcll(idle & ((1ull << lane) - 1ull));
                     unsigned qi = base + rank;
                     if (qi < qlen) {
                         q = queue[qi];
+                        slow_ray = from != 0;
                         const WfRays& R = a.R;
                         sp = a.scenes + R.scene[q];
                         const SceneDev& s = *sp;
+                        s_hw = s.hw;
+                        s_L = s.L;
                         c = make_sc32(s, a.o.wfb2);
                         ytop = (float)s.ytop;
                         mirror = s.mirror;
@@ -311,6 +385,13 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             }
         }
         if (__ballot(active) == 0ull) break;
+        {
+            const bool hp = __ballot(active && slow_ray) != 0ull;
+            if (hp != prio) {
+                prio = hp;
+                if (hp) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(0);
+            }
+        }
         if (!active) continue;
 
         int fin = -1;           // >= 0: the ray finishes with this status
@@ -338,8 +419,8 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             } else {
                 float xh = xhi, xl = xlo;
                 if (ue.cell != u.cell) {
-                    xh = (float)(sp->hw - (double)ue.cell * sp->L);
-                    xl = (float)(-sp->hw - (double)ue.cell * sp->L);
+                    xh = (float)(s_hw - (double)ue.cell * s_L);
+                    xl = (float)(-s_hw - (double)ue.cell * s_L);
                 }
                 float e[4];
                 ev_values32(c, ue, re, ytop, xh, xl, mirror, e);
@@ -390,7 +471,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                             lfin = false;
                             hacc = h;
                             hnx = hnext;
-                            th = (flo - fhi > 0.0f) ? flo / (flo - fhi) : 0.5f;
+                            th = (flo - fhi > 0.0f) ? flo * __builtin_amdgcn_rcpf(flo - fhi) : 0.5f;
                             if (!(th > 0.0f && th < 1.0f)) th = 0.5f;
                             loc = true;
                         }
@@ -427,10 +508,11 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                         } else if (!apply) {
                             float t;
                             if (side > 0 && hicode == 3 && flo <= kLocNoiseW) {
-                                const float sl = (fhi - flo) / (thi - tlo);
-                                t = tlo + fmaxf(2.0f * kLocNoiseW / fabsf(sl), kLocTol);
+                                const float sl = (fhi - flo) * __builtin_amdgcn_rcpf(thi - tlo);
+                                t = tlo + fmaxf(2.0f * kLocNoiseW * __builtin_amdgcn_rcpf(fabsf(sl)), kLocTol);
                             } else {
-                                t = (flo - fhi > 0.0f) ? (flo * thi - fhi * tlo) / (flo - fhi) : 0.5f * (tlo + thi);
+                                t = (flo - fhi > 0.0f) ? (flo * thi - fhi * tlo) * __builtin_amdgcn_rcpf(flo - fhi)
+                                                       : 0.5f * (tlo + thi);
                             }
                             if (lit >= 20 || !(t > tlo && t < thi)) t = 0.5f * (tlo + thi);
                             th = t;
@@ -510,7 +592,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
         } else {
             R.rx[q] = r[0]; R.ry[q] = r[1]; R.rz[q] = r[2];
             R.qx[q] = p3[0]; R.qy[q] = p3[1]; R.qz[q] = p3[2];
-            push(a.qair, &a.ctr->air_len, q);
+            R.flags[q] = WF_IN_AIR;
         }
         active = false;
         loc = false;
@@ -561,9 +643,9 @@ __device__ __forceinline__ int event_body(const WfArgs& a, long long q, const Sc
     return 1;
 }
 
-// Ray q in air (state in rx..qz): walk to the box (state stored, returns 0)
-// or finish it (returns 2).
-__device__ __forceinline__ int air_body(const WfArgs& a, long long q, const SceneDev& s)
+// Ray q in air (state in rx..qz): walk to the box (state stored, returns 0,
+// pin = the direction at the entry) or finish it (returns 2).
+__device__ __forceinline__ int air_body(const WfArgs& a, long long q, const SceneDev& s, double pin[3])
 {
     double r[3] = {a.R.rx[q], a.R.ry[q], a.R.rz[q]};
     double p[3] = {a.R.qx[q], a.R.qy[q], a.R.qz[q]};
@@ -577,6 +659,7 @@ __device__ __forceinline__ int air_body(const WfArgs& a, long long q, const Scen
     Box64 b = box_enter64(s, a.o, r, p);
     store_box64(a, q, s, b);
     a.R.status[q] = RS_OK;
+    pin[0] = p[0]; pin[1] = p[1]; pin[2] = p[2];
     return 0;
 }
 
@@ -585,27 +668,38 @@ template <int INTEG>
 __global__ void __launch_bounds__(256) k_wf_event(WfArgs a, int cur)
 {
     const unsigned qlen = a.ctr->ev_len;
-    int* qnext = a.qbox[cur ^ 1];
-    unsigned* qnext_len = &a.ctr->box_len[cur ^ 1];
-    for (unsigned qi = blockIdx.x * blockDim.x + threadIdx.x; qi < qlen; qi += gridDim.x * blockDim.x) {
-        const long long q = a.qev[qi];
-        const SceneDev s = a.scenes[a.R.scene[q]];
-        int r = event_body<INTEG>(a, q, s);
-        if (r == 0) push(qnext, qnext_len, (int)q);
-        else if (r == 1) push(a.qair, &a.ctr->air_len, (int)q);
+    // the loop bound is uniform over the wave, so that the pushes see every lane
+    for (unsigned base = blockIdx.x * blockDim.x; base < qlen; base += gridDim.x * blockDim.x) {
+        const unsigned qi = base + threadIdx.x;
+        int dest = -1, q = 0;
+        if (qi < qlen) {
+            q = a.qev[qi];
+            const SceneDev s = a.scenes[a.R.scene[q]];
+            int r = event_body<INTEG>(a, q, s);
+            // a visit that goes on in FP32 next round: the fast queue
+            if (r == 0) dest = 0;
+            else if (r == 1) a.R.flags[q] = WF_IN_AIR;
+        }
+        push_box_wave(a, cur ^ 1, dest, q);
     }
 }
 
-// Rays that left the box this round: walk through air (FP64).
+// Rays that left the box this round (flag WF_IN_AIR): walk through air
+// (FP64).  The rays are found by a scan of the flags, so that the in-box
+// kernel hands a ray over with a plain store.
 __global__ void __launch_bounds__(256) k_wf_air(WfArgs a, int cur)
 {
-    const unsigned qlen = a.ctr->air_len;
-    int* qnext = a.qbox[cur ^ 1];
-    unsigned* qnext_len = &a.ctr->box_len[cur ^ 1];
-    for (unsigned qi = blockIdx.x * blockDim.x + threadIdx.x; qi < qlen; qi += gridDim.x * blockDim.x) {
-        const long long q = a.qair[qi];
-        const SceneDev s = a.scenes[a.R.scene[q]];
-        if (air_body(a, q, s) == 0) push(qnext, qnext_len, (int)q);
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < a.n_rays;
+         base += (long long)gridDim.x * blockDim.x) {
+        const long long q = base + threadIdx.x;
+        int dest = -1;
+        if (q < a.n_rays && (a.R.flags[q] & WF_IN_AIR)) {
+            a.R.flags[q] = 0;
+            const SceneDev s = a.scenes[a.R.scene[q]];
+            double p[3];
+            if (air_body(a, q, s, p) == 0) dest = box_dest(a, p);
+        }
+        push_box_wave(a, cur ^ 1, dest, (int)q);
     }
 }
 

@@ -24,15 +24,20 @@ def exclusion_mask(orc, gpu_status, gpu_events, grazing=1e-6):
 def conditioning(O, sc, op, org, d, idx, delta):
     """Oracle's own sensitivity for rays idx: the largest change of its exit
     direction when the initial direction is perturbed by `delta` (two fixed
-    perpendicular perturbations)."""
+    perpendicular perturbations).  A perturbation that changes the ray's
+    status or its number of events changes the outcome itself: infinite."""
     idx = np.asarray(idx, dtype=np.int64)
     if idx.size == 0:
         return np.zeros(0)
-    base = O.trace_rays(sc, op, org[idx], d[idx])["dir"]
+    r0 = O.trace_rays(sc, op, org[idx], d[idx])
     kappa = np.zeros(idx.size)
     for v in (np.array([0.3, -0.7, 0.2]), np.array([-0.5, 0.1, 0.8])):
         dd = d[idx] + delta * v / np.linalg.norm(v)
-        kappa = np.maximum(kappa, angle(base, O.trace_rays(sc, op, org[idx], dd)["dir"]))
+        r = O.trace_rays(sc, op, org[idx], dd)
+        with np.errstate(invalid="ignore"):
+            k = angle(r0["dir"], r["dir"])
+        k[(r["status"] != r0["status"]) | (r["events"] != r0["events"]) | ~np.isfinite(k)] = np.inf
+        kappa = np.maximum(kappa, k)
     return kappa
 
 

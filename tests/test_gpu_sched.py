@@ -1,0 +1,64 @@
+"""Scheduling of the FP32 pipeline (gc_tune): the launch shape and queue
+policy decide only which lane integrates which ray and when, so every
+setting must give bit-identical images and counters."""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1012_5107_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1012_5107_amd import binding
+    return binding
+
+
+SETTINGS = [
+    dict(slow_pxy=0.0, slow_wave_div=0, refill=8, waves_per_simd=0),
+    dict(slow_pxy=0.25, slow_wave_div=4, refill=8, waves_per_simd=0),
+    dict(slow_pxy=0.3, slow_wave_div=1, refill=1, waves_per_simd=1),
+    dict(slow_pxy=1.0, slow_wave_div=0, refill=64, waves_per_simd=2),
+    dict(slow_pxy=0.2, slow_wave_div=3, refill=13, waves_per_simd=8),
+]
+
+
+@pytest.mark.parametrize("integ", ["rk4", "dopri5"])
+def test_render_identical_under_every_schedule(B, integ):
+    sc = W.scene(A=0.1, half_width=3.0)
+    cam = W.camera(96, 80, spp=2, jitter=True, seed=5)
+    op = W.opts("rk4", h=2e-3) if integ == "rk4" else W.opts("dopri5", rtol=1e-6)
+    ctx = B.Context(0)
+    try:
+        base_img, base_st = None, None
+        for s in SETTINGS:
+            got = ctx.tune(**s)
+            assert got == s
+            img, st = ctx.render(sc, cam, op, prec="f32")
+            torch.cuda.synchronize()
+            keys = ("rays", "accepted_steps", "rejected_steps", "events", "failed", "fallbacks", "fp64_steps")
+            if base_img is None:
+                base_img, base_st = img.clone(), {k: st[k] for k in keys}
+                assert base_st["accepted_steps"] > 0
+            else:
+                assert torch.equal(img, base_img), s
+                assert {k: st[k] for k in keys} == base_st, s
+    finally:
+        ctx.close()
+
+
+def test_tune_rejects_out_of_range(B):
+    ctx = B.Context(0)
+    try:
+        default = ctx.tune()
+        for bad in (dict(slow_pxy=-0.1), dict(slow_pxy=1.5), dict(slow_wave_div=-1), dict(refill=0),
+                    dict(refill=65), dict(waves_per_simd=9), dict(waves_per_simd=-1)):
+            with pytest.raises(B.GcError):
+                ctx.tune(**bad)
+            assert ctx.tune() == default
+    finally:
+        ctx.close()
