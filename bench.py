@@ -13,7 +13,11 @@ Workloads (--workload):
 
 One step = render the cloaked image(s) (FP32 path), render the flat-mirror
 reference(s) and correlate them (eqs. (14)-(15)).  Inputs are synthetic and
-resident on the GPU before the timed region.  Prints one JSON line.
+resident on the GPU before the timed region.  Before the timed region the
+FP32 pipeline is autotuned for the workload (step cap h_max and scheduling,
+within the accuracy bounds against the FP64 path); the headline value is
+rays/s of the tuned path, and the configured step cap is measured too.
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
                     [--no-cpu] [--no-fp64]
@@ -38,6 +42,10 @@ FLOP_PER_STEP = {"dopri5": 680.0, "rk4": 354.0}
 # Jacobian applied: four stage Jacobians of the field (~113 FLOP each from
 # W), the stage rebuild (~33) and the adjoint combinations (~30)
 FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
+# HBM bytes per launch of the in-cloak kernel on the 512 x 512 x 4 workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
+# size; keyed by (h_max, integrator); absent: not measured for this kernel
+TRAFFIC_K_WF_BOX = {}
 
 
 def parse():
@@ -92,51 +100,52 @@ def main():
     ref = torch.empty_like(img)
     stream = torch.cuda.current_stream()
 
-    # counters of one pass (outside the timed region)
-    _, st32 = ctx.render(sc, cam, op32, prec="f32", out=img)
-    ctx.render(ref_sc, cam, op32, prec="f32", out=ref)
-    c32, ncc32 = ctx.cross_correlate(img, ref)
-    print(f"# fp32 pass: {st32}", file=sys.stderr, flush=True)
+    def timed(op, steps):
+        """Whole job per step: FP32 render, flat reference, correlation."""
+        for _ in range(args.warmup):
+            ctx.render(sc, cam, op, prec="f32", out=img, stats=False)
+            ctx.render(ref_sc, cam, op, prec="f32", out=ref, stats=False)
+            ctx.cross_correlate(img, ref)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.render(sc, cam, op, prec="f32", out=img, stats=False)
+            ctx.render(ref_sc, cam, op, prec="f32", out=ref, stats=False)
+            ctx.cross_correlate(img, ref)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        # counters and the in-cloak kernel's device time (HIP events recorded
+        # by the library around each of its launches on this stream)
+        _, st = ctx.render(sc, cam, op, prec="f32", out=img)
+        c, _ = ctx.cross_correlate(img, ref)
+        return dt, st, c
 
-    def step():
-        ctx.render(sc, cam, op32, prec="f32", out=img, stats=False)
-        ctx.render(ref_sc, cam, op32, prec="f32", out=ref, stats=False)
-        return ctx.cross_correlate(img, ref)
+    def roofline(st, op):
+        achieved = st["hot_steps"] * FLOP_PER_STEP[op["integrator"]] / (st["hot_ms"] * 1e-3)
+        return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32, "traffic": TRAFFIC_K_WF_BOX.get((op["h_max"], op["integrator"])),
+                "kernel": "k_wf_box<DOPRI5>" if op["integrator"] == "dopri5" else "k_wf_box<RK4>",
+                "kernel_ms": st["hot_ms"], "kernel_steps": st["hot_steps"]}
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kernel_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        ctx.render(sc, cam, op32, prec="f32", out=img, stats=False)
-        e1.record(stream)
-        ctx.render(ref_sc, cam, op32, prec="f32", out=ref, stats=False)
-        ctx.cross_correlate(img, ref)
-        e1.synchronize()
-        kernel_ms.append(e0.elapsed_time(e1))   # the whole FP32 render
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    print(f"# fp32 step {dt * 1e3:.1f} ms, FP32 render {np.mean(kernel_ms):.1f} ms", file=sys.stderr, flush=True)
+    # the configured step control with the default scheduling
+    ctx.tune(**B.default_tune())
+    dt0, st0, c0 = timed(op32, 1)
+    print(f"# configured (h_max {op32['h_max']}): {dt0 * 1e3:.1f} ms, {st0}", file=sys.stderr, flush=True)
 
-    steps32 = st32["accepted_steps"]
+    # autotuned step cap and scheduling (outside the timed region)
+    ta = time.perf_counter()
+    tuned, rep = ctx.autotune(sc, cam, op32)
+    ta = time.perf_counter() - ta
+    print(f"# autotune {ta:.2f} s: h_max {tuned['h_max']}, tune {rep['tune']}", file=sys.stderr, flush=True)
+
+    dt, st32, c32 = timed(tuned, args.steps)
     rays = st32["rays"]
-    value = steps32 / dt
-    # dominant kernel: the FP32 in-cloak kernel; its device time comes from
-    # HIP events recorded by the library around each of its launches on this
-    # stream, and its work is the steps it took (the rest were taken by the
-    # FP64 event kernel)
-    _, stk = ctx.render(sc, cam, op32, prec="f32", out=img)
-    hot_steps = stk["hot_steps"]
-    k_ms = stk["hot_ms"]
-    achieved = hot_steps * FLOP_PER_STEP[op32["integrator"]] / (k_ms * 1e-3)
+    print(f"# tuned: {dt * 1e3:.1f} ms per step, {st32}", file=sys.stderr, flush=True)
 
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
-        "value": value,
-        "unit": "ray-steps/s",
+        "value": rays / dt,
+        "unit": "rays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -147,28 +156,28 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "512x512, 4 jittered spp, Lambda=1, A=0.1, cloak |x|<=4, y<=1.5, DOPRI5",
-                   "rtol_fp32": op32["rtol"], "rtol_fp64": op64["rtol"], "rays": rays,
-                   "ray_steps": steps32},
-        "rays_per_s": rays / dt,
+                   "rtol_fp32": tuned["rtol"], "h_max_fp32": tuned["h_max"], "rtol_fp64": op64["rtol"],
+                   "h_max_fp64": op64["h_max"], "schedule": rep["tune"], "rays": rays,
+                   "ray_steps": st32["accepted_steps"]},
+        "ray_steps_per_s": st32["accepted_steps"] / dt,
         "cc_fp32": c32,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_wf_box<DOPRI5>" if op32["integrator"] == "dopri5" else "k_wf_box<RK4>",
-                     "kernel_ms": k_ms, "kernel_steps": hot_steps},
-        "fp32_breakdown": {"hot_ms": stk["hot_ms"], "event_ms": stk["event_ms"], "tail_ms": stk["tail_ms"],
-                           "total_ms": stk["total_ms"], "rounds": stk["rounds"], "tail_rays": stk["tail_rays"],
-                           "fp64_steps": stk["fp64_steps"], "fallbacks": stk["fallbacks"],
-                           "failed": stk["failed"]},
+        "roofline": roofline(st32, tuned),
+        "fp32_breakdown": {k: st32[k] for k in ("hot_ms", "event_ms", "total_ms", "rounds", "fp64_steps",
+                                                  "fallbacks", "failed")},
+        "autotune": {"seconds": ta, "chosen_h_max": tuned["h_max"], "tune": rep["tune"],
+                     "tune_ms": rep["tune_ms"], "cal_rays": rep["cal_rays"], "ill_rays": rep["ill_rays"],
+                     "candidates": [{k: c[k] for k in ("h_max", "ms", "steps", "dir_p99", "dir_max", "changed",
+                                                       "cc_err", "passed")} for c in rep["candidates"]]},
+        "configured": {"h_max": op32["h_max"], "rays_per_s": st0["rays"] / dt0,
+                       "ray_steps_per_s": st0["accepted_steps"] / dt0, "ms": dt0 * 1e3,
+                       "roofline": roofline(st0, op32), "cc_fp32": c0},
     }
 
     if not args.no_fp64:
         # FP64 plain path on the same workload: one timed pass
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
         img64, st64 = ctx.render(sc, cam, op64, prec="f64")
-        e1.record(stream)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
         ref64, _ = ctx.render(ref_sc, cam, op64, prec="f64")
@@ -178,34 +187,15 @@ def main():
                              "achieved_tflops": st64["accepted_steps"] * FLOP_PER_STEP["dopri5"] / t64 / 1e12,
                              "frac_fp64_peak": st64["accepted_steps"] * FLOP_PER_STEP["dopri5"] / t64 / PEAK_FP64}
         out["cc_error_fp32_vs_fp64"] = abs(c32 - c64)
+        out["cc_error_fp32_configured_vs_fp64"] = abs(c0 - c64)
         out["speedup_rays_fp32_vs_fp64"] = (rays / dt) / (st64["rays"] / t64)
         d = (img - img64).abs().amax(dim=-1)
         out["rgb_error_fp32_vs_fp64"] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt())}
 
     if not args.no_cpu:
         from oracle import oracle as O
-        npix = 64
-        sample = None
-        while True:
-            pix = W.sample_pixels(Wd, H, npix, seed=11)
-            t2 = time.perf_counter()
-            _, cnt = O.render(sc, cam, op64, pixels=pix)
-            tc = time.perf_counter() - t2
-            sample = (npix, cnt, tc)
-            if tc > args.cpu_seconds / 4 or npix >= Wd * H:
-                break
-            npix = min(Wd * H, int(npix * max(2.0, min(8.0, args.cpu_seconds / max(tc, 1e-3)))))
-        npix, cnt, tc = sample
-        threads = os.cpu_count()
-        try:
-            threads = len(os.sched_getaffinity(0))
-        except AttributeError:
-            pass
-        out["cpu_baseline"] = {"value": cnt["steps"] / tc, "unit": "ray-steps/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"{npix} seeded pixels x 4 spp of the same workload (FP64 DOPRI5 rtol 1e-8), "
-                                         f"{cnt['rays']} rays, {cnt['steps']} ray-steps in {tc:.1f} s",
-                               "rays_per_s": cnt["rays"] / tc}
+        out["cpu_baseline"] = _cpu_baseline(O, sc, cam, op64, W, args.cpu_seconds,
+                                            "the same workload (FP64 DOPRI5 rtol 1e-8)")
     print(json.dumps(out), flush=True)
 
 
@@ -224,9 +214,9 @@ def _cpu_baseline(O, sc, cam, op, W, seconds, label):
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         threads = os.cpu_count()
-    return {"value": cnt["steps"] / tc, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
+    return {"value": cnt["rays"] / tc, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{npix} seeded pixels x {cam['spp']} spp of {label}, {cnt['rays']} rays, "
-                      f"{cnt['steps']} ray-steps in {tc:.1f} s", "rays_per_s": cnt["rays"] / tc}
+                      f"{cnt['steps']} ray-steps in {tc:.1f} s", "ray_steps_per_s": cnt["steps"] / tc}
 
 
 def main_batch(args):
@@ -242,6 +232,12 @@ def main_batch(args):
     dev = torch.device("cuda", 0)
     imgs = [torch.empty((c["height"], c["width"], 3), dtype=torch.float32, device=dev) for c in cams]
     refs = [ctx.render(W.reference_scene(s), c, op32, prec="f32")[0] for s, c in zip(scenes, cams)]
+    # step cap tuned on the whole batch (calibration at 1/8 and 1/4 of each
+    # camera's resolution, one timing per candidate), outside the timed region
+    ta = time.perf_counter()
+    op32, rep = ctx.autotune(scenes, cams, op32, dir_scale=8, cc_scale=4, reps=1, tune_sched=0)
+    ta = time.perf_counter() - ta
+    print(f"# autotune {ta:.1f} s: h_max {op32['h_max']}", file=sys.stderr, flush=True)
     _, c0, st = ctx.render_batch(scenes, cams, op32, refs=refs, outs=imgs)
     print(f"# batch pass: {st}", file=sys.stderr, flush=True)
 
@@ -261,18 +257,22 @@ def main_batch(args):
     achieved = stk["hot_steps"] * FLOP_PER_STEP["dopri5"] / (stk["hot_ms"] * 1e-3)
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
-        "value": st["accepted_steps"] / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps,
+        "value": st["rays"] / dt, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "64 scenes (seed 1012): A~U[0.02,0.15], half-width~U[2,8], res in {256,512,1024}^2, "
                                "az~U[-60,60], el~U[15,60] deg, 4 spp, DOPRI5, one launch",
-                   "rtol_fp32": op32["rtol"], "rays": st["rays"], "ray_steps": st["accepted_steps"]},
-        "rays_per_s": st["rays"] / dt,
+                   "rtol_fp32": op32["rtol"], "h_max_fp32": op32["h_max"], "rays": st["rays"],
+                   "ray_steps": st["accepted_steps"]},
+        "ray_steps_per_s": st["accepted_steps"] / dt,
+        "autotune": {"seconds": ta, "chosen_h_max": op32["h_max"],
+                     "candidates": [{k: c[k] for k in ("h_max", "ms", "steps", "dir_p99", "dir_max", "changed",
+                                                       "cc_err", "passed")} for c in rep["candidates"]]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_wf_box<DOPRI5>",
                      "kernel_ms": stk["hot_ms"], "kernel_steps": stk["hot_steps"]},
-        "fp32_breakdown": {k: stk[k] for k in ("hot_ms", "event_ms", "tail_ms", "total_ms", "rounds", "tail_rays",
-                                               "fp64_steps", "fallbacks", "failed")},
+        "fp32_breakdown": {k: stk[k] for k in ("hot_ms", "event_ms", "total_ms", "rounds", "fp64_steps",
+                                               "fallbacks", "failed")},
     }
     if not args.no_fp64:
         torch.cuda.synchronize()
@@ -317,12 +317,12 @@ def main_stress(args):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     out = {"metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
-           "value": st["accepted_steps"] / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps,
+           "value": st["rays"] / dt, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
            "warmup": 0, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "1024x1024, 8 spp, A=0.15 (Ak=0.94), elevation 10 deg at distance 12, DOPRI5",
                       "rtol_fp32": op32["rtol"], "rays": st["rays"], "ray_steps": st["accepted_steps"]},
-           "rays_per_s": st["rays"] / dt, "cc_fp32": c32, "fp32_counters": stk}
+           "ray_steps_per_s": st["accepted_steps"] / dt, "cc_fp32": c32, "fp32_counters": stk}
     print(json.dumps(out), flush=True)
 
 

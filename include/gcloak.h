@@ -186,6 +186,75 @@ void gc_default_tune(gc_tune* tune);
 gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* tune);
 gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* tune);
 
+/* Autotuner of the FP32 pipeline: the DOPRI5 step cap h_max and the
+ * scheduling (gc_tune), picked for a workload (one or more scenes with
+ * their cameras) subject to accuracy bounds against the FP64 path.
+ *
+ * Reference: the FP64 path with the same options except prec = GC_F64 and
+ * rtol = atol = ref_rtol (the FP64 path follows the CPU oracle to
+ * rounding).  Checks, per scene:
+ *   - exit directions of the camera's rays at width / dir_scale x
+ *     height / dir_scale (same spp, jitter and seed): rays whose FP64 exit
+ *     moves by more than dir_tol when the initial direction moves by 1e-6
+ *     (two fixed perpendicular perturbations), or whose status or event
+ *     count then changes, are ill-conditioned and not compared; of the
+ *     others, the fraction whose status or event count differs from the
+ *     reference must be at most max_changed, and the rest must have their
+ *     99th percentile angle error at most dir_tol and their maximum at most
+ *     50 dir_tol;
+ *   - the zero-shift correlation C0 (eq. (15)) of the image at
+ *     width / cc_scale x height / cc_scale against the flat-mirror
+ *     reference must be within cc_tol of the FP64 image's.
+ * Step-cap candidates: h_max x {1, 2.5, 5, 10, 25} (DOPRI5; RK4 keeps its
+ * step).  Of the candidates that pass, the one with the shortest FP32
+ * render of the whole workload is chosen (best of `reps`); then, if
+ * tune_sched, a fixed set of gc_tune settings is timed the same way and the
+ * fastest is installed in the context.  Results never depend on gc_tune. */
+typedef struct {
+    int32_t dir_scale;     /* default 4 */
+    int32_t cc_scale;      /* default 1 */
+    double dir_tol;        /* default 1e-4 rad */
+    double cc_tol;         /* default 1e-4 */
+    double max_changed;    /* default 0.01 */
+    double ref_rtol;       /* default 1e-8 */
+    int32_t reps;          /* default 2 */
+    int32_t tune_sched;    /* default 1 */
+} gc_autotune_opts;
+
+#define GC_AUTOTUNE_MAX_CAND 8
+
+typedef struct {
+    double h_max;
+    double ms;             /* best FP32 render time of the workload (HIP events) */
+    int64_t steps;         /* FP32 accepted steps of the workload */
+    double dir_p99, dir_max, changed, cc_err;   /* worst over the scenes */
+    int32_t pass;          /* all bounds hold */
+    int32_t reserved;
+} gc_autotune_cand;
+
+typedef struct {
+    int32_t n_cand;
+    int32_t chosen;        /* index of the chosen candidate, -1 if none passed (opts_out = opts) */
+    gc_autotune_cand cand[GC_AUTOTUNE_MAX_CAND];
+    gc_tune tune;          /* installed scheduling */
+    double tune_ms;        /* its best render time */
+    double base_tune_ms;   /* the render time with the context's scheduling on entry */
+    int64_t cal_rays;      /* rays of the direction check (all scenes) */
+    int64_t ill_rays;      /* of them ill-conditioned in FP64 */
+} gc_autotune_report;
+
+void gc_default_autotune_opts(gc_autotune_opts* at);
+
+/* Run the autotuner (see above) on n_scenes scenes and cameras with FP32
+ * options `opts` (prec must be GC_F32).  Writes the tuned options to
+ * opts_out (equal to opts but for h_max) and, if `report` is non-null, the
+ * measurements.  Device scratch for the calibration is allocated and freed
+ * inside the call; the stream is synchronised.  GC_EINVAL for bad
+ * arguments, GC_EUNSUPPORTED for prec != GC_F32. */
+gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                      const gc_opts* opts, const gc_autotune_opts* at, gc_opts* opts_out,
+                      gc_autotune_report* report, hipStream_t stream);
+
 /* Trace n rays (Sec. 3) from origins d_org and directions d_dir (n x 3
  * doubles, row-major; directions need not be unit) until they escape.
  * Outputs: exit point (where the ray left its last surface) and unit exit

@@ -68,10 +68,40 @@ class Tune(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class AutotuneOpts(ctypes.Structure):
+    _fields_ = [("dir_scale", ctypes.c_int32), ("cc_scale", ctypes.c_int32), ("dir_tol", ctypes.c_double),
+                ("cc_tol", ctypes.c_double), ("max_changed", ctypes.c_double), ("ref_rtol", ctypes.c_double),
+                ("reps", ctypes.c_int32), ("tune_sched", ctypes.c_int32)]
+
+
+AUTOTUNE_MAX_CAND = 8
+
+
+class AutotuneCand(ctypes.Structure):
+    _fields_ = [("h_max", ctypes.c_double), ("ms", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("dir_p99", ctypes.c_double), ("dir_max", ctypes.c_double), ("changed", ctypes.c_double),
+                ("cc_err", ctypes.c_double), ("pass_", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class AutotuneReport(ctypes.Structure):
+    _fields_ = [("n_cand", ctypes.c_int32), ("chosen", ctypes.c_int32), ("cand", AutotuneCand * AUTOTUNE_MAX_CAND),
+                ("tune", Tune), ("tune_ms", ctypes.c_double), ("base_tune_ms", ctypes.c_double),
+                ("cal_rays", ctypes.c_int64), ("ill_rays", ctypes.c_int64)]
+
+    def as_dict(self):
+        cands = []
+        for i in range(self.n_cand):
+            c = self.cand[i]
+            cands.append(dict(h_max=c.h_max, ms=c.ms, steps=int(c.steps), dir_p99=c.dir_p99, dir_max=c.dir_max,
+                              changed=c.changed, cc_err=c.cc_err, passed=bool(c.pass_)))
+        return dict(candidates=cands, chosen=int(self.chosen), tune=self.tune.as_dict(), tune_ms=self.tune_ms,
+                    base_tune_ms=self.base_tune_ms, cal_rays=int(self.cal_rays), ill_rays=int(self.ill_rays))
+
+
 # every symbol the header declares
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
            "gc_render_batch", "gc_render_grad", "gc_cross_correlate", "gc_default_tune", "gc_set_tune",
-           "gc_get_tune"]
+           "gc_get_tune", "gc_default_autotune_opts", "gc_autotune"]
 
 _lib = None
 
@@ -115,6 +145,11 @@ def load():
     L.gc_set_tune.restype = ctypes.c_int
     L.gc_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
     L.gc_get_tune.restype = ctypes.c_int
+    L.gc_default_autotune_opts.argtypes = [ctypes.POINTER(AutotuneOpts)]
+    L.gc_default_autotune_opts.restype = None
+    L.gc_autotune.argtypes = [vp, i32, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts),
+                              ctypes.POINTER(AutotuneOpts), ctypes.POINTER(Opts), ctypes.POINTER(AutotuneReport), vp]
+    L.gc_autotune.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -214,6 +249,32 @@ class Context:
             _check(L.gc_set_tune(self._h, ctypes.byref(t)))
         return t.as_dict()
 
+    def autotune(self, scenes, cameras, opts, stream=None, **at_kw):
+        """Autotune the FP32 pipeline for a workload (one scene/camera dict or
+        lists of them): returns (tuned opts dict, report dict).  The chosen
+        scheduling is installed in this context.  Keyword arguments set
+        gc_autotune_opts fields (dir_scale, cc_scale, dir_tol, cc_tol,
+        max_changed, ref_rtol, reps, tune_sched)."""
+        L = load()
+        if isinstance(scenes, dict):
+            scenes, cameras = [scenes], [cameras]
+        n = len(scenes)
+        sc_arr = (Scene * n)(*[make_scene(s) for s in scenes])
+        cam_arr = (Camera * n)(*[make_camera(c) for c in cameras])
+        op = make_opts(opts, "f32")
+        at = AutotuneOpts()
+        L.gc_default_autotune_opts(ctypes.byref(at))
+        for k, v in at_kw.items():
+            if k not in dict(AutotuneOpts._fields_):
+                raise KeyError(k)
+            setattr(at, k, v)
+        out = Opts()
+        rep = AutotuneReport()
+        _check(L.gc_autotune(self._h, n, sc_arr, cam_arr, ctypes.byref(op), ctypes.byref(at), ctypes.byref(out),
+                             ctypes.byref(rep), _stream_handle(stream)))
+        tuned = dict(opts, h_max=out.h_max, rtol=out.rtol, atol=out.atol)
+        return tuned, rep.as_dict()
+
     def render(self, scene, camera, opts, prec="f64", out=None, stats=True, stream=None):
         """Render an H x W x 3 float32 image on the device.  Returns
         (image, stats dict or None)."""
@@ -280,6 +341,13 @@ class Context:
 
 
 _default = {}
+
+
+def default_tune():
+    """gc_tune defaults as a dict."""
+    t = Tune()
+    load().gc_default_tune(ctypes.byref(t))
+    return t.as_dict()
 
 
 def context(device=0):

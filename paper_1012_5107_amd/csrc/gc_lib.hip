@@ -1122,3 +1122,5 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
 }
 
 }  // extern "C"
+
+#include "gc_autotune.hpp"

@@ -31,15 +31,18 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_1012_5107_amd import binding as B
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gcloak.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gc_scene), sizeof(gc_camera),'
-                   ' sizeof(gc_opts), sizeof(gc_stats), offsetof(gc_camera, seed), offsetof(gc_opts, max_steps));'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gc_scene),'
+                   ' sizeof(gc_camera), sizeof(gc_opts), sizeof(gc_stats), offsetof(gc_camera, seed),'
+                   ' offsetof(gc_opts, max_steps), sizeof(gc_tune), sizeof(gc_autotune_opts),'
+                   ' sizeof(gc_autotune_cand), sizeof(gc_autotune_report), offsetof(gc_autotune_report, tune));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
                            "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(B.Scene), ctypes.sizeof(B.Camera), ctypes.sizeof(B.Opts), ctypes.sizeof(B.Stats),
-            B.Camera.seed.offset, B.Opts.max_steps.offset]
+            B.Camera.seed.offset, B.Opts.max_steps.offset, ctypes.sizeof(B.Tune), ctypes.sizeof(B.AutotuneOpts),
+            ctypes.sizeof(B.AutotuneCand), ctypes.sizeof(B.AutotuneReport), B.AutotuneReport.tune.offset]
     assert got == want
 
 

@@ -62,3 +62,44 @@ def test_tune_rejects_out_of_range(B):
             assert ctx.tune() == default
     finally:
         ctx.close()
+
+
+def test_autotune_small_workload(B):
+    """The autotuner keeps every option but h_max, reports the candidates it
+    measured, chooses one that passed its own bounds, and installs the
+    fastest scheduling; an image rendered with the tuned options stays within
+    the correlation bound of the FP64 path.  At 96 x 80 pixels two correct
+    integrations differ in C0 by up to ~3e-4 (a handful of pixels at
+    discontinuities of the view flip), so the correlation bound here is 1e-3;
+    the full-size workloads meet 1e-4."""
+    sc = W.scene(A=0.1, half_width=3.0)
+    cam = W.camera(96, 80, spp=2, jitter=True, seed=5)
+    op = W.opts("dopri5", rtol=1e-7)
+    ctx = B.Context(0)
+    try:
+        tuned, rep = ctx.autotune(sc, cam, op, dir_scale=2, reps=1, cc_tol=1e-3)
+        print("[autotune]", rep, flush=True)
+        assert {k: v for k, v in tuned.items() if k != "h_max"} == {k: v for k, v in op.items() if k != "h_max"}
+        assert len(rep["candidates"]) == 5
+        assert [c["h_max"] for c in rep["candidates"]] == pytest.approx([op["h_max"] * f for f in (1, 2.5, 5, 10, 25)])
+        assert rep["cal_rays"] == 48 * 40 * 2
+        ch = rep["chosen"]
+        assert ch >= 0, "the configured step cap should pass its own bounds"
+        assert rep["candidates"][ch]["passed"]
+        assert tuned["h_max"] == rep["candidates"][ch]["h_max"]
+        assert all(c["ms"] >= rep["candidates"][ch]["ms"] for c in rep["candidates"] if c["passed"])
+        assert ctx.tune() == rep["tune"]
+        assert rep["tune_ms"] <= rep["base_tune_ms"]
+        ref_sc = W.reference_scene(sc)
+        g64, _ = ctx.render(sc, cam, dict(op, rtol=1e-8, atol=1e-8), prec="f64")
+        f64, _ = ctx.render(ref_sc, cam, dict(op, rtol=1e-8, atol=1e-8), prec="f64")
+        g32, _ = ctx.render(sc, cam, tuned, prec="f32")
+        c64 = ctx.cross_correlate(g64, f64)[0]
+        c32 = ctx.cross_correlate(g32, f64)[0]
+        assert abs(c32 - c64) <= 1e-3
+        with pytest.raises(B.GcError):
+            ctx.autotune(sc, cam, op, reps=0)
+        with pytest.raises(B.GcError):
+            ctx.autotune(ref_sc, cam, op)
+    finally:
+        ctx.close()
