@@ -186,6 +186,31 @@ void gc_default_tune(gc_tune* tune);
 gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* tune);
 gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* tune);
 
+/* Batched FP32 render as one HIP graph (S7: one launch for many scenes and
+ * their correlations).  gc_batch_plan_create renders the workload once
+ * eagerly (which fixes the number of pipeline rounds it needs: every ray's
+ * path is deterministic), then captures, on a stream of its own: the
+ * counters' reset (a kernel, no memset node), the flight of every camera
+ * ray to the box, that many rounds of the in-box / FP64 / air kernels, the
+ * pixel averages into d_rgb[i], and, when d_ref is non-null, for each
+ * scene the flat-mirror reference into d_ref[i] (if render_refs) and the
+ * zero-shift correlation C0 (eq. (15)) of d_rgb[i] against d_ref[i].  The
+ * plan owns its pipeline buffers (the context's are not touched) and keeps
+ * the image pointers and the context's gc_tune of the moment: the images
+ * must stay allocated while the plan lives.  Launch replays the graph on a
+ * stream (asynchronous); results synchronises that stream and returns
+ * C0[n_scenes] and the counters (total_ms from HIP events around the
+ * replay; hot_ms, event_ms are 0).  GC_EUNSUPPORTED for prec != GC_F32 or
+ * a flat-mirror scene; GC_EDEVICE if the replay left rays unfinished (the
+ * workload changed under the plan). */
+typedef struct gc_batch_plan gc_batch_plan;
+gc_status gc_batch_plan_create(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                               const gc_opts* opts, float* const* d_rgb, float* const* d_ref, int32_t render_refs,
+                               gc_batch_plan** out);
+gc_status gc_batch_plan_launch(gc_batch_plan* plan, hipStream_t stream);
+gc_status gc_batch_plan_results(gc_batch_plan* plan, double* C0, gc_stats* stats, hipStream_t stream);
+void gc_batch_plan_destroy(gc_batch_plan* plan);
+
 /* Autotuner of the FP32 pipeline: the DOPRI5 step cap h_max and the
  * scheduling (gc_tune), picked for a workload (one or more scenes with
  * their cameras) subject to accuracy bounds against the FP64 path.

@@ -101,7 +101,8 @@ class AutotuneReport(ctypes.Structure):
 # every symbol the header declares
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
            "gc_render_batch", "gc_render_grad", "gc_cross_correlate", "gc_default_tune", "gc_set_tune",
-           "gc_get_tune", "gc_default_autotune_opts", "gc_autotune"]
+           "gc_get_tune", "gc_default_autotune_opts", "gc_autotune", "gc_batch_plan_create", "gc_batch_plan_launch",
+           "gc_batch_plan_results", "gc_batch_plan_destroy"]
 
 _lib = None
 
@@ -150,6 +151,15 @@ def load():
     L.gc_autotune.argtypes = [vp, i32, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts),
                               ctypes.POINTER(AutotuneOpts), ctypes.POINTER(Opts), ctypes.POINTER(AutotuneReport), vp]
     L.gc_autotune.restype = ctypes.c_int
+    L.gc_batch_plan_create.argtypes = [vp, i32, ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Opts),
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    L.gc_batch_plan_create.restype = ctypes.c_int
+    L.gc_batch_plan_launch.argtypes = [vp, vp]
+    L.gc_batch_plan_launch.restype = ctypes.c_int
+    L.gc_batch_plan_results.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Stats), vp]
+    L.gc_batch_plan_results.restype = ctypes.c_int
+    L.gc_batch_plan_destroy.argtypes = [vp]
+    L.gc_batch_plan_destroy.restype = None
     _lib = L
     return L
 
@@ -307,6 +317,11 @@ class Context:
                                       _stream_handle(stream)))
         return imgs, (list(c0) if c0 is not None else None), st.as_dict()
 
+    def batch_plan(self, scenes, cameras, opts, outs, refs=None, render_refs=True):
+        """Capture a batched FP32 render (and, with refs, the flat-mirror
+        references and C0 per scene) as one HIP graph: see BatchPlan."""
+        return BatchPlan(self, scenes, cameras, opts, outs, refs, render_refs)
+
     def render_grad(self, scene, camera, opts, ref, prec="f64", loss="ncc", checkpoint_every=64, out=None,
                     sample_dm=False, stream=None):
         """Loss 1 - NCC (loss="ncc") or 1 - C0 of eq. (15) (loss="c0")
@@ -341,6 +356,49 @@ class Context:
 
 
 _default = {}
+
+
+class BatchPlan:
+    """A batched FP32 render captured as one HIP graph (gc_batch_plan): the
+    images (and flat-mirror references, when refs are given with
+    render_refs) are device tensors the plan writes on every launch."""
+
+    def __init__(self, ctx, scenes, cameras, opts, outs, refs=None, render_refs=True):
+        L = load()
+        n = len(scenes)
+        self.n = n
+        self.outs, self.refs = list(outs), (list(refs) if refs is not None else None)
+        sc_arr = (Scene * n)(*[make_scene(s) for s in scenes])
+        cam_arr = (Camera * n)(*[make_camera(c) for c in cameras])
+        op = make_opts(opts, "f32")
+        rgb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.outs])
+        ref = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.refs]) if self.refs is not None else None
+        h = ctypes.c_void_p()
+        _check(L.gc_batch_plan_create(ctx._h, n, sc_arr, cam_arr, ctypes.byref(op), rgb, ref,
+                                      int(bool(render_refs and refs is not None)), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().gc_batch_plan_launch(self._h, _stream_handle(stream)))
+
+    def results(self, stream=None):
+        """(C0 list or None, stats dict); synchronises the stream."""
+        c0 = (ctypes.c_double * self.n)()
+        st = Stats()
+        _check(load().gc_batch_plan_results(self._h, c0 if self.refs is not None else None, ctypes.byref(st),
+                                            _stream_handle(stream)))
+        return (list(c0) if self.refs is not None else None), st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gc_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def default_tune():

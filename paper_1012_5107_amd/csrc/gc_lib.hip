@@ -632,15 +632,25 @@ static void wf_carve(void* base, long long n, WfRays& R)
     R.rgb = (float*)take(sizeof(float) * 3 * n);
 }
 
+static void wf_free(WfStore& w)
+{
+    void* bufs[] = {w.rays, w.queues, w.tables, w.ctr, w.tot};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (w.h_ctr) (void)hipHostFree(w.h_ctr);
+    for (hipEvent_t e : w.ev)
+        if (e) (void)hipEventDestroy(e);
+    w = WfStore();
+}
+
 static size_t wf_table_bytes(int ns)
 {
     return (size_t)ns * (sizeof(SceneDev) + sizeof(CamDev) + sizeof(float*)) + (size_t)(ns + 1) * 2 * sizeof(long long) +
            1024;
 }
 
-static gc_status wf_reserve(gc_ctx* ctx, long long n_rays, int n_scenes)
+static gc_status wf_reserve(gc_ctx* ctx, WfStore& w, long long n_rays, int n_scenes)
 {
-    WfStore& w = ctx->wf;
     if (!w.ctr) {
         if (hipMalloc(&w.ctr, sizeof(QCtr)) != hipSuccess || hipMalloc(&w.tot, sizeof(WfTotals)) != hipSuccess ||
             hipHostMalloc(&w.h_ctr, sizeof(QCtr)) != hipSuccess)
@@ -700,10 +710,44 @@ static WfTables wf_tables(void* base, int ns)
     return t;
 }
 
-// Run the pipeline for a filled WfArgs (tables already on the device).
-static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
+// persistent grid of the in-box kernel under the context's scheduling
+static unsigned wf_box_max(const gc_ctx* ctx, const WfStore& w, int integ)
 {
-    WfStore& w = ctx->wf;
+    int box_max = w.box_blocks[integ];
+    if (ctx->tune.waves_per_simd > 0) box_max = std::min(box_max, ctx->tune.waves_per_simd * ctx->n_cu);
+    return (unsigned)box_max;
+}
+
+// One round: the in-box kernel takes every ray of the round's queues
+// through its visit (or to a step that needs FP64), the FP64 kernel takes
+// those steps, the air kernel walks the rays that left.  With timing, HIP
+// events bracket the in-box kernel (ev[1], ev[2]) and the other two (ev[3]).
+// Enqueues kernels only, so that a graph can hold it.
+static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, unsigned box_g, unsigned air_g,
+                          bool timing, hipStream_t stream)
+{
+    const unsigned scan_g = (unsigned)std::min<long long>((a.n_rays + 255) / 256, 8ll * ctx->n_cu);
+    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
+    if (timing) HIP_OK(hipEventRecord(w.ev[1], stream));
+    if (a.o.integ == 0)
+        hipLaunchKernelGGL(k_wf_box<0>, dim3(box_g), dim3(256), 0, stream, a, cur);
+    else
+        hipLaunchKernelGGL(k_wf_box<1>, dim3(box_g), dim3(256), 0, stream, a, cur);
+    if (timing) HIP_OK(hipEventRecord(w.ev[2], stream));
+    if (a.o.integ == 0)
+        hipLaunchKernelGGL(k_wf_event<0>, dim3(air_g), dim3(256), 0, stream, a, cur);
+    else
+        hipLaunchKernelGGL(k_wf_event<1>, dim3(air_g), dim3(256), 0, stream, a, cur);
+    hipLaunchKernelGGL(k_wf_air, dim3(scan_g), dim3(256), 0, stream, a, cur);
+    if (timing) HIP_OK(hipEventRecord(w.ev[3], stream));
+    HIP_OK(hipGetLastError());
+    return GC_OK;
+}
+
+// Run the pipeline for a filled WfArgs (tables already on the device),
+// round by round, reading the queue lengths back after each.
+static gc_status wf_run(gc_ctx* ctx, WfStore& w, WfArgs& a, hipStream_t stream)
+{
     const int integ = a.o.integ;
     const unsigned init_blocks = (unsigned)((a.n_rays + 255) / 256);
     w.fp64_steps = 0;
@@ -711,37 +755,21 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
     w.tail_rays = 0;
     w.hot_ms = w.event_ms = w.tail_ms = 0.0;
     HIP_OK(hipEventRecord(w.ev[0], stream));
-    HIP_OK(hipMemsetAsync(w.ctr, 0, sizeof(QCtr), stream));
+    hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, stream, w.ctr, w.tot);
     hipLaunchKernelGGL(k_wf_init, dim3(init_blocks), dim3(256), 0, stream, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     unsigned len = w.h_ctr->box_len[0] + w.h_ctr->slow_len[0];
-    int box_max = w.box_blocks[integ];
-    if (ctx->tune.waves_per_simd > 0) box_max = std::min(box_max, ctx->tune.waves_per_simd * ctx->n_cu);
-    // one round per visit of the box: the in-box kernel takes every ray of
-    // the queue through its visit (or to a step that needs FP64), the FP64
-    // kernel takes those steps, the air kernel walks the rays that left
+    const unsigned box_max = wf_box_max(ctx, w, integ);
+    // one round per visit of the box
     for (int round = 0; len > 0; ++round) {
         const int cur = round & 1;
         const unsigned need = (len + 255) / 256;
-        const unsigned box_g = std::min<unsigned>(need, (unsigned)box_max);
+        const unsigned box_g = std::min<unsigned>(need, box_max);
         const unsigned air_g = std::min<unsigned>(need, (unsigned)(8 * ctx->n_cu));
-        const unsigned scan_g = (unsigned)std::min<long long>((a.n_rays + 255) / 256, 8ll * ctx->n_cu);
-        hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
-        HIP_OK(hipEventRecord(w.ev[1], stream));
-        if (integ == 0)
-            hipLaunchKernelGGL(k_wf_box<0>, dim3(box_g), dim3(256), 0, stream, a, cur);
-        else
-            hipLaunchKernelGGL(k_wf_box<1>, dim3(box_g), dim3(256), 0, stream, a, cur);
-        HIP_OK(hipEventRecord(w.ev[2], stream));
-        if (integ == 0)
-            hipLaunchKernelGGL(k_wf_event<0>, dim3(air_g), dim3(256), 0, stream, a, cur);
-        else
-            hipLaunchKernelGGL(k_wf_event<1>, dim3(air_g), dim3(256), 0, stream, a, cur);
-        hipLaunchKernelGGL(k_wf_air, dim3(scan_g), dim3(256), 0, stream, a, cur);
-        HIP_OK(hipEventRecord(w.ev[3], stream));
-        HIP_OK(hipGetLastError());
+        gc_status r = wf_round(ctx, w, a, cur, box_g, air_g, true, stream);
+        if (r != GC_OK) return r;
         HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
         float t1 = 0.f, t2 = 0.f;
@@ -757,9 +785,8 @@ static gc_status wf_run(gc_ctx* ctx, WfArgs& a, hipStream_t stream)
     return GC_OK;
 }
 
-static WfArgs wf_args(gc_ctx* ctx, const OptsDev& o, int ns, long long n_rays)
+static WfArgs wf_args(const gc_ctx* ctx, const WfStore& w, const OptsDev& o, int ns, long long n_rays)
 {
-    WfStore& w = ctx->wf;
     WfArgs a;
     std::memset(&a, 0, sizeof a);
     wf_carve(w.rays, w.cap_rays, a.R);
@@ -782,14 +809,14 @@ static WfArgs wf_args(gc_ctx* ctx, const OptsDev& o, int ns, long long n_rays)
     return a;
 }
 
-static gc_status wf_read_totals(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
+static gc_status wf_read_totals(WfStore& w, gc_stats* st, hipStream_t stream)
 {
     WfTotals h;
-    HIP_OK(hipEventRecord(ctx->wf.ev[4], stream));
-    HIP_OK(hipMemcpyAsync(&h, ctx->wf.tot, sizeof h, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipEventRecord(w.ev[4], stream));
+    HIP_OK(hipMemcpyAsync(&h, w.tot, sizeof h, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     float tt = 0.f;
-    HIP_OK(hipEventElapsedTime(&tt, ctx->wf.ev[0], ctx->wf.ev[4]));
+    HIP_OK(hipEventElapsedTime(&tt, w.ev[0], w.ev[4]));
     if (st) {
         std::memset(st, 0, sizeof *st);
         st->rays = (int64_t)h.rays;
@@ -798,21 +825,23 @@ static gc_status wf_read_totals(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
         st->events = (int64_t)h.events;
         st->fallbacks = (int64_t)h.fallbacks;
         st->failed = (int64_t)h.failed;
-        st->fp64_steps = ctx->wf.fp64_steps;
-        st->rounds = ctx->wf.rounds;
-        st->hot_ms = ctx->wf.hot_ms;
-        st->event_ms = ctx->wf.event_ms;
-        st->tail_ms = ctx->wf.tail_ms;
-        st->tail_rays = ctx->wf.tail_rays;
-        st->hot_steps = (int64_t)ctx->wf.h_ctr->hot_steps;
+        st->fp64_steps = w.fp64_steps;
+        st->rounds = w.rounds;
+        st->hot_ms = w.hot_ms;
+        st->event_ms = w.event_ms;
+        st->tail_ms = w.tail_ms;
+        st->tail_rays = w.tail_rays;
+        st->hot_steps = (int64_t)w.h_ctr->hot_steps;
         st->total_ms = tt;
     }
     return GC_OK;
 }
 
 // Render n scenes with the FP32 pipeline into the given device images.
-static gc_status wf_render(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
-                           float* const* d_rgb, gc_stats* st, hipStream_t stream)
+// Reserve the store's buffers for n scenes, upload their tables and fill
+// the kernel arguments (render mode).  n_pix: total pixels.
+static gc_status wf_setup(gc_ctx* ctx, WfStore& w, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
+                          float* const* d_rgb, hipStream_t stream, WfArgs* a, long long* n_pix_out)
 {
     std::vector<long long> roff(ns + 1), poff(ns + 1);
     roff[0] = poff[0] = 0;
@@ -823,7 +852,7 @@ static gc_status wf_render(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev
     }
     const long long n_rays = roff[ns], n_pix = poff[ns];
     if (n_rays > (1ll << 31) - 1) return fail(GC_EINVAL, "more than 2^31 - 1 samples in one launch");
-    gc_status r = wf_reserve(ctx, n_rays, ns);
+    gc_status r = wf_reserve(ctx, w, n_rays, ns);
     if (r != GC_OK) return r;
     // tables: staged in host memory, copied in one go
     const size_t tb = wf_table_bytes(ns);
@@ -835,38 +864,55 @@ static gc_status wf_render(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev
         th.images[i] = d_rgb[i];
     }
     for (int i = 0; i <= ns; ++i) { th.ray_off[i] = roff[i]; th.pix_off[i] = poff[i]; }
-    HIP_OK(hipMemcpyAsync(ctx->wf.tables, host.data(), tb, hipMemcpyHostToDevice, stream));
-    WfArgs a = wf_args(ctx, o, ns, n_rays);
-    r = wf_run(ctx, a, stream);
-    if (r != GC_OK) return r;
-    WfTables td = wf_tables(ctx->wf.tables, ns);
-    HIP_OK(hipMemsetAsync(ctx->wf.tot, 0, sizeof(WfTotals), stream));
+    HIP_OK(hipMemcpyAsync(w.tables, host.data(), tb, hipMemcpyHostToDevice, stream));
+    *a = wf_args(ctx, w, o, ns, n_rays);
+    *n_pix_out = n_pix;
+    return GC_OK;
+}
+
+// pixel averages and counters (enqueue only)
+static gc_status wf_finish(WfStore& w, const WfArgs& a, int ns, long long n_pix, hipStream_t stream)
+{
+    WfTables td = wf_tables(w.tables, ns);
     hipLaunchKernelGGL(k_wf_finish, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, stream, a,
-                       (float* const*)td.images, (const long long*)td.pix_off, n_pix, ctx->wf.tot);
+                       (float* const*)td.images, (const long long*)td.pix_off, n_pix, w.tot);
     HIP_OK(hipGetLastError());
-    return wf_read_totals(ctx, st, stream);
+    return GC_OK;
+}
+
+static gc_status wf_render(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
+                           float* const* d_rgb, gc_stats* st, hipStream_t stream)
+{
+    WfStore& w = ctx->wf;
+    WfArgs a;
+    long long n_pix = 0;
+    gc_status r = wf_setup(ctx, w, ns, sc, cams, o, d_rgb, stream, &a, &n_pix);
+    if (r != GC_OK) return r;
+    if ((r = wf_run(ctx, w, a, stream)) != GC_OK) return r;
+    if ((r = wf_finish(w, a, ns, n_pix, stream)) != GC_OK) return r;
+    return wf_read_totals(w, st, stream);
 }
 
 static gc_status wf_trace(gc_ctx* ctx, const SceneDev& s, const OptsDev& o, long long n, const double* org,
                           const double* dir, double* out_org, double* out_dir, int* status, long long* steps,
                           int* events, hipStream_t stream)
 {
-    gc_status r = wf_reserve(ctx, n, 1);
+    WfStore& w = ctx->wf;
+    gc_status r = wf_reserve(ctx, w, n, 1);
     if (r != GC_OK) return r;
     std::vector<char> host(wf_table_bytes(1), 0);
     WfTables th = wf_tables(host.data(), 1);
     th.scenes[0] = s;
     th.ray_off[0] = 0;
     th.ray_off[1] = n;
-    HIP_OK(hipMemcpyAsync(ctx->wf.tables, host.data(), host.size(), hipMemcpyHostToDevice, stream));
-    WfArgs a = wf_args(ctx, o, 1, n);
+    HIP_OK(hipMemcpyAsync(w.tables, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+    WfArgs a = wf_args(ctx, w, o, 1, n);
     a.in_org = org;
     a.in_dir = dir;
-    r = wf_run(ctx, a, stream);
+    r = wf_run(ctx, w, a, stream);
     if (r != GC_OK) return r;
-    HIP_OK(hipMemsetAsync(ctx->wf.tot, 0, sizeof(WfTotals), stream));
     hipLaunchKernelGGL(k_wf_trace_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a, out_org,
-                       out_dir, status, steps, events, ctx->wf.tot);
+                       out_dir, status, steps, events, w.tot);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(stream));
     return GC_OK;
@@ -956,14 +1002,7 @@ void gc_destroy(gc_ctx* c)
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_ccout) (void)hipFree(c->d_ccout);
-    if (c->wf.rays) (void)hipFree(c->wf.rays);
-    if (c->wf.queues) (void)hipFree(c->wf.queues);
-    if (c->wf.tables) (void)hipFree(c->wf.tables);
-    if (c->wf.ctr) (void)hipFree(c->wf.ctr);
-    if (c->wf.tot) (void)hipFree(c->wf.tot);
-    if (c->wf.h_ctr) (void)hipHostFree(c->wf.h_ctr);
-    for (hipEvent_t e : c->wf.ev)
-        if (e) (void)hipEventDestroy(e);
+    wf_free(c->wf);
     AdjStore& a = c->adj;
     void* bufs[] = {a.tape, a.seg, a.srgb, a.sgrad, a.ovf, a.img, a.cs, a.ctr, a.red};
     for (void* b : bufs)
@@ -1124,3 +1163,4 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
 }  // extern "C"
 
 #include "gc_autotune.hpp"
+#include "gc_plan.hpp"

@@ -35,6 +35,10 @@
 
 namespace gc {
 
+struct WfTotals {
+    unsigned long long rays, steps, rejected, events, failed, fallbacks;
+};
+
 struct QCtr {
     unsigned box_len[2];
     unsigned box_head[2];
@@ -214,6 +218,16 @@ __device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, con
 }
 
 // ---------------------------------------------------------------------------
+// Counters to zero at the start of a launch (a kernel, not a memset, so
+// that a captured graph holds no memset node).
+__global__ void __launch_bounds__(64) k_wf_zero(QCtr* c, WfTotals* t)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *c = QCtr{};
+        *t = WfTotals{};
+    }
+}
+
 __global__ void __launch_bounds__(256) k_wf_reset(QCtr* c, int cur)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -703,10 +717,7 @@ __global__ void __launch_bounds__(256) k_wf_air(WfArgs a, int cur)
     }
 }
 
-// Pixel averages (render mode) and counters.
-struct WfTotals {
-    unsigned long long rays, steps, rejected, events, failed, fallbacks;
-};
+// Pixel averages (render mode) and counters (totals in WfTotals).
 
 __global__ void __launch_bounds__(256) k_wf_finish(WfArgs a, float* const* images, const long long* pix_off,
                                                    long long n_pix, WfTotals* tot)

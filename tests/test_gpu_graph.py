@@ -1,0 +1,70 @@
+"""The batched FP32 render captured as one HIP graph (gc_batch_plan): every
+replay must reproduce the eager batch render bit for bit (images, flat
+references, C0 and counters), also with other work and synchronisations
+between the replays."""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1012_5107_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1012_5107_amd import binding
+    return binding
+
+
+def _workload():
+    scenes = [W.scene(A=0.1, half_width=3.0), W.scene(A=0.05, half_width=2.2), W.scene(A=0.13, half_width=5.0)]
+    cams = [W.camera(64, 48, spp=2, jitter=True, seed=1), W.camera(40, 40, spp=1, jitter=False, seed=2),
+            W.camera(72, 56, spp=2, jitter=True, seed=3, eye=W.orbit_eye(20.0, 35.0, 7.0))]
+    return scenes, cams, W.opts("dopri5", rtol=1e-6)
+
+
+def test_plan_replays_match_eager_batch(B):
+    scenes, cams, op = _workload()
+    ctx = B.Context(0)
+    try:
+        refs_e = [ctx.render(W.reference_scene(s), c, op, prec="f32")[0] for s, c in zip(scenes, cams)]
+        imgs_e, c0_e, st_e = ctx.render_batch(scenes, cams, op, refs=refs_e)
+        outs = [torch.full_like(i, float("nan")) for i in imgs_e]
+        refs = [torch.full_like(r, float("nan")) for r in refs_e]
+        plan = ctx.batch_plan(scenes, cams, op, outs, refs=refs, render_refs=True)
+        try:
+            for rep in range(3):
+                for t in outs + refs:
+                    t.fill_(float("nan"))
+                torch.cuda.synchronize()
+                plan.launch()
+                c0, st = plan.results()
+                for a, b in zip(outs, imgs_e):
+                    assert torch.equal(a, b), rep
+                for a, b in zip(refs, refs_e):
+                    assert torch.equal(a, b), rep
+                assert c0 == c0_e, rep
+                for k in ("rays", "accepted_steps", "rejected_steps", "events", "failed", "fallbacks"):
+                    assert st[k] == st_e[k], (rep, k)
+                assert st["rounds"] == st_e["rounds"] and st["total_ms"] > 0
+                # unrelated eager work between replays
+                ctx.render(scenes[1], cams[1], op, prec="f32")
+                torch.cuda.synchronize()
+        finally:
+            plan.close()
+        # without references: images only
+        plan = ctx.batch_plan(scenes[:2], cams[:2], op, outs[:2])
+        try:
+            plan.launch()
+            c0, st = plan.results()
+            assert c0 is None
+            assert torch.equal(outs[0], imgs_e[0]) and torch.equal(outs[1], imgs_e[1])
+        finally:
+            plan.close()
+        with pytest.raises(B.GcError):   # flat-mirror scenes are not batched
+            ctx.batch_plan([W.reference_scene(scenes[0])], cams[:1], op, outs[:1])
+    finally:
+        ctx.close()
