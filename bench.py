@@ -44,8 +44,9 @@ FLOP_PER_STEP = {"dopri5": 680.0, "rk4": 354.0}
 FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 # HBM bytes per launch of the in-cloak kernel on the 512 x 512 x 4 workload,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
-# size; keyed by (h_max, integrator); absent: not measured for this kernel
-TRAFFIC_K_WF_BOX = {}
+# size (profiles/k_wf_box_dopri5_512x512x4_tuned.txt); keyed by (rtol, h_max,
+# integrator); absent: not measured for this kernel and setting
+TRAFFIC_K_WF_BOX = {(1e-7, 0.2, "dopri5"): 4.50e8}
 
 
 def parse():
@@ -58,6 +59,13 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--workload", choices=["single", "batch", "stress", "grad"], default="single")
+    p.add_argument("--autotune", choices=["on", "off"], default="on",
+                   help="off: skip the autotuner and use --h-max, --rtol32 and --sched (single workload)")
+    p.add_argument("--h-max", type=float, default=None, help="FP32 step cap with --autotune off")
+    p.add_argument("--sched", type=str, default=None,
+                   help="gc_tune with --autotune off: slow_pxy,slow_wave_div,refill,waves_per_simd")
+    p.add_argument("--no-configured", action="store_true",
+                   help="skip the measurement at the configured step cap (single workload)")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="first copy this many MiB device to device (a reference kernel of known traffic for "
                         "hardware counters)")
@@ -123,20 +131,30 @@ def main():
     def roofline(st, op):
         achieved = st["hot_steps"] * FLOP_PER_STEP[op["integrator"]] / (st["hot_ms"] * 1e-3)
         return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32, "traffic": TRAFFIC_K_WF_BOX.get((op["h_max"], op["integrator"])),
+                "frac": achieved / PEAK_FP32,
+                "traffic": TRAFFIC_K_WF_BOX.get((op["rtol"], op["h_max"], op["integrator"])),
                 "kernel": "k_wf_box<DOPRI5>" if op["integrator"] == "dopri5" else "k_wf_box<RK4>",
                 "kernel_ms": st["hot_ms"], "kernel_steps": st["hot_steps"]}
 
     # the configured step control with the default scheduling
     ctx.tune(**B.default_tune())
-    dt0, st0, c0 = timed(op32, 1)
-    print(f"# configured (h_max {op32['h_max']}): {dt0 * 1e3:.1f} ms, {st0}", file=sys.stderr, flush=True)
+    if not args.no_configured:
+        dt0, st0, c0 = timed(op32, 1)
+        print(f"# configured (h_max {op32['h_max']}): {dt0 * 1e3:.1f} ms, {st0}", file=sys.stderr, flush=True)
 
-    # autotuned step cap and scheduling (outside the timed region)
-    ta = time.perf_counter()
-    tuned, rep = ctx.autotune(sc, cam, op32)
-    ta = time.perf_counter() - ta
-    print(f"# autotune {ta:.2f} s: h_max {tuned['h_max']}, tune {rep['tune']}", file=sys.stderr, flush=True)
+    if args.autotune == "on":
+        # autotuned step control and scheduling (outside the timed region)
+        ta = time.perf_counter()
+        tuned, rep = ctx.autotune(sc, cam, op32)
+        ta = time.perf_counter() - ta
+        print(f"# autotune {ta:.2f} s: rtol {tuned['rtol']} h_max {tuned['h_max']}, tune {rep['tune']}",
+              file=sys.stderr, flush=True)
+    else:
+        tuned = dict(op32, h_max=args.h_max if args.h_max is not None else op32["h_max"])
+        if args.sched:
+            v = args.sched.split(",")
+            ctx.tune(slow_pxy=float(v[0]), slow_wave_div=int(v[1]), refill=int(v[2]), waves_per_simd=int(v[3]))
+        rep, ta = None, 0.0
 
     dt, st32, c32 = timed(tuned, args.steps)
     rays = st32["rays"]
@@ -157,21 +175,27 @@ def main():
         "data": "synthetic",
         "config": {"workload": "512x512, 4 jittered spp, Lambda=1, A=0.1, cloak |x|<=4, y<=1.5, DOPRI5",
                    "rtol_fp32": tuned["rtol"], "h_max_fp32": tuned["h_max"], "rtol_fp64": op64["rtol"],
-                   "h_max_fp64": op64["h_max"], "schedule": rep["tune"], "rays": rays,
+                   "h_max_fp64": op64["h_max"], "schedule": ctx.tune(), "rays": rays,
                    "ray_steps": st32["accepted_steps"]},
         "ray_steps_per_s": st32["accepted_steps"] / dt,
         "cc_fp32": c32,
         "roofline": roofline(st32, tuned),
         "fp32_breakdown": {k: st32[k] for k in ("hot_ms", "event_ms", "total_ms", "rounds", "fp64_steps",
                                                   "fallbacks", "failed")},
-        "autotune": {"seconds": ta, "chosen_h_max": tuned["h_max"], "tune": rep["tune"],
-                     "tune_ms": rep["tune_ms"], "cal_rays": rep["cal_rays"], "ill_rays": rep["ill_rays"],
-                     "candidates": [{k: c[k] for k in ("h_max", "ms", "steps", "dir_p99", "dir_max", "changed",
-                                                       "cc_err", "passed")} for c in rep["candidates"]]},
-        "configured": {"h_max": op32["h_max"], "rays_per_s": st0["rays"] / dt0,
-                       "ray_steps_per_s": st0["accepted_steps"] / dt0, "ms": dt0 * 1e3,
-                       "roofline": roofline(st0, op32), "cc_fp32": c0},
     }
+    if rep is not None:
+        out["autotune"] = {"seconds": ta, "chosen_rtol": tuned["rtol"], "chosen_h_max": tuned["h_max"],
+                           "tune": rep["tune"], "tune_ms": rep["tune_ms"], "cal_rays": rep["cal_rays"],
+                           "ill_rays": rep["ill_rays"],
+                           "candidates": [{k: c[k] for k in ("rtol", "h_max", "ms", "steps", "dir_p99", "dir_max",
+                                                             "changed", "cc_err", "passed")}
+                                          for c in rep["candidates"]]}
+    else:
+        out["autotune"] = None
+    if not args.no_configured:
+        out["configured"] = {"h_max": op32["h_max"], "rays_per_s": st0["rays"] / dt0,
+                             "ray_steps_per_s": st0["accepted_steps"] / dt0, "ms": dt0 * 1e3,
+                             "roofline": roofline(st0, op32), "cc_fp32": c0}
 
     if not args.no_fp64:
         # FP64 plain path on the same workload: one timed pass
@@ -187,7 +211,8 @@ def main():
                              "achieved_tflops": st64["accepted_steps"] * FLOP_PER_STEP["dopri5"] / t64 / 1e12,
                              "frac_fp64_peak": st64["accepted_steps"] * FLOP_PER_STEP["dopri5"] / t64 / PEAK_FP64}
         out["cc_error_fp32_vs_fp64"] = abs(c32 - c64)
-        out["cc_error_fp32_configured_vs_fp64"] = abs(c0 - c64)
+        if not args.no_configured:
+            out["cc_error_fp32_configured_vs_fp64"] = abs(c0 - c64)
         out["speedup_rays_fp32_vs_fp64"] = (rays / dt) / (st64["rays"] / t64)
         d = (img - img64).abs().amax(dim=-1)
         out["rgb_error_fp32_vs_fp64"] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt())}
@@ -232,12 +257,13 @@ def main_batch(args):
     dev = torch.device("cuda", 0)
     imgs = [torch.empty((c["height"], c["width"], 3), dtype=torch.float32, device=dev) for c in cams]
     refs = [ctx.render(W.reference_scene(s), c, op32, prec="f32")[0] for s, c in zip(scenes, cams)]
-    # step cap tuned on the whole batch (calibration at 1/8 and 1/4 of each
-    # camera's resolution, one timing per candidate), outside the timed region
+    # step control tuned on the whole batch (directions at 1/4 of each
+    # camera's resolution, C0 at full size, one timing per candidate),
+    # outside the timed region
     ta = time.perf_counter()
-    op32, rep = ctx.autotune(scenes, cams, op32, dir_scale=8, cc_scale=4, reps=1, tune_sched=0)
+    op32, rep = ctx.autotune(scenes, cams, op32, dir_scale=4, cc_scale=1, reps=1, tune_sched=0)
     ta = time.perf_counter() - ta
-    print(f"# autotune {ta:.1f} s: h_max {op32['h_max']}", file=sys.stderr, flush=True)
+    print(f"# autotune {ta:.1f} s: rtol {op32['rtol']} h_max {op32['h_max']}", file=sys.stderr, flush=True)
     # one eager pass: counters and the in-cloak kernel's device time (HIP
     # events around its launches)
     _, c0_eager, stk = ctx.render_batch(scenes, cams, op32, refs=refs, outs=imgs)
@@ -269,8 +295,8 @@ def main_batch(args):
                    "rtol_fp32": op32["rtol"], "h_max_fp32": op32["h_max"], "rays": st["rays"],
                    "ray_steps": st["accepted_steps"]},
         "ray_steps_per_s": st["accepted_steps"] / dt,
-        "autotune": {"seconds": ta, "chosen_h_max": op32["h_max"],
-                     "candidates": [{k: c[k] for k in ("h_max", "ms", "steps", "dir_p99", "dir_max", "changed",
+        "autotune": {"seconds": ta, "chosen_rtol": op32["rtol"], "chosen_h_max": op32["h_max"],
+                     "candidates": [{k: c[k] for k in ("rtol", "h_max", "ms", "steps", "dir_p99", "dir_max", "changed",
                                                        "cc_err", "passed")} for c in rep["candidates"]]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_wf_box<DOPRI5>",

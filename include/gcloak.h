@@ -211,9 +211,10 @@ gc_status gc_batch_plan_launch(gc_batch_plan* plan, hipStream_t stream);
 gc_status gc_batch_plan_results(gc_batch_plan* plan, double* C0, gc_stats* stats, hipStream_t stream);
 void gc_batch_plan_destroy(gc_batch_plan* plan);
 
-/* Autotuner of the FP32 pipeline: the DOPRI5 step cap h_max and the
- * scheduling (gc_tune), picked for a workload (one or more scenes with
- * their cameras) subject to accuracy bounds against the FP64 path.
+/* Autotuner of the FP32 pipeline: the DOPRI5 tolerance rtol (= atol), the
+ * step cap h_max and the scheduling (gc_tune), picked for a workload (one
+ * or more scenes with their cameras) subject to accuracy bounds against
+ * the FP64 path.
  *
  * Reference: the FP64 path with the same options except prec = GC_F64 and
  * rtol = atol = ref_rtol (the FP64 path follows the CPU oracle to
@@ -229,12 +230,17 @@ void gc_batch_plan_destroy(gc_batch_plan* plan);
  *     50 dir_tol;
  *   - the zero-shift correlation C0 (eq. (15)) of the image at
  *     width / cc_scale x height / cc_scale against the flat-mirror
- *     reference must be within cc_tol of the FP64 image's.
- * Step-cap candidates: h_max x {1, 2.5, 5, 10, 25} (DOPRI5; RK4 keeps its
- * step).  Of the candidates that pass, the one with the shortest FP32
- * render of the whole workload is chosen (best of `reps`); then, if
- * tune_sched, a fixed set of gc_tune settings is timed the same way and the
- * fastest is installed in the context.  Results never depend on gc_tune. */
+ *     reference must be within cc_tol of the FP64 image's (with
+ *     cc_scale = 1 the timed full-size renders are the ones checked).
+ * Candidates (DOPRI5): rtol x {1, 1/3, 1/10} times h_max x {1, 2.5, 5,
+ * 10, 25}; RK4 keeps its step (one candidate).  Of the candidates that
+ * pass, the one with the shortest FP32 render of the whole workload is
+ * chosen (best of `reps`); then, if tune_sched, a fixed set of gc_tune
+ * settings is timed the same way and the fastest is installed in the
+ * context.  Results never depend on gc_tune.  C0 differences near 1e-4 are
+ * at the level by which two correct integrations (FP64 at rtol 1e-7 and
+ * 1e-8) differ on images of ~10^4 pixels, so the correlation check wants
+ * the full-size images. */
 typedef struct {
     int32_t dir_scale;     /* default 4 */
     int32_t cc_scale;      /* default 1 */
@@ -246,9 +252,10 @@ typedef struct {
     int32_t tune_sched;    /* default 1 */
 } gc_autotune_opts;
 
-#define GC_AUTOTUNE_MAX_CAND 8
+#define GC_AUTOTUNE_MAX_CAND 16
 
 typedef struct {
+    double rtol;
     double h_max;
     double ms;             /* best FP32 render time of the workload (HIP events) */
     int64_t steps;         /* FP32 accepted steps of the workload */
@@ -272,7 +279,7 @@ void gc_default_autotune_opts(gc_autotune_opts* at);
 
 /* Run the autotuner (see above) on n_scenes scenes and cameras with FP32
  * options `opts` (prec must be GC_F32).  Writes the tuned options to
- * opts_out (equal to opts but for h_max) and, if `report` is non-null, the
+ * opts_out (equal to opts but for rtol, atol and h_max) and, if `report` is non-null, the
  * measurements.  Device scratch for the calibration is allocated and freed
  * inside the call; the stream is synchronised.  GC_EINVAL for bad
  * arguments, GC_EUNSUPPORTED for prec != GC_F32. */

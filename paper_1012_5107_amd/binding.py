@@ -74,11 +74,11 @@ class AutotuneOpts(ctypes.Structure):
                 ("reps", ctypes.c_int32), ("tune_sched", ctypes.c_int32)]
 
 
-AUTOTUNE_MAX_CAND = 8
+AUTOTUNE_MAX_CAND = 16
 
 
 class AutotuneCand(ctypes.Structure):
-    _fields_ = [("h_max", ctypes.c_double), ("ms", ctypes.c_double), ("steps", ctypes.c_int64),
+    _fields_ = [("rtol", ctypes.c_double), ("h_max", ctypes.c_double), ("ms", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("dir_p99", ctypes.c_double), ("dir_max", ctypes.c_double), ("changed", ctypes.c_double),
                 ("cc_err", ctypes.c_double), ("pass_", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
@@ -92,7 +92,7 @@ class AutotuneReport(ctypes.Structure):
         cands = []
         for i in range(self.n_cand):
             c = self.cand[i]
-            cands.append(dict(h_max=c.h_max, ms=c.ms, steps=int(c.steps), dir_p99=c.dir_p99, dir_max=c.dir_max,
+            cands.append(dict(rtol=c.rtol, h_max=c.h_max, ms=c.ms, steps=int(c.steps), dir_p99=c.dir_p99, dir_max=c.dir_max,
                               changed=c.changed, cc_err=c.cc_err, passed=bool(c.pass_)))
         return dict(candidates=cands, chosen=int(self.chosen), tune=self.tune.as_dict(), tune_ms=self.tune_ms,
                     base_tune_ms=self.base_tune_ms, cal_rays=int(self.cal_rays), ill_rays=int(self.ill_rays))

@@ -1,10 +1,11 @@
 // gc_autotune.hpp -- host side of the FP32 pipeline's autotuner (included at
 // the end of gc_lib.hip, after the public entry points it calls).
 //
-// The tuner checks each candidate step cap against the FP64 path on
-// calibration cameras (exit directions with an FP64 conditioning screen,
-// and the zero-shift correlation of eq. (15)), times the whole workload for
-// the candidates that pass, then times a fixed set of scheduling settings.
+// The tuner times the whole workload for each candidate step control
+// (tolerance and step cap), checks it against the FP64 path on calibration
+// cameras (exit directions with an FP64 conditioning screen, and the
+// zero-shift correlation of eq. (15)), keeps the fastest that passes, then
+// times a fixed set of scheduling settings.
 #pragma once
 #include <algorithm>
 #include <cmath>
@@ -168,6 +169,7 @@ gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, con
         max_ccpix = std::max(max_ccpix, cal[i].cc_npix);
     }
     DevMem pert, out_dir, st_buf, ev_buf, img64, img32;
+    static_assert(GC_AUTOTUNE_MAX_CAND >= 15, "room for every candidate");
     if (!pert.alloc(sizeof(double) * 3 * max_cal) || !out_dir.alloc(sizeof(double) * 3 * max_cal) ||
         !st_buf.alloc(sizeof(int32_t) * max_cal) || !ev_buf.alloc(sizeof(int32_t) * max_cal) ||
         !img64.alloc(sizeof(float) * 3 * max_ccpix) || !img32.alloc(sizeof(float) * 3 * max_ccpix))
@@ -249,15 +251,22 @@ gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, con
         return GC_OK;
     };
 
-    // ---- step-cap candidates ----------------------------------------------
+    // ---- step-control candidates --------------------------------------------
+    static const double kTolFactor[] = {1.0, 1.0 / 3.0, 0.1};
     static const double kCapFactor[] = {1.0, 2.5, 5.0, 10.0, 25.0};
-    const int n_cap = opts->integ == GC_DOPRI5 ? 5 : 1;
+    const bool dp = opts->integ == GC_DOPRI5;
+    const int n_tol = dp ? 3 : 1, n_cap = dp ? 5 : 1;
     double best_ms = HUGE_VAL;
+    for (int ti = 0; ti < n_tol; ++ti)
     for (int ci = 0; ci < n_cap; ++ci) {
         gc_autotune_cand& cand = rep.cand[rep.n_cand++];
         gc_opts o = *opts;
+        o.rtol = opts->rtol * kTolFactor[ti];
+        o.atol = opts->atol * kTolFactor[ti];
         o.h_max = opts->h_max * kCapFactor[ci];
+        cand.rtol = o.rtol;
         cand.h_max = o.h_max;
+        if ((r = time_workload(o, &cand.ms, &cand.steps)) != GC_OK) return r;
         double p99 = 0.0, mx = 0.0, chg = 0.0, cce = 0.0;
         for (int i = 0; i < n_scenes; ++i) {
             Calib& c = cal[i];
@@ -279,10 +288,15 @@ gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, con
                 p99 = std::max(p99, err[k99]);
                 mx = std::max(mx, *std::max_element(err.begin(), err.end()));
             }
-            if ((r = gc_render(ctx, &scenes[i], &c.cc_cam, &o, img32.as<float>(), nullptr, stream)) != GC_OK) return r;
+            // at full size the timed render's image is the one to check
+            const float* img = d_rgb[i];
+            if (at.cc_scale > 1) {
+                if ((r = gc_render(ctx, &scenes[i], &c.cc_cam, &o, img32.as<float>(), nullptr, stream)) != GC_OK)
+                    return r;
+                img = img32.as<float>();
+            }
             double c0 = 0.0;
-            if ((r = gc_cross_correlate(ctx, img32.as<float>(), c.flat.as<float>(), c.cc_npix, 3, &c0, nullptr,
-                                        stream)) != GC_OK)
+            if ((r = gc_cross_correlate(ctx, img, c.flat.as<float>(), c.cc_npix, 3, &c0, nullptr, stream)) != GC_OK)
                 return r;
             cce = std::max(cce, std::fabs(c0 - c.c0_ref));
         }
@@ -291,7 +305,6 @@ gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, con
         cand.changed = chg;
         cand.cc_err = cce;
         cand.pass = p99 <= at.dir_tol && mx <= 50.0 * at.dir_tol && chg <= at.max_changed && cce <= at.cc_tol;
-        if ((r = time_workload(o, &cand.ms, &cand.steps)) != GC_OK) return r;
         if (cand.pass && cand.ms < best_ms) {
             best_ms = cand.ms;
             rep.chosen = rep.n_cand - 1;

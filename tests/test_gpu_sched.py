@@ -79,14 +79,18 @@ def test_autotune_small_workload(B):
     try:
         tuned, rep = ctx.autotune(sc, cam, op, dir_scale=2, reps=1, cc_tol=1e-3)
         print("[autotune]", rep, flush=True)
-        assert {k: v for k, v in tuned.items() if k != "h_max"} == {k: v for k, v in op.items() if k != "h_max"}
-        assert len(rep["candidates"]) == 5
-        assert [c["h_max"] for c in rep["candidates"]] == pytest.approx([op["h_max"] * f for f in (1, 2.5, 5, 10, 25)])
+        tuned_keys = ("h_max", "rtol", "atol")
+        assert {k: v for k, v in tuned.items() if k not in tuned_keys} == \
+            {k: v for k, v in op.items() if k not in tuned_keys}
+        assert tuned["atol"] == pytest.approx(tuned["rtol"])
+        grid = [(op["rtol"] * t, op["h_max"] * f) for t in (1, 1 / 3, 0.1) for f in (1, 2.5, 5, 10, 25)]
+        assert len(rep["candidates"]) == len(grid)
+        assert [(c["rtol"], c["h_max"]) for c in rep["candidates"]] == pytest.approx(grid)
         assert rep["cal_rays"] == 48 * 40 * 2
         ch = rep["chosen"]
         assert ch >= 0, "the configured step cap should pass its own bounds"
         assert rep["candidates"][ch]["passed"]
-        assert tuned["h_max"] == rep["candidates"][ch]["h_max"]
+        assert (tuned["rtol"], tuned["h_max"]) == (rep["candidates"][ch]["rtol"], rep["candidates"][ch]["h_max"])
         assert all(c["ms"] >= rep["candidates"][ch]["ms"] for c in rep["candidates"] if c["passed"])
         assert ctx.tune() == rep["tune"]
         assert rep["tune_ms"] <= rep["base_tune_ms"]
