@@ -400,6 +400,31 @@ def main_grad(args):
                               "total_ms": st["total_ms"], "fp64_samples": st["tail_rays"],
                               "long_tape_samples": st["rounds"], "failed": st["failed"]},
     }
+    # The pathwise gradient of the image sums one term per sample, and a
+    # sample close to a change of its event sequence has an unbounded
+    # derivative: the total can be carried by one term.  Reported beside the
+    # total: the largest term's share and the sum without the 0.1% largest.
+    def tail(rr):
+        img = rr["image"].double().reshape(-1, 3)
+        f = ref.double().reshape(-1, 3)
+        fp, gp = f - f.mean(dim=0), img - img.mean(dim=0)
+        sff, sgg, sfg = (fp * fp).sum(), (gp * gp).sum(), (fp * gp).sum()
+        ncc = sfg / torch.sqrt(sff * sgg)
+        w = -(fp / torch.sqrt(sff * sgg) - ncc * gp / sgg)                 # dL/dg per pixel and channel
+        dmix = torch.tensor([0.85, 0.65, -0.25], dtype=torch.float64, device=img.device)   # Ca - Cb of the sky
+        wp = (w @ dmix) / cam["spp"]
+        terms = wp.repeat_interleave(cam["spp"])[:, None] * rr["sample_dm"]
+        res = {}
+        for k, name in ((0, "dA"), (1, "dhw")):
+            t = terms[:, k]
+            order = torch.argsort(t.abs(), descending=True)
+            cut = max(1, t.numel() // 1000)
+            res[name] = {"total": float(t.sum()), "largest_term_share": float(t[order[0]] / t.sum()),
+                         "without_largest_0.1pct": float(t.sum() - t[order[:cut]].sum())}
+        return res
+
+    r_dm = ctx.render_grad(sc, cam, op, ref, prec="f32", loss="ncc", sample_dm=True)
+    out["gradient_terms_fp32"] = tail(r_dm)
     if not args.no_fp64:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -408,6 +433,7 @@ def main_grad(args):
         t64 = time.perf_counter() - t1
         out["fp64_adjoint"] = {"ms": t64 * 1e3, "ray_steps_per_s": r64["stats"]["accepted_steps"] / t64,
                                "loss": r64["loss"], "dL_dA": r64["dA"], "dL_dhw": r64["dhw"]}
+        out["gradient_terms_fp64"] = tail(ctx.render_grad(sc, cam, op, ref, prec="f64", loss="ncc", sample_dm=True))
         out["loss_error_fp32_vs_fp64"] = abs(r["loss"] - r64["loss"])
         out["grad_rel_error_fp32_vs_fp64"] = {
             "dA": abs(r["dA"] - r64["dA"]) / max(abs(r64["dA"]), 1e-300),

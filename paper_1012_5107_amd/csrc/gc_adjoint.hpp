@@ -154,7 +154,8 @@ __device__ inline cx<T> adj_w(const SceneDev& s, T wfb2, T x, T y, T xp, T yp, c
         for (int it = 0; it < 8; ++it) {
             cx<T> w0 = W;
             halley_step<T>(s, fx, y, W);
-            if (!(norm2(W - w0) > (T)1e-30 * fmax((T)1e-10, norm2(W)))) break;
+            // cubic convergence: a relative update of 1e-7 leaves rounding
+            if (!(norm2(W - w0) > (T)1e-14 * fmax((T)1e-10, norm2(W)))) break;
         }
         if (!(isfinite(W.re) && isfinite(W.im))) W = w0_cold(zarg64(s, x, y));
     } else {
