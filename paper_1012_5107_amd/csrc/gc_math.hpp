@@ -147,27 +147,27 @@ __device__ __noinline__ cx<double> w0_cold(cx<double> z)
 {
     double az2 = norm2(z);
     if (az2 == 0.0) return z;
-    cx<double> starts[4];
-    int n = 0;
-    if (az2 < 0.0625) starts[n++] = z - z * z + 1.5 * (z * z * z);
+    // the starts in order; each is formed only if the ones before it failed
+    cx<double> first = z;
+    bool have = false;
+    auto attempt = [&](cx<double> w, cx<double>& out) {
+        bool ok = w0_refine(z, w);
+        if (ok) { out = w; return true; }
+        if (!have) { first = w; have = true; }
+        return false;
+    };
+    cx<double> w;
+    if (az2 < 0.0625 && attempt(z - z * z + 1.5 * (z * z * z), w)) return w;
     cx<double> zb = mk(z.re + kInvE, z.im);
     if (norm2(zb) < 0.09) {
         // p = sqrt(2 (e z + 1)) with e z + 1 = e (z + 1/e)
         cx<double> p = csqrt_d(mk(2.0 * 2.71828182845904523536, 0.0) * zb);
-        starts[n++] = mk(-1.0, 0.0) + p - (1.0 / 3.0) * (p * p) + (11.0 / 72.0) * (p * p * p);
+        if (attempt(mk(-1.0, 0.0) + p - (1.0 / 3.0) * (p * p) + (11.0 / 72.0) * (p * p * p), w)) return w;
     }
-    starts[n++] = clog_d(mk(1.0 + z.re, z.im));
+    if (attempt(clog_d(mk(1.0 + z.re, z.im)), w)) return w;
     {
         cx<double> l1 = clog_d(z), l2 = clog_d(l1);
-        starts[n++] = l1 - l2 + cdiv_d(l2, l1);
-    }
-    cx<double> first = starts[0];
-    bool have = false;
-    for (int i = 0; i < n; ++i) {
-        cx<double> w = starts[i];
-        bool ok = w0_refine(z, w);
-        if (ok) return w;
-        if (!have) { first = w; have = true; }
+        if (attempt(l1 - l2 + cdiv_d(l2, l1), w)) return w;
     }
     return first;
 }

@@ -38,6 +38,7 @@ namespace gc {
 struct WfTotals {
     unsigned long long rays, steps, rejected, events, failed, fallbacks;
 };
+static_assert(sizeof(WfTotals) == 6 * sizeof(unsigned long long), "six consecutive counters");
 
 struct QCtr {
     unsigned box_len[2];
@@ -191,9 +192,9 @@ __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const S
     R.qx[q] = p[0]; R.qy[q] = p[1]; R.qz[q] = p[2];
     float c3[3] = {0.0f, 0.0f, 0.0f};
     if (status == RS_OK) {
-        double c[3];
-        sky_rgb<double>(s.K, p, c);
-        c3[0] = (float)c[0]; c3[1] = (float)c[1]; c3[2] = (float)c[2];
+        // the image is FP32: so is the sky lookup
+        const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
+        sky_rgb<float>((float)s.K, pf, c3);
     }
     R.rgb[3 * q + 0] = c3[0];
     R.rgb[3 * q + 1] = c3[1];
@@ -717,6 +718,32 @@ __global__ void __launch_bounds__(256) k_wf_air(WfArgs a, int cur)
     }
 }
 
+// Fold per-thread counters into the totals: wave sums by shuffles, block
+// sums in LDS, one set of atomics per block (every thread of the block calls
+// it).
+__device__ __forceinline__ void add_totals(WfTotals* tot, unsigned long long c_rays, unsigned long long c_steps,
+                                           unsigned long long c_rej, unsigned long long c_ev,
+                                           unsigned long long c_fail, unsigned long long c_fb)
+{
+    unsigned long long v[6] = {c_rays, c_steps, c_rej, c_ev, c_fail, c_fb};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    __shared__ unsigned long long part[4][6];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) part[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        unsigned long long sum = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += part[w][k];
+        // WfTotals is six consecutive counters in the order of v
+        if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(tot) + k, sum);
+    }
+}
+
 // Pixel averages (render mode) and counters (totals in WfTotals).
 
 __global__ void __launch_bounds__(256) k_wf_finish(WfArgs a, float* const* images, const long long* pix_off,
@@ -751,23 +778,7 @@ __global__ void __launch_bounds__(256) k_wf_finish(WfArgs a, float* const* image
         float* img = images[si];
         for (int k = 0; k < 3; ++k) img[3 * local + k] = acc[k] * inv;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        c_rays += __shfl_xor(c_rays, off, 64);
-        c_steps += __shfl_xor(c_steps, off, 64);
-        c_rej += __shfl_xor(c_rej, off, 64);
-        c_ev += __shfl_xor(c_ev, off, 64);
-        c_fail += __shfl_xor(c_fail, off, 64);
-        c_fb += __shfl_xor(c_fb, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&tot->fallbacks, c_fb);
-        atomicAdd(&tot->rays, c_rays);
-        atomicAdd(&tot->steps, c_steps);
-        atomicAdd(&tot->rejected, c_rej);
-        atomicAdd(&tot->events, c_ev);
-        atomicAdd(&tot->failed, c_fail);
-    }
+    add_totals(tot, c_rays, c_steps, c_rej, c_ev, c_fail, c_fb);
 }
 
 // trace_rays mode: copy the exit rays out and fold the counters.
@@ -791,23 +802,7 @@ __global__ void __launch_bounds__(256) k_wf_trace_out(WfArgs a, double* out_org,
         c_fail = a.R.status[q] != RS_OK;
         c_fb = (unsigned)a.R.fbk[q];
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        c_rays += __shfl_xor(c_rays, off, 64);
-        c_steps += __shfl_xor(c_steps, off, 64);
-        c_rej += __shfl_xor(c_rej, off, 64);
-        c_ev += __shfl_xor(c_ev, off, 64);
-        c_fail += __shfl_xor(c_fail, off, 64);
-        c_fb += __shfl_xor(c_fb, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&tot->fallbacks, c_fb);
-        atomicAdd(&tot->rays, c_rays);
-        atomicAdd(&tot->steps, c_steps);
-        atomicAdd(&tot->rejected, c_rej);
-        atomicAdd(&tot->events, c_ev);
-        atomicAdd(&tot->failed, c_fail);
-    }
+    add_totals(tot, c_rays, c_steps, c_rej, c_ev, c_fail, c_fb);
 }
 
 }  // namespace gc
