@@ -261,7 +261,10 @@ def main_batch(args):
     # camera's resolution, C0 at full size, one timing per candidate),
     # outside the timed region
     ta = time.perf_counter()
-    op32, rep = ctx.autotune(scenes, cams, op32, dir_scale=4, cc_scale=1, reps=1, tune_sched=0)
+    if args.autotune == "on":
+        op32, rep = ctx.autotune(scenes, cams, op32, dir_scale=4, cc_scale=1, reps=1, tune_sched=0)
+    else:
+        rep = {"candidates": []}
     ta = time.perf_counter() - ta
     print(f"# autotune {ta:.1f} s: rtol {op32['rtol']} h_max {op32['h_max']}", file=sys.stderr, flush=True)
     # one eager pass: counters and the in-cloak kernel's device time (HIP
