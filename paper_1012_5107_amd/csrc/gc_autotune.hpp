@@ -123,7 +123,7 @@ void gc_default_autotune_opts(gc_autotune_opts* at)
     at->tune_sched = 1;
 }
 
-gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
                       const gc_opts* opts, const gc_autotune_opts* atp, gc_opts* opts_out,
                       gc_autotune_report* report, hipStream_t stream)
 {
@@ -314,6 +314,16 @@ gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, con
 
     // ---- scheduling ---------------------------------------------------------
     const gc_tune entry = ctx->tune;
+    // the context's scheduling on entry comes back on any early exit
+    struct Restore {
+        gc_ctx* c;
+        gc_tune t;
+        bool keep;
+        ~Restore()
+        {
+            if (!keep) c->tune = t;
+        }
+    } restore{ctx, entry, false};
     rep.tune = entry;
     if ((r = time_workload(*opts_out, &rep.base_tune_ms, nullptr)) != GC_OK) return r;
     rep.tune_ms = rep.base_tune_ms;
@@ -330,19 +340,24 @@ gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, con
             t.waves_per_simd = (int32_t)s[3];
             ctx->tune = t;
             double ms = 0.0;
-            if ((r = time_workload(*opts_out, &ms, nullptr)) != GC_OK) {
-                ctx->tune = entry;
-                return r;
-            }
+            if ((r = time_workload(*opts_out, &ms, nullptr)) != GC_OK) return r;
             if (ms < rep.tune_ms) {
                 rep.tune_ms = ms;
                 rep.tune = t;
             }
         }
-        ctx->tune = rep.tune;
     }
+    ctx->tune = rep.tune;
+    restore.keep = true;
     if (report) *report = rep;
     return GC_OK;
+}
+
+gc_status gc_autotune(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                      const gc_opts* opts, const gc_autotune_opts* atp, gc_opts* opts_out,
+                      gc_autotune_report* report, hipStream_t stream)
+{
+    GC_GUARD(autotune_impl(ctx, n_scenes, scenes, cameras, opts, atp, opts_out, report, stream));
 }
 
 }  // extern "C"

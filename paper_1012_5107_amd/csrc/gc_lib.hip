@@ -295,6 +295,26 @@ static gc_status fail(gc_status st, const char* fmt, ...)
     return st;
 }
 
+// No C++ exception may cross the C ABI: a host allocation that throws
+// becomes GC_ENOMEM.
+static gc_status host_alloc_failed()
+{
+    try {
+        g_err = "host allocation failed";
+    } catch (...) {
+    }
+    return GC_ENOMEM;
+}
+
+#define GC_GUARD(call)                  \
+    do {                                \
+        try {                           \
+            return (call);              \
+        } catch (...) {                 \
+            return host_alloc_failed(); \
+        }                               \
+    } while (0)
+
 #define HIP_OK(call)                                                                              \
     do {                                                                                          \
         hipError_t e_ = (call);                                                                   \
@@ -954,7 +974,7 @@ void gc_default_tune(gc_tune* t)
     t->waves_per_simd = 0;
 }
 
-gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* t)
+static gc_status set_tune_impl(gc_ctx* ctx, const gc_tune* t)
 {
     if (!ctx || !t) return fail(GC_EINVAL, "ctx and tune must be non-null");
     if (!(t->slow_pxy >= 0.0 && t->slow_pxy <= 1.0)) return fail(GC_EINVAL, "slow_pxy must be in [0, 1]");
@@ -966,14 +986,24 @@ gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* t)
     return GC_OK;
 }
 
-gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* t)
+gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* t)
+{
+    GC_GUARD(set_tune_impl(ctx, t));
+}
+
+static gc_status get_tune_impl(const gc_ctx* ctx, gc_tune* t)
 {
     if (!ctx || !t) return fail(GC_EINVAL, "ctx and tune must be non-null");
     *t = ctx->tune;
     return GC_OK;
 }
 
-gc_status gc_create(gc_ctx** out, int hip_device)
+gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* t)
+{
+    GC_GUARD(get_tune_impl(ctx, t));
+}
+
+static gc_status create_impl(gc_ctx** out, int hip_device)
 {
     if (!out) return fail(GC_EINVAL, "out is null");
     *out = nullptr;
@@ -1000,6 +1030,11 @@ gc_status gc_create(gc_ctx** out, int hip_device)
     return GC_OK;
 }
 
+gc_status gc_create(gc_ctx** out, int hip_device)
+{
+    GC_GUARD(create_impl(out, hip_device));
+}
+
 void gc_destroy(gc_ctx* c)
 {
     if (!c) return;
@@ -1018,7 +1053,7 @@ void gc_destroy(gc_ctx* c)
     delete c;
 }
 
-gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts, int64_t n, const double* d_org,
+static gc_status trace_rays_impl(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts, int64_t n, const double* d_org,
                         const double* d_dir, double* d_out_org, double* d_out_dir, int32_t* d_status,
                         int64_t* d_steps, int32_t* d_events, hipStream_t stream)
 {
@@ -1045,7 +1080,14 @@ gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts,
     return GC_OK;
 }
 
-gc_status gc_render(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
+gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts, int64_t n, const double* d_org,
+                        const double* d_dir, double* d_out_org, double* d_out_dir, int32_t* d_status,
+                        int64_t* d_steps, int32_t* d_events, hipStream_t stream)
+{
+    GC_GUARD(trace_rays_impl(ctx, scene, opts, n, d_org, d_dir, d_out_org, d_out_dir, d_status, d_steps, d_events, stream));
+}
+
+static gc_status render_impl(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
                     float* d_rgb, gc_stats* stats, hipStream_t stream)
 {
     if (!ctx) return fail(GC_EINVAL, "ctx is null");
@@ -1072,7 +1114,13 @@ gc_status gc_render(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera,
     return GC_OK;
 }
 
-gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+gc_status gc_render(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
+                    float* d_rgb, gc_stats* stats, hipStream_t stream)
+{
+    GC_GUARD(render_impl(ctx, scene, camera, opts, d_rgb, stats, stream));
+}
+
+static gc_status render_batch_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
                           const gc_opts* opts, float* const* d_rgb, const float* const* d_ref, double* C0,
                           gc_stats* st, hipStream_t stream)
 {
@@ -1105,7 +1153,14 @@ gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes,
     return GC_OK;
 }
 
-gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
+gc_status gc_render_batch(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                          const gc_opts* opts, float* const* d_rgb, const float* const* d_ref, double* C0,
+                          gc_stats* st, hipStream_t stream)
+{
+    GC_GUARD(render_batch_impl(ctx, n_scenes, scenes, cameras, opts, d_rgb, d_ref, C0, st, stream));
+}
+
+static gc_status render_grad_impl(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
                          const float* d_ref, int32_t loss_kind, int32_t checkpoint_every, float* d_rgb,
                          double* d_sample_dm, double* loss, double* dL_dA, double* dL_dhw, gc_stats* st,
                          hipStream_t stream)
@@ -1142,7 +1197,15 @@ gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* ca
     return GC_OK;
 }
 
-gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref, int64_t npix, int32_t nch,
+gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
+                         const float* d_ref, int32_t loss_kind, int32_t checkpoint_every, float* d_rgb,
+                         double* d_sample_dm, double* loss, double* dL_dA, double* dL_dhw, gc_stats* st,
+                         hipStream_t stream)
+{
+    GC_GUARD(render_grad_impl(ctx, scene, camera, opts, d_ref, loss_kind, checkpoint_every, d_rgb, d_sample_dm, loss, dL_dA, dL_dhw, st, stream));
+}
+
+static gc_status cross_correlate_impl(gc_ctx* ctx, const float* d_img, const float* d_ref, int64_t npix, int32_t nch,
                              double* C0, double* ncc, hipStream_t stream)
 {
     if (!ctx) return fail(GC_EINVAL, "ctx is null");
@@ -1163,6 +1226,12 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
     *C0 = h[0];
     if (ncc) *ncc = h[1];
     return GC_OK;
+}
+
+gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref, int64_t npix, int32_t nch,
+                             double* C0, double* ncc, hipStream_t stream)
+{
+    GC_GUARD(cross_correlate_impl(ctx, d_img, d_ref, npix, nch, C0, ncc, stream));
 }
 
 }  // extern "C"

@@ -43,7 +43,7 @@ static void plan_free(gc_batch_plan* p)
 
 extern "C" {
 
-gc_status gc_batch_plan_create(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
                                const gc_opts* opts, float* const* d_rgb, float* const* d_ref, int32_t render_refs,
                                gc_batch_plan** out)
 {
@@ -130,7 +130,14 @@ gc_status gc_batch_plan_create(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
     return GC_OK;
 }
 
-gc_status gc_batch_plan_launch(gc_batch_plan* p, hipStream_t stream)
+gc_status gc_batch_plan_create(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
+                               const gc_opts* opts, float* const* d_rgb, float* const* d_ref, int32_t render_refs,
+                               gc_batch_plan** out)
+{
+    GC_GUARD(batch_plan_create_impl(ctx, n_scenes, scenes, cameras, opts, d_rgb, d_ref, render_refs, out));
+}
+
+static gc_status batch_plan_launch_impl(gc_batch_plan* p, hipStream_t stream)
 {
     if (!p) return fail(GC_EINVAL, "plan is null");
     HIP_OK(hipSetDevice(p->ctx->device));
@@ -140,7 +147,12 @@ gc_status gc_batch_plan_launch(gc_batch_plan* p, hipStream_t stream)
     return GC_OK;
 }
 
-gc_status gc_batch_plan_results(gc_batch_plan* p, double* C0, gc_stats* st, hipStream_t stream)
+gc_status gc_batch_plan_launch(gc_batch_plan* p, hipStream_t stream)
+{
+    GC_GUARD(batch_plan_launch_impl(p, stream));
+}
+
+static gc_status batch_plan_results_impl(gc_batch_plan* p, double* C0, gc_stats* st, hipStream_t stream)
 {
     using namespace gc;
     if (!p) return fail(GC_EINVAL, "plan is null");
@@ -174,6 +186,11 @@ gc_status gc_batch_plan_results(gc_batch_plan* p, double* C0, gc_stats* st, hipS
         C0[i] = cc[4 * i];
     }
     return GC_OK;
+}
+
+gc_status gc_batch_plan_results(gc_batch_plan* p, double* C0, gc_stats* st, hipStream_t stream)
+{
+    GC_GUARD(batch_plan_results_impl(p, C0, st, stream));
 }
 
 void gc_batch_plan_destroy(gc_batch_plan* p)
