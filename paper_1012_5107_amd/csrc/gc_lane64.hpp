@@ -555,13 +555,16 @@ __device__ inline int box_step64(const SceneDev& s, const OptsDev& o, Box64& b, 
 }
 
 // Stepper state on entry into the box at (r, p) (p already refracted).
-__device__ inline Box64 box_enter64(const SceneDev& s, const OptsDev& o, const double r[3], const double p[3])
+// In-box state just inside a face at r; W is W0 at r (the value the walk
+// through air used for the index at the face).
+__device__ inline Box64 box_enter64(const SceneDev& s, const OptsDev& o, const double r[3], const double p[3],
+                                    cx<double> W)
 {
     Box64 b;
     b.u = {r[0], r[1], p[0], p[1]};
     b.z = r[2];
     b.pz = p[2];
-    b.r1.W = w0_cold(zarg64(s, b.u.x, b.u.y));
+    b.r1.W = W;
     rhs64(s, b.u.x, b.u.y, b.r1.W, b.r1.ax, b.r1.ay, b.r1.dW);
     b.h = (o.integ == 0) ? o.h : o.h0;
     b.last_rej = false;
@@ -571,9 +574,9 @@ __device__ inline Box64 box_enter64(const SceneDev& s, const OptsDev& o, const d
 // Integrate inside the box from (r, p) just inside a face.  On RS_OK r, p
 // hold the exit point and the momentum in air.
 __device__ inline int integrate_box64(const SceneDev& s, const OptsDev& o, double r[3], double p[3],
-                                      LaneCount& cnt, double* min_cos)
+                                      cx<double> W, LaneCount& cnt, double* min_cos)
 {
-    Box64 b = box_enter64(s, o, r, p);
+    Box64 b = box_enter64(s, o, r, p, W);
     for (;;) {
         if (cnt.steps >= o.max_steps) return RS_MAX_STEPS;
         int st = RS_OK;
@@ -588,11 +591,14 @@ enum AirOutcome { AO_ESCAPED = 0, AO_ENTERED = 1, AO_FAIL = 2 };
 
 // Straight flight from (r, p) through air, reflecting off the bare grating,
 // until the ray escapes (p = unit exit direction) or enters the box (r on the
-// face, p refracted inside).  The acceleration of eq. (11) vanishes outside
-// the cloak.
+// face, p refracted inside, *w_in = W0 at r).  The acceleration of eq. (11)
+// vanishes outside the cloak.
 __device__ inline int air_walk(const SceneDev& s, const OptsDev& o, double r[3], double p[3], LaneCount& cnt,
-                               double* min_cos, int* status)
+                               double* min_cos, int* status, cx<double>* w_in)
 {
+    // highest point of the metal: a ray that enters through the top face
+    // above it has met no metal on the way
+    const double s_top = (s.mirror == 1 || s.A == 0.0) ? 0.0 : s.A;
     for (;;) {
         if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(p[0]) && isfinite(p[1]) &&
               isfinite(p[2]))) {
@@ -601,8 +607,8 @@ __device__ inline int air_walk(const SceneDev& s, const OptsDev& o, double r[3],
         }
         int face;
         double tb = air_box_entry(s, r, p, &face);
-        double xi;
-        double tg = air_contact(s, r, p, &xi);
+        double xi = 0.0;
+        const double tg = (face == 0 && s.ytop > s_top) ? kInf : air_contact(s, r, p, &xi);
         if (!(tb < kInf) && !(tg < kInf)) return AO_ESCAPED;
         if (++cnt.events > o.max_events) { *status = RS_MAX_EVENTS; return AO_FAIL; }
         if (tg <= tb) {
@@ -630,6 +636,7 @@ __device__ inline int air_walk(const SceneDev& s, const OptsDev& o, double r[3],
         cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
         double n2 = 1.0 / sqrt(norm2(mk(1.0 + W.re, W.im)));
         if (!snell(p, nf, n2)) continue;
+        *w_in = W;
         return AO_ENTERED;
     }
 }
@@ -644,13 +651,14 @@ __device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const dou
     double p[3] = {dir[0] / nd, dir[1] / nd, dir[2] / nd};
     for (;;) {
         int st = RS_OK;
-        int ao = air_walk(s, o, r, p, cnt, min_cos, &st);
+        cx<double> W;
+        int ao = air_walk(s, o, r, p, cnt, min_cos, &st, &W);
         if (ao == AO_FAIL) return st;
         if (ao == AO_ESCAPED) {
             for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
             return RS_OK;
         }
-        st = integrate_box64(s, o, r, p, cnt, min_cos);
+        st = integrate_box64(s, o, r, p, W, cnt, min_cos);
         if (st != RS_OK) return st;
     }
 }

@@ -208,11 +208,12 @@ __device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, con
 {
     double mc = 1.0;
     int st = RS_OK;
-    int ao = air_walk(s, a.o, r, p, cnt, &mc, &st);
+    cx<double> W;
+    int ao = air_walk(s, a.o, r, p, cnt, &mc, &st, &W);
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return -1; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return -1; }
-    Box64 b = box_enter64(s, a.o, r, p);
+    Box64 b = box_enter64(s, a.o, r, p, W);
     store_box64(a, q, s, b);
     a.R.status[q] = RS_OK;
     return box_dest(a, p);
@@ -667,11 +668,12 @@ __device__ __forceinline__ int air_body(const WfArgs& a, long long q, const Scen
     LaneCount cnt = {a.R.steps[q], a.R.rej[q], a.R.events[q], 0};
     double mc = 1.0;
     int st = RS_OK;
-    int ao = air_walk(s, a.o, r, p, cnt, &mc, &st);
+    cx<double> W;
+    int ao = air_walk(s, a.o, r, p, cnt, &mc, &st, &W);
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return 2; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return 2; }
-    Box64 b = box_enter64(s, a.o, r, p);
+    Box64 b = box_enter64(s, a.o, r, p, W);
     store_box64(a, q, s, b);
     a.R.status[q] = RS_OK;
     pin[0] = p[0]; pin[1] = p[1]; pin[2] = p[2];
