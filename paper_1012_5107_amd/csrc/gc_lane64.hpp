@@ -32,20 +32,26 @@ struct LaneCount {
 // Grating geometry, eq. (2): x = xi - A sin(k xi), y = A cos(k xi).
 // ---------------------------------------------------------------------------
 // Solve M = E - e sin E (e < 1) for E: safeguarded Newton in [M - e, M + e].
+// It stops once the residual is at the rounding level of its terms (with
+// the last Newton step applied): at that point the Newton iterate lands on
+// an end of the bracket, where the safeguard would otherwise bisect on.
 __device__ inline double kepler_E(double M, double e)
 {
     double lo = M - e, hi = M + e;
     double E = M + e * sin(M);
+    const double noise = 4.0 * 2.220446049250313e-16 * (fabs(M) + 2.0 * e + 1.0);
     for (int it = 0; it < 60; ++it) {
         double sn, c;
         sincos(E, &sn, &c);
-        double f = E - e * sn - M;
+        const double f = E - e * sn - M;
+        const double dE = f / (1.0 - e * c);
+        if (fabs(f) <= noise) { E -= dE; break; }
         if (f > 0.0) hi = E; else lo = E;
-        double En = E - f / (1.0 - e * c);
+        double En = E - dE;
         if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
-        double dE = En - E;
+        const double step = En - E;
         E = En;
-        if (fabs(dE) <= 1e-15 * fmax(1.0, fabs(E))) break;
+        if (fabs(step) <= 1e-15 * fmax(1.0, fabs(E))) break;
     }
     return E;
 }
@@ -149,6 +155,15 @@ __device__ __noinline__ double air_contact(const SceneDev& s, const double r[3],
                 double dG;
                 double g = sg * line_G(s, z, x0, y0, dx, dy, &dG);
                 dG *= sg;
+                // residual at the rounding level of G's terms: converged
+                // (see kepler_E); the last Newton step stays in the bracket
+                const double noise = 4.0 * 2.220446049250313e-16 *
+                                     (fabs(dy) * (fabs(z) + A + fabs(x0)) + fabs(dx) * (A + fabs(y0)));
+                if (fabs(g) <= noise) {
+                    const double zn = z - g / dG;
+                    if ((zn - lo) * (zn - hi) <= 0.0 && isfinite(zn)) z = zn;
+                    break;
+                }
                 if (g > 0.0) lo = z; else hi = z;
                 double zn = z - g / dG;
                 bool inside = (zn - lo) * (zn - hi) < 0.0;

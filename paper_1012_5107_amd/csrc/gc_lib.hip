@@ -238,7 +238,7 @@ struct WfStore {
     long long cap_rays = 0;
     int cap_scenes = 0;
     void* rays = nullptr;       // one allocation for all per-ray arrays
-    int* queues = nullptr;      // 5 x cap_rays: box (2 rounds), FP64, slow box (2 rounds)
+    int* queues = nullptr;      // 6 x cap_rays: box (2 rounds), FP64, slow box (2 rounds), air
     void* tables = nullptr;     // scenes, cameras, offsets, image pointers
     QCtr* ctr = nullptr;
     WfTotals* tot = nullptr;
@@ -695,7 +695,7 @@ static gc_status wf_reserve(gc_ctx* ctx, WfStore& w, long long n_rays, int n_sce
         w.cap_rays = 0;
         long long cap = n_rays + n_rays / 8;
         if (hipMalloc(&w.rays, wf_ray_bytes(cap) + 64 * 256) != hipSuccess ||
-            hipMalloc((void**)&w.queues, sizeof(int) * 5 * (size_t)cap) != hipSuccess)
+            hipMalloc((void**)&w.queues, sizeof(int) * 6 * (size_t)cap) != hipSuccess)
             return fail(GC_ENOMEM, "pipeline ray buffers (%lld rays): allocation failed", cap);
         w.cap_rays = cap;
     }
@@ -743,6 +743,22 @@ static unsigned wf_box_max(const gc_ctx* ctx, const WfStore& w, int integ)
     return (unsigned)box_max;
 }
 
+// Grid of the air kernel: its queue length is known on the device only.
+static unsigned wf_air_blocks(const gc_ctx* ctx, const WfArgs& a)
+{
+    return (unsigned)std::max<long long>(1, std::min<long long>((a.n_rays + 255) / 256, 2ll * ctx->n_cu));
+}
+
+// Start of a launch: counters zeroed, camera (or given) rays to the box
+// queues of the first round; the rays whose first leg meets the bare grating
+// walk in the air kernel.  Enqueues kernels only, so that a graph can hold it.
+static void wf_start(const gc_ctx* ctx, WfStore& w, const WfArgs& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, stream, w.ctr, w.tot);
+    hipLaunchKernelGGL(k_wf_init, dim3((unsigned)((a.n_rays + 255) / 256)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_wf_air, dim3(wf_air_blocks(ctx, a)), dim3(256), 0, stream, a, 0);
+}
+
 // One round: the in-box kernel takes every ray of the round's queues
 // through its visit (or to a step that needs FP64), the FP64 kernel takes
 // those steps, the air kernel walks the rays that left.  With timing, HIP
@@ -751,7 +767,6 @@ static unsigned wf_box_max(const gc_ctx* ctx, const WfStore& w, int integ)
 static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, unsigned box_g, unsigned air_g,
                           bool timing, hipStream_t stream)
 {
-    const unsigned scan_g = (unsigned)std::min<long long>((a.n_rays + 255) / 256, 8ll * ctx->n_cu);
     hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
     if (timing) HIP_OK(hipEventRecord(w.ev[1], stream));
     if (a.o.integ == 0)
@@ -763,7 +778,7 @@ static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, uns
         hipLaunchKernelGGL(k_wf_event<0>, dim3(air_g), dim3(256), 0, stream, a, cur);
     else
         hipLaunchKernelGGL(k_wf_event<1>, dim3(air_g), dim3(256), 0, stream, a, cur);
-    hipLaunchKernelGGL(k_wf_air, dim3(scan_g), dim3(256), 0, stream, a, cur);
+    hipLaunchKernelGGL(k_wf_air, dim3(wf_air_blocks(ctx, a)), dim3(256), 0, stream, a, cur ^ 1);
     if (timing) HIP_OK(hipEventRecord(w.ev[3], stream));
     HIP_OK(hipGetLastError());
     return GC_OK;
@@ -774,14 +789,12 @@ static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, uns
 static gc_status wf_run(gc_ctx* ctx, WfStore& w, WfArgs& a, hipStream_t stream)
 {
     const int integ = a.o.integ;
-    const unsigned init_blocks = (unsigned)((a.n_rays + 255) / 256);
     w.fp64_steps = 0;
     w.rounds = 0;
     w.tail_rays = 0;
     w.hot_ms = w.event_ms = w.tail_ms = 0.0;
     HIP_OK(hipEventRecord(w.ev[0], stream));
-    hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, stream, w.ctr, w.tot);
-    hipLaunchKernelGGL(k_wf_init, dim3(init_blocks), dim3(256), 0, stream, a);
+    wf_start(ctx, w, a, stream);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
@@ -820,6 +833,7 @@ static WfArgs wf_args(const gc_ctx* ctx, const WfStore& w, const OptsDev& o, int
     a.qev = w.queues + 2 * w.cap_rays;
     a.qslow[0] = w.queues + 3 * w.cap_rays;
     a.qslow[1] = w.queues + 4 * w.cap_rays;
+    a.qair = w.queues + 5 * w.cap_rays;
     a.sch.slow_pxy2 = (float)(ctx->tune.slow_pxy * ctx->tune.slow_pxy);
     a.sch.slow_div = ctx->tune.slow_wave_div;
     a.sch.refill = ctx->tune.refill;

@@ -97,8 +97,7 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
         return bail(fail(GC_EDEVICE, "hipStreamBeginCapture failed"));
     gc_status cr = GC_OK;
     do {
-        hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, cs, p->w.ctr, p->w.tot);
-        hipLaunchKernelGGL(k_wf_init, dim3((unsigned)((p->a.n_rays + 255) / 256)), dim3(256), 0, cs, p->a);
+        wf_start(ctx, p->w, p->a, cs);
         const unsigned box_g = wf_box_max(ctx, p->w, o.integ);
         const unsigned air_g = (unsigned)(8 * ctx->n_cu);
         for (int round = 0; round < p->rounds && cr == GC_OK; ++round)

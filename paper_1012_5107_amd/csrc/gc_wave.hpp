@@ -47,6 +47,7 @@ struct QCtr {
     unsigned slow_head[2];
     unsigned ev_len;
     unsigned ev_head;
+    unsigned air_len;               // rays whose walk through air needs the contact search
     unsigned long long hot_steps;   // accepted steps taken by k_wf_box (all rounds)
 };
 
@@ -60,8 +61,7 @@ struct WfRays {
     float* rgb;   // 3 per ray
 };
 
-// WF_IN_AIR: the ray left the box (state in rx..qz); the air kernel takes it
-enum WfFlag { WF_LAST_REJ = 1, WF_IN_AIR = 2 };
+enum WfFlag { WF_LAST_REJ = 1 };
 
 // Scheduling of the in-box kernel (what is computed does not depend on it).
 struct WfSched {
@@ -76,6 +76,7 @@ struct WfArgs {
     int* qslow[2];     // box entries predicted to take many steps
     WfSched sch;
     int* qev;
+    int* qair;         // rays in air (state in rx..qz) for the air kernel
     QCtr* ctr;
     const SceneDev* scenes;
     const CamDev* cams;
@@ -182,6 +183,45 @@ __device__ __forceinline__ void push_box_wave(const WfArgs& a, int nxt, int dest
     else if (dest == 1) a.qslow[nxt][b1 + (unsigned)__popcll(m1 & below)] = q;
 }
 
+// Append q to the air queue where `want` holds, one atomic per wave.  Every
+// active lane of the wave calls it together.
+__device__ __forceinline__ void push_air_wave(const WfArgs& a, bool want, int q)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(want);
+    if (!m) return;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned b = 0;
+    if (lane == leader) b = atomicAdd(&a.ctr->air_len, (unsigned)__popcll(m));
+    b = __shfl(b, leader, 64);
+    if (want) a.qair[b + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = q;
+}
+
+// The first leg of a walk through air from (r, p) needs no search for a
+// contact with the bare grating: the metal is flat, or the ray moves up from
+// above its highest point, or it enters through the top face above it.
+// (Only decides which kernel walks the ray; the walk is the same.)
+__device__ __forceinline__ bool air_leg_plain(const SceneDev& s, const double r[3], const double p[3])
+{
+    if (s.mirror == 1 || s.A == 0.0) return true;
+    if (p[1] > 0.0 && r[1] >= s.A) return true;
+    int face;
+    air_box_entry(s, r, p, &face);
+    return face == 0 && s.ytop > s.A;
+}
+
+// The walk through air from (r, p) ends at once with an escape (no face, no
+// metal ahead): exactly the case in which air_walk returns AO_ESCAPED without
+// an event.
+__device__ __forceinline__ bool air_escapes_now(const SceneDev& s, const double r[3], const double p[3])
+{
+    if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])))
+        return false;
+    if (!(p[1] > 0.0 && (s.mirror == 1 || s.A == 0.0 || r[1] >= s.A))) return false;
+    int face;
+    return !(air_box_entry(s, r, p, &face) < kInf);
+}
+
 // terminal state: exit ray in air, or a failure (black)
 __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const SceneDev& s, int status,
                                            const double r[3], const double p[3])
@@ -241,10 +281,14 @@ __global__ void __launch_bounds__(256) k_wf_reset(QCtr* c, int cur)
         c->slow_head[cur ^ 1] = 0;
         c->ev_len = 0;
         c->ev_head = 0;
+        c->air_len = 0;
     }
 }
 
-__device__ __forceinline__ int init_ray(const WfArgs& a, long long q)
+// Returns the box queue of the ray (-1: none); *deferred: the ray's first
+// leg through air needs the contact search, its state is stored for the air
+// kernel (so that the few such lanes do not hold up whole waves here).
+__device__ __forceinline__ int init_ray(const WfArgs& a, long long q, bool* deferred)
 {
     int si = scene_of(a, q);
     const SceneDev s = a.scenes[si];
@@ -267,6 +311,13 @@ __device__ __forceinline__ int init_ray(const WfArgs& a, long long q)
     a.R.fbk[q] = 0;
     a.R.steps[q] = 0;
     a.R.rej[q] = 0;
+    if (!air_leg_plain(s, r, p)) {
+        a.R.events[q] = 0;
+        a.R.rx[q] = r[0]; a.R.ry[q] = r[1]; a.R.rz[q] = r[2];
+        a.R.qx[q] = p[0]; a.R.qy[q] = p[1]; a.R.qz[q] = p[2];
+        *deferred = true;
+        return -1;
+    }
     LaneCount cnt = {0, 0, 0, 0};
     return continue_in_air(a, q, s, r, p, cnt);
 }
@@ -276,8 +327,10 @@ __global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
 {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int dest = -1;
-    if (q < a.n_rays) dest = init_ray(a, q);
+    bool deferred = false;
+    if (q < a.n_rays) dest = init_ray(a, q, &deferred);
     push_box_wave(a, 0, dest, (int)q);
+    push_air_wave(a, deferred, (int)q);
 }
 
 // In-box event location in FP32: regula falsi with the Illinois
@@ -605,10 +658,13 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
         if (fin >= 0) {
             const double zero[3] = {0.0, 0.0, 0.0};
             finish_ray(a, q, *sp, fin, r, zero);
+        } else if (air_escapes_now(*sp, r, p3)) {
+            // leaves the box with nothing ahead: the sky, as the air kernel would
+            finish_ray(a, q, *sp, RS_OK, r, p3);
         } else {
             R.rx[q] = r[0]; R.ry[q] = r[1]; R.rz[q] = r[2];
             R.qx[q] = p3[0]; R.qy[q] = p3[1]; R.qz[q] = p3[2];
-            R.flags[q] = WF_IN_AIR;
+            push(a.qair, &a.ctr->air_len, q);
         }
         active = false;
         loc = false;
@@ -689,34 +745,37 @@ __global__ void __launch_bounds__(256) k_wf_event(WfArgs a, int cur)
     for (unsigned base = blockIdx.x * blockDim.x; base < qlen; base += gridDim.x * blockDim.x) {
         const unsigned qi = base + threadIdx.x;
         int dest = -1, q = 0;
+        bool air = false;
         if (qi < qlen) {
             q = a.qev[qi];
             const SceneDev s = a.scenes[a.R.scene[q]];
             int r = event_body<INTEG>(a, q, s);
             // a visit that goes on in FP32 next round: the fast queue
             if (r == 0) dest = 0;
-            else if (r == 1) a.R.flags[q] = WF_IN_AIR;
+            else if (r == 1) air = true;
         }
         push_box_wave(a, cur ^ 1, dest, q);
+        push_air_wave(a, air, q);
     }
 }
 
-// Rays that left the box this round (flag WF_IN_AIR): walk through air
-// (FP64).  The rays are found by a scan of the flags, so that the in-box
-// kernel hands a ray over with a plain store.
-__global__ void __launch_bounds__(256) k_wf_air(WfArgs a, int cur)
+// The air queue (rays that left the box this round other than straight to
+// the sky, or camera rays whose first leg meets the bare grating): walk
+// through air in FP64; a ray that enters the box goes to box queue nxt.
+__global__ void __launch_bounds__(256) k_wf_air(WfArgs a, int nxt)
 {
-    for (long long base = (long long)blockIdx.x * blockDim.x; base < a.n_rays;
-         base += (long long)gridDim.x * blockDim.x) {
-        const long long q = base + threadIdx.x;
-        int dest = -1;
-        if (q < a.n_rays && (a.R.flags[q] & WF_IN_AIR)) {
-            a.R.flags[q] = 0;
+    const unsigned len = a.ctr->air_len;
+    // the loop bound is uniform over the block, so that the pushes see every lane
+    for (unsigned base = blockIdx.x * blockDim.x; base < len; base += gridDim.x * blockDim.x) {
+        const unsigned i = base + threadIdx.x;
+        int dest = -1, q = 0;
+        if (i < len) {
+            q = a.qair[i];
             const SceneDev s = a.scenes[a.R.scene[q]];
             double p[3];
             if (air_body(a, q, s, p) == 0) dest = box_dest(a, p);
         }
-        push_box_wave(a, cur ^ 1, dest, (int)q);
+        push_box_wave(a, nxt, dest, q);
     }
 }
 
