@@ -46,7 +46,10 @@ FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
 # size (profiles/k_wf_box_dopri5_512x512x4_tuned.txt); keyed by (rtol, h_max,
 # integrator); absent: not measured for this kernel and setting
-TRAFFIC_K_WF_BOX = {(1e-7, 0.2, "dopri5"): 4.50e8}
+TRAFFIC_K_WF_BOX = {(1e-7, 0.2, "dopri5"): 4.77e8}
+# the same for the 64-scene batch, summed over the two pipeline rounds of one
+# render (profiles/k_wf_box_dopri5_batch64.txt); keyed by (rtol, h_max)
+TRAFFIC_K_WF_BOX_BATCH = {(1e-7, 0.02): 5.24e10}
 
 
 def parse():
@@ -302,8 +305,9 @@ def main_batch(args):
                      "candidates": [{k: c[k] for k in ("rtol", "h_max", "ms", "steps", "dir_p99", "dir_max", "changed",
                                                        "cc_err", "passed")} for c in rep["candidates"]]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_wf_box<DOPRI5>",
-                     "kernel_ms": stk["hot_ms"], "kernel_steps": stk["hot_steps"]},
+                     "frac": achieved / PEAK_FP32,
+                     "traffic": TRAFFIC_K_WF_BOX_BATCH.get((op32["rtol"], op32["h_max"])),
+                     "kernel": "k_wf_box<DOPRI5>", "kernel_ms": stk["hot_ms"], "kernel_steps": stk["hot_steps"]},
         "fp32_breakdown": {k: stk[k] for k in ("hot_ms", "event_ms", "total_ms", "rounds", "fp64_steps",
                                                "fallbacks", "failed")},
     }
