@@ -149,7 +149,9 @@ __device__ __forceinline__ void rk4_step32(const Sc32& c, const St32& u, const R
     renorm_cell(c, ue);
 }
 
-// DOPRI5 step in FP32; returns the scaled RMS error over (x, y, px, py).
+// DOPRI5 step in FP32; returns the square of the scaled RMS error over
+// (x, y, px, py) (the step control needs only comparisons with 1 and a power
+// of it, so no square root is taken).
 __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const Rhs32& r1, float h, float rtol,
                                             float atol, St32& ue, Rhs32& re, bool& bad)
 {
@@ -190,6 +192,7 @@ __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const 
         float sx = 0, sy = 0, sax = 0, say = 0;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
+            if (j == 1) continue;   // b2 = 0
             sx += A[5][j] * kx[j];
             sy += A[5][j] * ky[j];
             sax += A[5][j] * kax[j];
@@ -211,6 +214,7 @@ __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const 
     float ex = 0, ey = 0, epx = 0, epy = 0;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
+        if (j == 1) continue;   // e2 = 0
         ex += E[j] * kx[j];
         ey += E[j] * ky[j];
         epx += E[j] * kax[j];
@@ -221,7 +225,7 @@ __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const 
     float q1 = h * ey * __builtin_amdgcn_rcpf(atol + rtol * fmaxf(fabsf(u.y), fabsf(ue.y)));
     float q2 = h * epx * __builtin_amdgcn_rcpf(atol + rtol * fmaxf(fabsf(u.px), fabsf(ue.px)));
     float q3 = h * epy * __builtin_amdgcn_rcpf(atol + rtol * fmaxf(fabsf(u.py), fabsf(ue.py)));
-    return __builtin_sqrtf(0.25f * (q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3));
+    return 0.25f * (q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
 }
 
 __device__ __forceinline__ bool st32_finite(const St32& u)
@@ -261,10 +265,10 @@ __device__ __forceinline__ void split32(double v, float& hi, float& lo)
     lo = (float)(v - (double)hi);
 }
 
-// err^(-1/5) through the hardware log2/exp2
-__device__ __forceinline__ float pow_m02(float err)
+// err^(-1/5) from err^2, through the hardware log2/exp2
+__device__ __forceinline__ float pow_m02_sq(float err2)
 {
-    return __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
+    return __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(err2));
 }
 
 }  // namespace gc
