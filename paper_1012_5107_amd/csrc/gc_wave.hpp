@@ -222,6 +222,24 @@ __device__ __forceinline__ bool air_escapes_now(const SceneDev& s, const double 
     return !(air_box_entry(s, r, p, &face) < kInf);
 }
 
+// In-box state at an entry for the queues.  Only W (at the entry point, from
+// the walk through air) is stored: the kernel that takes the ray evaluates
+// the field itself, so none is evaluated here.
+__device__ __forceinline__ Box64 box_entry_state(const OptsDev& o, const double r[3], const double p[3],
+                                                 cx<double> W)
+{
+    Box64 b;
+    b.u = {r[0], r[1], p[0], p[1]};
+    b.z = r[2];
+    b.pz = p[2];
+    b.r1.W = W;
+    b.r1.ax = b.r1.ay = 0.0;
+    b.r1.dW = {0.0, 0.0};
+    b.h = (o.integ == 0) ? o.h : o.h0;
+    b.last_rej = false;
+    return b;
+}
+
 // terminal state: exit ray in air, or a failure (black)
 __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const SceneDev& s, int status,
                                            const double r[3], const double p[3])
@@ -253,7 +271,7 @@ __device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, con
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return -1; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return -1; }
-    Box64 b = box_enter64(s, a.o, r, p, W);
+    Box64 b = box_entry_state(a.o, r, p, W);
     store_box64(a, q, s, b);
     a.R.status[q] = RS_OK;
     return box_dest(a, p);
@@ -729,7 +747,7 @@ __device__ __forceinline__ int air_body(const WfArgs& a, long long q, const Scen
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return 2; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return 2; }
-    Box64 b = box_enter64(s, a.o, r, p, W);
+    Box64 b = box_entry_state(a.o, r, p, W);
     store_box64(a, q, s, b);
     a.R.status[q] = RS_OK;
     pin[0] = p[0]; pin[1] = p[1]; pin[2] = p[2];
