@@ -81,6 +81,46 @@ def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32, max_factor):
                      max_factor=max_factor)
 
 
+def _air_path_rays(hw, n, seed):
+    """Seeded rays that start in air and take every kind of leg through air:
+    beside the box heading down to the bare grating (which they meet before
+    anything else; some then enter through a side face), level with the box
+    heading into a side face, and steeply down through the top face (they
+    leave through it straight to the sky)."""
+    rng = np.random.default_rng(seed)
+    m = n // 3
+    org, d = [], []
+    x = np.where(rng.uniform(-1, 1, m) < 0, -1.0, 1.0) * (hw + rng.uniform(0.3, 3.0, m))
+    org.append(np.stack([x, rng.uniform(0.4, 2.0, m), np.zeros(m)], 1))
+    d.append(np.stack([rng.uniform(-0.6, 0.6, m), rng.uniform(-1.0, -0.15, m), rng.uniform(-1, 1, m)], 1))
+    side = np.where(rng.uniform(-1, 1, m) < 0, -1.0, 1.0)
+    org.append(np.stack([side * (hw + 1.0), rng.uniform(0.15, 1.4, m), np.zeros(m)], 1))
+    d.append(np.stack([-side * rng.uniform(0.3, 1.0, m), rng.uniform(-0.3, 0.3, m), rng.uniform(-0.6, 0.6, m)], 1))
+    k = n - 2 * m
+    org.append(np.stack([rng.uniform(-0.5 * hw, 0.5 * hw, k), np.full(k, 3.0), np.zeros(k)], 1))
+    d.append(np.stack([rng.uniform(-0.3, 0.3, k), -np.ones(k), rng.uniform(-0.3, 0.3, k)], 1))
+    org, d = np.concatenate(org), np.concatenate(d)
+    return org, d / np.linalg.norm(d, axis=1, keepdims=True), m
+
+
+@pytest.mark.parametrize("prec,tol,delta", [("f64", 1e-10, 1e-15), ("f32", 1e-4, 1e-6)])
+def test_trace_air_legs_match_oracle(B, prec, tol, delta):
+    """Walks through air in both paths: the contact search on the bare
+    grating, side-face entries and exits, and rays finished in the in-box
+    kernel when they leave straight to the sky."""
+    sc, _, op64, op32 = W.plain_vs_fp32_512()
+    op = op64 if prec == "f64" else dict(op32, rtol=1e-7, atol=1e-7)
+    org, d, m = _air_path_rays(sc["half_width"], 600, 11)
+    orc = O.trace_rays(sc, op, org, d)
+    # the rays take the legs they were made for
+    assert np.mean(orc["contacts"][:m] > 0) > 0.9 and np.mean(orc["steps"][:m] > 0) > 0.1
+    assert np.mean(orc["steps"][m:2 * m] > 0) > 0.8
+    assert np.all(orc["steps"][2 * m:] > 0) and np.all(orc["dir"][2 * m:, 1] > 0)
+    oo, od, st, steps, ev = _gpu_trace(B, sc, op, org, d, prec)
+    assert np.array_equal(st, orc["status"])
+    check_directions(O, sc, op, org, d, orc, od, st, ev, tol, delta, f"air legs {prec}")
+
+
 @pytest.mark.parametrize("prec,tol_px", [("f64", 1e-6), ("f32", 5e-3)])
 def test_render_and_cc_match_oracle_plain_64(B, prec, tol_px):
     sc, cam, op = W.plain_64()
