@@ -302,7 +302,8 @@ gc_status gc_trace_rays(gc_ctx* ctx, const gc_scene* scene, const gc_opts* opts,
 /* Render one image (Sec. 4): d_rgb is height x width x 3 float32 (HWC, row
  * 0 at the top), each pixel the mean of its spp sky colours (failed samples
  * black).  With scene->mirror = 1 (flat mirror, cloak = 0) the reference
- * image is produced in closed form (FP64 sky lookup for either precision).
+ * image is produced in closed form (FP64 direction and sky angles, FP32 tanh,
+ * for either precision).
  * The FP32 pipeline looks the sky up in FP32 (the image is FP32).  `st` (host, may
  * be null) receives the counters and then the call synchronises the
  * stream. */

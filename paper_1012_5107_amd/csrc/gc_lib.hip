@@ -112,10 +112,9 @@ __global__ void __launch_bounds__(256) k_render64(SceneDev s, CamDev cam, OptsDe
 }
 
 // Reference image: flat mirror y = 0 in air.  A downward ray leaves with
-// d_y negated; an upward one sees the sky directly.  T: precision of the
-// sky lookup and the pixel mean (the camera ray is FP64); the reference is
-// rendered in FP64 for both precisions of the cloaked image.
-template <typename T>
+// d_y negated; an upward one sees the sky directly.  The camera ray and the
+// sky's angles are FP64, its tanh FP32 (sky_rgb_image); the same reference
+// serves both precisions of the cloaked image.
 __global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float* rgb, DevCounters* cnt)
 {
     long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,18 +122,17 @@ __global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float
     unsigned long long c_rays = 0, c_ev = 0;
     if (pix < npx) {
         int i = (int)(pix % cam.W), j = (int)(pix / cam.W);
-        T acc[3] = {0, 0, 0};
+        double acc[3] = {0, 0, 0};
         for (int smp = 0; smp < cam.spp; ++smp) {
             double d[3];
             camera_dir(cam, i, j, smp, d);
             if (d[1] < 0.0 && cam.eye[1] > 0.0) { d[1] = -d[1]; c_ev++; }
-            const T dt[3] = {(T)d[0], (T)d[1], (T)d[2]};
-            T c[3];
-            sky_rgb<T>((T)K, dt, c);
-            for (int a = 0; a < 3; ++a) acc[a] += c[a];
+            float c[3];
+            sky_rgb_image(K, d, c);
+            for (int a = 0; a < 3; ++a) acc[a] += (double)c[a];
         }
         c_rays = cam.spp;
-        for (int a = 0; a < 3; ++a) rgb[3 * pix + a] = (float)(acc[a] / (T)cam.spp);
+        for (int a = 0; a < 3; ++a) rgb[3 * pix + a] = (float)(acc[a] / cam.spp);
     }
     add_counters(cnt, c_rays, 0, 0, c_ev, 0, 0);
 }
@@ -1118,7 +1116,7 @@ static gc_status render_impl(gc_ctx* ctx, const gc_scene* scene, const gc_camera
     long long npx = (long long)c.W * c.H;
     unsigned nb = (unsigned)((npx + 255) / 256);
     if (scene->mirror == 1)
-        hipLaunchKernelGGL(k_render_flat<double>, dim3(nb), dim3(256), 0, stream, c, s.K, d_rgb, ctx->d_cnt);
+        hipLaunchKernelGGL(k_render_flat, dim3(nb), dim3(256), 0, stream, c, s.K, d_rgb, ctx->d_cnt);
     else if (opts->prec == GC_F64)
         hipLaunchKernelGGL(k_render64, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
     else

@@ -107,7 +107,7 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
         for (int i = 0; i < n_scenes && p->corr; ++i) {
             const long long npix = (long long)cd[i].W * cd[i].H;
             if (render_refs)
-                hipLaunchKernelGGL(k_render_flat<double>, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, cs, cd[i],
+                hipLaunchKernelGGL(k_render_flat, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, cs, cd[i],
                                    sd[i].K, d_ref[i], p->d_flatcnt);
             long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
             hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, cs, (const float*)d_rgb[i],
