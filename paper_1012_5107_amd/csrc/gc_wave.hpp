@@ -408,8 +408,51 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
     int side = 0, emask = 0, lit = 0, hicode = -1;
     bool need64 = false;   // the next step from u needs FP64
     unsigned my_steps = 0;
+    // a lane whose visit has ended: 0 none, 1 + the face it left through, or
+    // 16 + its failure status.  The lane is idle until the wave refills, so
+    // its exit is written then, together with the other lanes' (once per
+    // refill instead of once per iteration in which some lane finishes).
+    int pend = 0;
 
     for (;;) {
+        if (__ballot(pend != 0)) {
+            const unsigned long long idle = __ballot(!active);
+            if (exhausted || (unsigned)__popcll(idle) >= kRefill || __ballot(active) == 0ull) {
+                bool to_air = false;
+                if (pend != 0) {
+                    // the ray's exit from the box: a point and direction in air
+                    const WfRays& R = a.R;
+                    double r[3] = {(double)u.cell * sp->L + ((double)u.fx + (double)u.lx),
+                                   (double)u.y + (double)u.ly, z0 + (double)pz * ((double)tau + (double)ltau)};
+                    R.steps[q] = steps;
+                    R.rej[q] = rej;
+                    R.events[q] = nev;
+                    R.fbk[q] = fbk;
+                    if (pend >= 16) {
+                        const double zero[3] = {0.0, 0.0, 0.0};
+                        finish_ray(a, q, *sp, pend - 16, r, zero);
+                    } else {
+                        // the refraction out of the face, recomputed from the
+                        // same state as when the event was applied
+                        double p3[3] = {(double)u.px + (double)u.lpx, (double)u.py + (double)u.lpy, (double)pz};
+                        double nf[3] = {0.0, 0.0, 0.0};
+                        const int face = pend - 1;
+                        if (face == 0) nf[1] = 1.0; else if (face == 1) nf[0] = 1.0; else nf[0] = -1.0;
+                        snell(p3, nf, 1.0);
+                        if (air_escapes_now(*sp, r, p3)) {
+                            // nothing ahead: the sky, as the air kernel would
+                            finish_ray(a, q, *sp, RS_OK, r, p3);
+                        } else {
+                            R.rx[q] = r[0]; R.ry[q] = r[1]; R.rz[q] = r[2];
+                            R.qx[q] = p3[0]; R.qy[q] = p3[1]; R.qz[q] = p3[2];
+                            to_air = true;
+                        }
+                    }
+                    pend = 0;
+                }
+                push_air_wave(a, to_air, q);
+            }
+        }
         if (!exhausted) {
             unsigned long long idle = __ballot(!active);
             // claim in batches: one atomic per wave for at least kRefill lanes
@@ -483,6 +526,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
 
         int fin = -1;           // >= 0: the ray finishes with this status
         bool leaves = false;    // the ray left the box
+        int lface = 0;          // ... through this face
         double p3[3] = {0.0, 0.0, 0.0};
         if (!loc && steps >= max_steps) {
             fin = RS_MAX_STEPS;
@@ -634,6 +678,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                             if (evc == 0) nf[1] = 1.0; else if (evc == 1) nf[0] = 1.0; else nf[0] = -1.0;
                             if (snell(p3, nf, 1.0)) {
                                 leaves = true;
+                                lface = evc;
                             } else {
                                 split32(p3[0], u.px, u.lpx);
                                 split32(p3[1], u.py, u.lpy);
@@ -665,25 +710,8 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             continue;
         }
         if (fin < 0 && !leaves) continue;
-        // the ray ends its visit of the box: as a point and direction in air
-        const WfRays& R = a.R;
-        double r[3] = {(double)u.cell * sp->L + ((double)u.fx + (double)u.lx), (double)u.y + (double)u.ly,
-                       z0 + (double)pz * ((double)tau + (double)ltau)};
-        R.steps[q] = steps;
-        R.rej[q] = rej;
-        R.events[q] = nev;
-        R.fbk[q] = fbk;
-        if (fin >= 0) {
-            const double zero[3] = {0.0, 0.0, 0.0};
-            finish_ray(a, q, *sp, fin, r, zero);
-        } else if (air_escapes_now(*sp, r, p3)) {
-            // leaves the box with nothing ahead: the sky, as the air kernel would
-            finish_ray(a, q, *sp, RS_OK, r, p3);
-        } else {
-            R.rx[q] = r[0]; R.ry[q] = r[1]; R.rz[q] = r[2];
-            R.qx[q] = p3[0]; R.qy[q] = p3[1]; R.qz[q] = p3[2];
-            push(a.qair, &a.ctr->air_len, q);
-        }
+        // the visit has ended: the exit is written at the next refill
+        pend = fin >= 0 ? 16 + fin : 1 + lface;
         active = false;
         loc = false;
     }
