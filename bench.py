@@ -46,10 +46,10 @@ FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
 # size (profiles/k_wf_box_dopri5_512x512x4_tuned.txt); keyed by (rtol, h_max,
 # integrator); absent: not measured for this kernel and setting
-TRAFFIC_K_WF_BOX = {(1e-7, 0.2, "dopri5"): 4.77e8, (1e-7, 0.5, "dopri5"): 4.78e8, (1e-7, 0.1, "dopri5"): 4.74e8}
+TRAFFIC_K_WF_BOX = {(1e-7, 0.2, "dopri5"): 4.96e8, (1e-7, 0.5, "dopri5"): 4.96e8, (1e-7, 0.1, "dopri5"): 4.92e8}
 # the same for the 64-scene batch, summed over the two pipeline rounds of one
 # render (profiles/k_wf_box_dopri5_batch64.txt); keyed by (rtol, h_max)
-TRAFFIC_K_WF_BOX_BATCH = {(1e-7, 0.02): 5.24e10}
+TRAFFIC_K_WF_BOX_BATCH = {(1e-7, 0.02): 5.60e10}
 
 
 def parse():
