@@ -366,7 +366,7 @@ __device__ __forceinline__ T adj_event(const SceneDev& s, int ev, const AS<T>& u
     case 0: return ((T)s.ytop - u.y) - u.yl;
     case 1: return ((T)s.hw - u.x) - u.xl;
     case 2: return ((T)s.hw + u.x) + u.xl;
-    default: return (u.y + u.W.re * (T)(1.0 / s.k)) + u.yl;
+    default: return (u.y + u.W.re * (T)s.invk) + u.yl;
     }
 }
 
@@ -444,7 +444,7 @@ __device__ inline void event_grad(const SceneDev& s, int ev, const AS<T>& ue, T 
     if (ev == 0) { ge[0] = (T)0; ge[1] = (T)-1; return; }
     if (ev == 1) { ge[0] = (T)-1; ge[1] = (T)0; *ehw = (T)1; return; }
     if (ev == 2) { ge[0] = (T)1; ge[1] = (T)0; *ehw = (T)1; return; }
-    const T k = (T)s.k, ik = (T)(1.0 / s.k);
+    const T k = (T)s.k, ik = (T)s.invk;
     const cx<T> D = {(T)1 + ue.W.re, ue.W.im};
     const cx<T> iD = rcp(norm2(D)) * conjg(D);
     const cx<T> WiD = ue.W * iD;

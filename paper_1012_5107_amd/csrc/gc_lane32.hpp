@@ -29,7 +29,7 @@ __device__ __forceinline__ Sc32 make_sc32(const SceneDev& s, double wfb2)
     c.L = (float)s.L;
     c.invL = (float)s.invL;
     c.k = (float)s.k;
-    c.invk = (float)(1.0 / s.k);
+    c.invk = (float)s.invk;
     c.ne = (float)(-s.e);
     c.mkl2e = (float)(-s.k * kLog2e);
     c.ybp = (float)s.ybp;
@@ -149,9 +149,7 @@ __device__ __forceinline__ void rk4_step32(const Sc32& c, const St32& u, const R
     renorm_cell(c, ue);
 }
 
-// DOPRI5 step in FP32; returns the square of the scaled RMS error over
-// (x, y, px, py) (the step control needs only comparisons with 1 and a power
-// of it, so no square root is taken).
+// DOPRI5 step in FP32; returns the scaled RMS error over (x, y, px, py).
 __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const Rhs32& r1, float h, float rtol,
                                             float atol, St32& ue, Rhs32& re, bool& bad)
 {
@@ -225,7 +223,7 @@ __device__ __forceinline__ float dp5_step32(const Sc32& c, const St32& u, const 
     float q1 = h * ey * __builtin_amdgcn_rcpf(atol + rtol * fmaxf(fabsf(u.y), fabsf(ue.y)));
     float q2 = h * epx * __builtin_amdgcn_rcpf(atol + rtol * fmaxf(fabsf(u.px), fabsf(ue.px)));
     float q3 = h * epy * __builtin_amdgcn_rcpf(atol + rtol * fmaxf(fabsf(u.py), fabsf(ue.py)));
-    return 0.25f * (q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    return __builtin_sqrtf(0.25f * (q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3));
 }
 
 __device__ __forceinline__ bool st32_finite(const St32& u)
@@ -265,10 +263,10 @@ __device__ __forceinline__ void split32(double v, float& hi, float& lo)
     lo = (float)(v - (double)hi);
 }
 
-// err^(-1/5) from err^2, through the hardware log2/exp2
-__device__ __forceinline__ float pow_m02_sq(float err2)
+// err^(-1/5) through the hardware log2/exp2
+__device__ __forceinline__ float pow_m02(float err)
 {
-    return __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(err2));
+    return __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
 }
 
 }  // namespace gc

@@ -359,6 +359,7 @@ static gc_status make_scene(const gc_scene* sc, SceneDev* s)
     s->k = k;
     s->e = sc->A * k;
     s->invL = 1.0 / sc->Lambda;
+    s->invk = 1.0 / k;
     s->ybp = sc->A > 0 ? (1.0 + std::log(s->e)) / k : -HUGE_VAL;
     s->S_hw = (sc->mirror == 0 && std::isfinite(sc->half_width)) ? host_kepler_height(sc->A, sc->Lambda, sc->half_width) : 0.0;
     s->cloak = sc->cloak;

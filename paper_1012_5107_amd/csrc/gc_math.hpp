@@ -30,6 +30,7 @@ constexpr double kInvE = 0.36787944117144232160;
 struct SceneDev {
     double L, A, hw, ytop, K;
     double k, e, invL;
+    double invk;       // 1 / k
     double ybp;        // branch-point height (1 + ln(A k)) / k: Z crosses the cut only below it
     double S_hw;       // grating height at x = +-half_width
     int cloak, mirror;

@@ -534,13 +534,13 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
             const float tstep = loc ? th * hacc : h;
             St32 ue;
             Rhs32 re;
-            float err2 = 0.0f;   // DOPRI5: squared scaled error
+            float err = 0.0f;
             bool bad = false;
             if (INTEG == 0)
                 rk4_step32(c, u, r1, tstep, ue, re, bad);
             else
-                err2 = dp5_step32(c, u, r1, tstep, rtol, atol, ue, re, bad);
-            if (bad || !st32_finite(ue) || (INTEG == 1 && !loc && !isfinite(err2))) {
+                err = dp5_step32(c, u, r1, tstep, rtol, atol, ue, re, bad);
+            if (bad || !st32_finite(ue) || (INTEG == 1 && !loc && !isfinite(err))) {
                 // this step (from u, of length h; the accepted length when
                 // locating) goes to the FP64 path
                 if (loc) h = hacc;
@@ -561,14 +561,14 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                     float hnext = h;
                     bool accepted = true;
                     if (INTEG == 1) {
-                        if (err2 > 1.0f) {
-                            h *= fmaxf(0.2f, 0.9f * pow_m02_sq(err2));
+                        if (err > 1.0f) {
+                            h *= fmaxf(0.2f, 0.9f * pow_m02(err));
                             last_rej = true;
                             ++rej;
                             accepted = false;
                             if (h < hmin) fin = RS_UNDERFLOW;
                         } else {
-                            float fac = (err2 == 0.0f) ? 5.0f : 0.9f * pow_m02_sq(err2);
+                            float fac = (err == 0.0f) ? 5.0f : 0.9f * pow_m02(err);
                             fac = fminf(5.0f, fmaxf(0.2f, fac));
                             if (last_rej) fac = fminf(fac, 1.0f);
                             last_rej = false;
