@@ -7,21 +7,22 @@
 // queues of ray indices:
 //
 //   k_wf_init    one lane per sample: camera ray (or given ray), flight
-//                through air to the box, the sky, or a failure;
+//                through air to the box, the sky, or a failure; a ray whose
+//                first leg meets the bare grating goes to the air queue;
 //   k_wf_box     persistent FP32 kernel: each wave claims rays from the box
 //                queue (one atomic per wave, ballot + rank for the lanes)
 //                and integrates each through its whole visit of the box:
 //                steps, the location of each event on the partial steps of
 //                the same integrator, grating reflections and total
-//                internal reflections; a ray that leaves the box is flagged
-//                for the air kernel, a ray whose next step needs FP64 (a
-//                stage point near the branch point or a path across the
-//                branch cut) goes to the FP64 queue, and the lane takes a
-//                new ray;
+//                internal reflections; a ray that leaves the box straight
+//                to the sky is finished here, any other that leaves goes to
+//                the air queue, a ray whose next step needs FP64 (a stage
+//                point near the branch point or a path across the branch
+//                cut) goes to the FP64 queue, and the lane takes a new ray;
 //   k_wf_event   FP64: that step (with step control and any event in it);
 //                the ray goes on in the next round's box queue;
-//   k_wf_air     FP64: the flagged rays' flight through air to the box
-//                (next box queue), the sky or a failure;
+//   k_wf_air     FP64: the air queue's flights to the box (next box queue),
+//                the bare grating, the sky or a failure;
 //   k_wf_finish  averages each pixel's samples and folds the counters.
 //
 // Rounds of (k_wf_box, k_wf_event, k_wf_air) repeat until the box queue is
