@@ -139,7 +139,7 @@ template <typename T> __device__ __forceinline__ T icm(cx<T> a, cx<T> b) { retur
 
 // ---------------------------------------------------------------------------
 // Forward RK4 step in precision T.  W0 at each stage is warm-started from
-// the previous stage (first-order predictor, then Halley); a stage whose
+// the previous stage (predictor -- second order in FP64 -- then Halley); a stage whose
 // segment from the previous one crosses the branch cut, or (FP32) comes
 // close to the branch point, takes W0 from scratch in FP64.
 // ---------------------------------------------------------------------------
@@ -148,7 +148,7 @@ __device__ inline cx<T> adj_w(const SceneDev& s, T wfb2, T x, T y, T xp, T yp, c
 {
     if (crosses_cut(s, (double)x, (double)y, (double)xp, (double)yp))
         return cvt<T>(w0_cold(zarg64(s, (double)x, (double)y)));
-    cx<T> W = Wp + dWp * mk<T>(x - xp, y - yp);
+    cx<T> W = sizeof(T) == 8 ? predict_w<T>(s, Wp, dWp, mk<T>(x - xp, y - yp)) : Wp + dWp * mk<T>(x - xp, y - yp);
     const T fx = x - (T)s.L * rint(x * (T)s.invL);
     if constexpr (sizeof(T) == 8) {
         for (int it = 0; it < 8; ++it) {

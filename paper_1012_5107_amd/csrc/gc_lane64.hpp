@@ -248,7 +248,7 @@ struct Rhs64 {
 __device__ inline void rhs_at(const SceneDev& s, double x, double y, double xp, double yp, const Rhs64& prev,
                               Rhs64& out)
 {
-    out.W = prev.W + prev.dW * mk(x - xp, y - yp);
+    out.W = predict_w<double>(s, prev.W, prev.dW, mk(x - xp, y - yp));
     rhs64(s, x, y, out.W, out.ax, out.ay, out.dW, crosses_cut(s, x, y, xp, yp));
 }
 

@@ -234,6 +234,23 @@ __device__ __forceinline__ void accel_from_w(const SceneDev& s, cx<T> W, T& ax, 
     dW = {-k * u.im * r, k * u.re * r};
 }
 
+// Warm start for W0 at zeta + dz from the converged W and W' = dW/dzeta at
+// zeta (W is analytic in zeta = x + i y, since Z = -A k e^{i k zeta}), to
+// second order: W'' = i k W' / (1 + W)^2.  Near the branch point the series
+// converges on a short segment only; there the quadratic term is dropped
+// unless it is well below the linear one.
+template <typename T>
+__device__ __forceinline__ cx<T> predict_w(const SceneDev& s, cx<T> W, cx<T> dW, cx<T> dz)
+{
+    const cx<T> lin = dW * dz;
+    const cx<T> cD = {(T)1 + W.re, -W.im};            // conj(1 + W)
+    const T id2 = rcp(norm2(cD));
+    const cx<T> iD2 = (id2 * id2) * (cD * cD);         // 1 / (1 + W)^2
+    const cx<T> ikdW = {-(T)s.k * dW.im, (T)s.k * dW.re};
+    const cx<T> quad = (T)0.5 * ((ikdW * iD2) * (dz * dz));
+    return norm2(quad) < (T)0.25 * norm2(lin) ? (W + lin) + quad : W + lin;
+}
+
 // FP64 right-hand side with warm start: iterate Halley to convergence.
 // FP64 right-hand side with a warm start: W holds the prediction on entry;
 // Halley steps until the update is at rounding level.  `cold` asks for W0
