@@ -159,8 +159,12 @@ __device__ inline cx<T> adj_w(const SceneDev& s, T wfb2, T x, T y, T xp, T yp, c
         }
         if (!(isfinite(W.re) && isfinite(W.im))) W = w0_cold(zarg64(s, x, y));
     } else {
+        // cubic convergence: after an update below 1e-3 (relative) the
+        // error left is below FP32 resolution; a second step only after a
+        // poor start
+        const cx<T> w0 = W;
         halley_step<T>(s, fx, y, W);
-        halley_step<T>(s, fx, y, W);
+        if (norm2(W - w0) > (T)1e-6 * ((T)1 + norm2(W))) halley_step<T>(s, fx, y, W);
         T d2 = ((T)1 + W.re) * ((T)1 + W.re) + W.im * W.im;
         if (!(d2 >= wfb2) || !(isfinite(W.re) && isfinite(W.im)))
             W = cvt<T>(w0_cold(zarg64(s, (double)x, (double)y)));
