@@ -232,7 +232,7 @@ void gc_batch_plan_destroy(gc_batch_plan* plan);
  *     width / cc_scale x height / cc_scale against the flat-mirror
  *     reference must be within cc_tol of the FP64 image's (with
  *     cc_scale = 1 the timed full-size renders are the ones checked).
- * Candidates (DOPRI5): rtol x {1, 1/3, 1/10} times h_max x {1, 2.5, 5,
+ * Candidates (DOPRI5): rtol x {3, 1, 1/3} times h_max x {1, 2.5, 5,
  * 10, 25}; RK4 keeps its step (one candidate).  Of the candidates that
  * pass, the one with the shortest FP32 render of the whole workload is
  * chosen (best of `reps`); then, if tune_sched, a fixed set of gc_tune
