@@ -235,7 +235,8 @@ void gc_batch_plan_destroy(gc_batch_plan* plan);
  * Candidates (DOPRI5): rtol x {3, 1, 1/3} times h_max x {1, 2.5, 5,
  * 10, 25}; RK4 keeps its step (one candidate).  Of the candidates that
  * pass, the one with the shortest FP32 render of the whole workload is
- * chosen (best of `reps`); then, if tune_sched, a fixed set of gc_tune
+ * chosen (best of `reps`); if none passes, the fastest that is nowhere less
+ * accurate than the options as given (see `chosen`); then, if tune_sched, a fixed set of gc_tune
  * settings is timed the same way and the fastest is installed in the
  * context.  Results never depend on gc_tune.  C0 differences near 1e-4 are
  * at the level by which two correct integrations (FP64 at rtol 1e-7 and
@@ -266,7 +267,10 @@ typedef struct {
 
 typedef struct {
     int32_t n_cand;
-    int32_t chosen;        /* index of the chosen candidate, -1 if none passed (opts_out = opts) */
+    int32_t chosen;        /* index of the candidate returned in opts_out: the fastest that
+                              passed; if none passed, the fastest whose every measured error
+                              (dir_p99, dir_max, changed, cc_err) is at most that of the options
+                              as given (its pass stays 0); -1 if neither (opts_out = opts) */
     gc_autotune_cand cand[GC_AUTOTUNE_MAX_CAND];
     gc_tune tune;          /* installed scheduling */
     double tune_ms;        /* its best render time */

@@ -315,6 +315,33 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
         }
     }
 
+    if (rep.chosen < 0 && n_tol * n_cap > 1) {
+        // no candidate meets the bounds: the fastest one that is nowhere less
+        // accurate than the options as given (every measured error at most
+        // theirs), which keeps the reported accuracy and saves time; its pass
+        // flag stays 0
+        int base = -1;
+        for (int ti = 0; ti < n_tol; ++ti)
+            for (int ci = 0; ci < n_cap; ++ci)
+                if (kTolFactor[ti] == 1.0 && kCapFactor[ci] == 1.0) base = ti * n_cap + ci;
+        const gc_autotune_cand& b = rep.cand[base];
+        double best = b.ms;
+        for (int i = 0; i < rep.n_cand; ++i) {
+            const gc_autotune_cand& c = rep.cand[i];
+            if (c.ms < best && c.dir_p99 <= b.dir_p99 && c.dir_max <= b.dir_max && c.changed <= b.changed &&
+                c.cc_err <= b.cc_err) {
+                best = c.ms;
+                rep.chosen = i;
+            }
+        }
+        if (rep.chosen >= 0) {
+            const int ti = rep.chosen / n_cap, ci = rep.chosen % n_cap;
+            opts_out->rtol = opts->rtol * kTolFactor[ti];
+            opts_out->atol = opts->atol * kTolFactor[ti];
+            opts_out->h_max = opts->h_max * kCapFactor[ci];
+        }
+    }
+
     // ---- scheduling ---------------------------------------------------------
     const gc_tune entry = ctx->tune;
     // the context's scheduling on entry comes back on any early exit

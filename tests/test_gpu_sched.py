@@ -64,6 +64,39 @@ def test_tune_rejects_out_of_range(B):
         ctx.close()
 
 
+def test_autotune_fallback_when_nothing_passes(B):
+    """With bounds no candidate can meet, the autotuner returns the fastest
+    candidate whose every measured error is at most that of the options as
+    given (flagged as not passing), or the options themselves."""
+    sc = W.scene(A=0.1, half_width=3.0)
+    cam = W.camera(64, 48, spp=1, jitter=True, seed=9)
+    op = W.opts("dopri5", rtol=1e-7)
+    ctx = B.Context(0)
+    try:
+        tuned, rep = ctx.autotune(sc, cam, op, dir_scale=2, reps=1, tune_sched=0, dir_tol=1e-12, cc_tol=1e-12)
+        cands = rep["candidates"]
+        assert not any(c["passed"] for c in cands)
+        base = [i for i, c in enumerate(cands) if c["rtol"] == pytest.approx(op["rtol"])
+                and c["h_max"] == pytest.approx(op["h_max"])]
+        assert len(base) == 1
+        b = cands[base[0]]
+        ch = rep["chosen"]
+        if ch < 0:
+            assert (tuned["rtol"], tuned["h_max"]) == (op["rtol"], op["h_max"])
+        else:
+            c = cands[ch]
+            assert c["ms"] < b["ms"]
+            for k in ("dir_p99", "dir_max", "changed", "cc_err"):
+                assert c[k] <= b[k], k
+            assert (tuned["rtol"], tuned["h_max"]) == pytest.approx((c["rtol"], c["h_max"]))
+            # no other no-worse candidate is faster
+            for o in cands:
+                if all(o[k] <= b[k] for k in ("dir_p99", "dir_max", "changed", "cc_err")):
+                    assert o["ms"] >= c["ms"]
+    finally:
+        ctx.close()
+
+
 def test_autotune_small_workload(B):
     """The autotuner keeps every option but h_max, reports the candidates it
     measured, chooses one that passed its own bounds, and installs the
