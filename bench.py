@@ -46,11 +46,11 @@ FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
 # size (profiles/k_wf_box_dopri5_512x512x4_tuned.txt); keyed by (rtol, h_max,
 # integrator); absent: not measured for this kernel and setting
-TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.02e8, (3e-7, 0.2, "dopri5"): 4.99e8, (3e-7, 0.1, "dopri5"): 4.94e8,
+TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.03e8, (3e-7, 0.2, "dopri5"): 4.99e8, (3e-7, 0.1, "dopri5"): 4.94e8,
                     (1e-7, 0.2, "dopri5"): 4.96e8, (1e-7, 0.5, "dopri5"): 4.96e8, (1e-7, 0.1, "dopri5"): 4.92e8}
 # the same for the 64-scene batch, summed over the two pipeline rounds of one
 # render (profiles/k_wf_box_dopri5_batch64.txt); keyed by (rtol, h_max)
-TRAFFIC_K_WF_BOX_BATCH = {(1e-7 / 3, 0.1): 5.81e10, (1e-7, 0.02): 5.60e10}
+TRAFFIC_K_WF_BOX_BATCH = {(1e-7 / 3, 0.1): 5.84e10, (1e-7, 0.02): 5.60e10}
 
 
 def _measured(table, key):
@@ -169,9 +169,26 @@ def main():
             ctx.tune(slow_pxy=float(v[0]), slow_wave_div=int(v[1]), refill=int(v[2]), waves_per_simd=int(v[3]))
         rep, ta = None, 0.0
 
-    dt, st32, c32 = timed(tuned, args.steps)
+    dt_eager, st32, c32 = timed(tuned, args.steps)
     rays = st32["rays"]
-    print(f"# tuned: {dt * 1e3:.1f} ms per step, {st32}", file=sys.stderr, flush=True)
+    print(f"# tuned, eager calls: {dt_eager * 1e3:.1f} ms per step, {st32}", file=sys.stderr, flush=True)
+    # the timed step: the same job captured as one HIP graph (render, flat
+    # reference, C0), as the batch workload runs it -- no host round trips
+    # between the pipeline's rounds and the correlation
+    plan = ctx.batch_plan([sc], [cam], tuned, [img], refs=[ref], render_refs=True)
+    for _ in range(args.warmup):
+        plan.launch()
+        plan.results()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    cg, _ = plan.results()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    plan.close()
+    assert cg[0] == c32, "graph replay differs from the eager render"
+    print(f"# tuned, graph replay: {dt * 1e3:.2f} ms per step", file=sys.stderr, flush=True)
 
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
@@ -186,11 +203,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "512x512, 4 jittered spp, Lambda=1, A=0.1, cloak |x|<=4, y<=1.5, DOPRI5",
+        "config": {"workload": "512x512, 4 jittered spp, Lambda=1, A=0.1, cloak |x|<=4, y<=1.5, DOPRI5, one HIP "
+                               "graph launch per step (render, flat reference, C0)",
                    "rtol_fp32": tuned["rtol"], "h_max_fp32": tuned["h_max"], "rtol_fp64": op64["rtol"],
                    "h_max_fp64": op64["h_max"], "schedule": ctx.tune(), "rays": rays,
                    "ray_steps": st32["accepted_steps"]},
         "ray_steps_per_s": st32["accepted_steps"] / dt,
+        "eager_ms_per_step": dt_eager * 1e3,
         "cc_fp32": c32,
         "roofline": roofline(st32, tuned),
         "fp32_breakdown": {k: st32[k] for k in ("hot_ms", "event_ms", "total_ms", "rounds", "fp64_steps",

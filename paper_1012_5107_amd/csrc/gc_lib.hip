@@ -31,23 +31,30 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
     return v;
 }
 
+// Fold per-thread counters into the device totals (cnt may be null: nothing
+// is counted).  Wave sums by shuffles, block sums in LDS, then one atomic per
+// block and non-zero counter: the counters share a cache line, whose atomics
+// the memory system performs one at a time, so per-wave atomics would bound a
+// short kernel.  Every thread of the block calls it.
 __device__ __forceinline__ void add_counters(DevCounters* c, unsigned long long rays, unsigned long long steps,
                                              unsigned long long rej, unsigned long long ev,
                                              unsigned long long fb, unsigned long long failed)
 {
-    rays = wave_sum(rays);
-    steps = wave_sum(steps);
-    rej = wave_sum(rej);
-    ev = wave_sum(ev);
-    fb = wave_sum(fb);
-    failed = wave_sum(failed);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&c->rays, rays);
-        atomicAdd(&c->steps, steps);
-        atomicAdd(&c->rejected, rej);
-        atomicAdd(&c->events, ev);
-        atomicAdd(&c->fallbacks, fb);
-        atomicAdd(&c->failed, failed);
+    if (!c) return;
+    unsigned long long v[6] = {rays, steps, rej, ev, fb, failed};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+    __shared__ unsigned long long part[4][6];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) part[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        unsigned long long sum = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += part[w][k];
+        // DevCounters is six consecutive counters in the order of v
+        if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(c) + k, sum);
     }
 }
 
@@ -117,11 +124,14 @@ __global__ void __launch_bounds__(256) k_render64(SceneDev s, CamDev cam, OptsDe
 // serves both precisions of the cloaked image.
 __global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float* rgb, DevCounters* cnt)
 {
-    long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long npx = (long long)cam.W * cam.H;
+    const long long npx = (long long)cam.W * cam.H;
     unsigned long long c_rays = 0, c_ev = 0;
-    if (pix < npx) {
-        int i = (int)(pix % cam.W), j = (int)(pix / cam.W);
+    // grid-stride over pixels (the grid is bounded so that the counters take
+    // few atomics); the loop bound is uniform over the block
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < npx; base += (long long)gridDim.x * blockDim.x) {
+        const long long pix = base + threadIdx.x;
+        if (pix >= npx) continue;
+        const int i = (int)(pix % cam.W), j = (int)(pix / cam.W);
         double acc[3] = {0, 0, 0};
         for (int smp = 0; smp < cam.spp; ++smp) {
             double d[3];
@@ -131,10 +141,16 @@ __global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float
             sky_rgb_image(K, d, c);
             for (int a = 0; a < 3; ++a) acc[a] += (double)c[a];
         }
-        c_rays = cam.spp;
+        c_rays += cam.spp;
         for (int a = 0; a < 3; ++a) rgb[3 * pix + a] = (float)(acc[a] / cam.spp);
     }
     add_counters(cnt, c_rays, 0, 0, c_ev, 0, 0);
+}
+
+// Blocks of k_render_flat for npx pixels: one per 256 pixels up to 8 per CU.
+static unsigned flat_blocks(int n_cu, long long npx)
+{
+    return (unsigned)std::max<long long>(1, std::min<long long>((npx + 255) / 256, 8LL * n_cu));
 }
 
 // ---------------------------------------------------------------------------
@@ -754,7 +770,8 @@ static unsigned wf_air_blocks(const gc_ctx* ctx, const WfArgs& a)
 static void wf_start(const gc_ctx* ctx, WfStore& w, const WfArgs& a, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, stream, w.ctr, w.tot);
-    hipLaunchKernelGGL(k_wf_init, dim3((unsigned)((a.n_rays + 255) / 256)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_wf_init, dim3((unsigned)((a.n_rays + 256 * kInitRays - 1) / (256 * kInitRays))), dim3(256), 0,
+                       stream, a);
     hipLaunchKernelGGL(k_wf_air, dim3(wf_air_blocks(ctx, a)), dim3(256), 0, stream, a, 0);
 }
 
@@ -912,8 +929,8 @@ static gc_status wf_setup(gc_ctx* ctx, WfStore& w, int ns, const SceneDev* sc, c
 static gc_status wf_finish(WfStore& w, const WfArgs& a, int ns, long long n_pix, hipStream_t stream)
 {
     WfTables td = wf_tables(w.tables, ns);
-    hipLaunchKernelGGL(k_wf_finish, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, stream, a,
-                       (float* const*)td.images, (const long long*)td.pix_off, n_pix, w.tot);
+    hipLaunchKernelGGL(k_wf_finish, dim3((unsigned)std::min((n_pix + 255) / 256, kFoldBlocks)), dim3(256), 0,
+                       stream, a, (float* const*)td.images, (const long long*)td.pix_off, n_pix, w.tot);
     HIP_OK(hipGetLastError());
     return GC_OK;
 }
@@ -949,8 +966,8 @@ static gc_status wf_trace(gc_ctx* ctx, const SceneDev& s, const OptsDev& o, long
     a.in_dir = dir;
     r = wf_run(ctx, w, a, stream);
     if (r != GC_OK) return r;
-    hipLaunchKernelGGL(k_wf_trace_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a, out_org,
-                       out_dir, status, steps, events, w.tot);
+    hipLaunchKernelGGL(k_wf_trace_out, dim3((unsigned)std::min((n + 255) / 256, kFoldBlocks)), dim3(256), 0, stream,
+                       a, out_org, out_dir, status, steps, events, w.tot);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(stream));
     return GC_OK;
@@ -1117,7 +1134,8 @@ static gc_status render_impl(gc_ctx* ctx, const gc_scene* scene, const gc_camera
     long long npx = (long long)c.W * c.H;
     unsigned nb = (unsigned)((npx + 255) / 256);
     if (scene->mirror == 1)
-        hipLaunchKernelGGL(k_render_flat, dim3(nb), dim3(256), 0, stream, c, s.K, d_rgb, ctx->d_cnt);
+        hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npx)), dim3(256), 0, stream, c, s.K, d_rgb,
+                           stats ? ctx->d_cnt : nullptr);
     else if (opts->prec == GC_F64)
         hipLaunchKernelGGL(k_render64, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
     else

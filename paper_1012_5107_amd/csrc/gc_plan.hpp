@@ -21,7 +21,6 @@ struct gc_batch_plan {
     bool corr = false;
     double* d_cc = nullptr;      // 4 doubles per scene: C0, ncc and the two variances
     double* d_part = nullptr;    // partial moments of the correlation
-    DevCounters* d_flatcnt = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -34,7 +33,6 @@ static void plan_free(gc_batch_plan* p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_cc) (void)hipFree(p->d_cc);
     if (p->d_part) (void)hipFree(p->d_part);
-    if (p->d_flatcnt) (void)hipFree(p->d_flatcnt);
     if (p->e0) (void)hipEventDestroy(p->e0);
     if (p->e1) (void)hipEventDestroy(p->e1);
     wf_free(p->w);
@@ -82,7 +80,6 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
     if (hipStreamCreate(&cs) != hipSuccess) return bail(fail(GC_EDEVICE, "hipStreamCreate failed"));
     if (hipMalloc(&p->d_cc, sizeof(double) * 4 * n_scenes) != hipSuccess ||
         hipMalloc(&p->d_part, sizeof(double) * kCCBlocks * 5 * kCCMaxCh) != hipSuccess ||
-        hipMalloc(&p->d_flatcnt, sizeof(DevCounters)) != hipSuccess ||
         hipEventCreate(&p->e0) != hipSuccess || hipEventCreate(&p->e1) != hipSuccess)
         return bail(fail(GC_ENOMEM, "batch plan: allocation failed"));
     if ((r = wf_setup(ctx, p->w, n_scenes, sd.data(), cd.data(), o, d_rgb, cs, &p->a, &p->n_pix)) != GC_OK)
@@ -107,8 +104,8 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
         for (int i = 0; i < n_scenes && p->corr; ++i) {
             const long long npix = (long long)cd[i].W * cd[i].H;
             if (render_refs)
-                hipLaunchKernelGGL(k_render_flat, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, cs, cd[i],
-                                   sd[i].K, d_ref[i], p->d_flatcnt);
+                hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npix)), dim3(256), 0, cs, cd[i],
+                                   sd[i].K, d_ref[i], nullptr);
             long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
             hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, cs, (const float*)d_rgb[i],
                                (const float*)d_ref[i], npix, 3, p->d_part);

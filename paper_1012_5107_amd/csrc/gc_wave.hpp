@@ -6,7 +6,7 @@
 // register footprints, so they are separate kernels that pass rays through
 // queues of ray indices:
 //
-//   k_wf_init    one lane per sample: camera ray (or given ray), flight
+//   k_wf_init    a few samples per lane: camera ray (or given ray), flight
 //                through air to the box, the sky, or a failure; a ray whose
 //                first leg meets the bare grating goes to the air queue;
 //   k_wf_box     persistent FP32 kernel: each wave claims rays from the box
@@ -341,15 +341,71 @@ __device__ __forceinline__ int init_ray(const WfArgs& a, long long q, bool* defe
     return continue_in_air(a, q, s, r, p, cnt);
 }
 
-// One lane per sample: camera (or given) ray, flight to the box.
+// k_wf_init: camera (or given) rays and their flight to the box, kInitRays
+// samples per lane.  Its appends to the three queues (fast box, slow box,
+// air) take one atomic per block and queue: atomics on the queue counters
+// are performed one at a time, and at one per wave they bounded the kernel.
+constexpr int kInitRays = 4;
+
+// Queue k (0 fast box, 1 slow box, 2 air) of the 3-bit code r of a lane:
+// bits 0-1 the box queue + 1 (0: none), bit 2 the air queue.
+__device__ __forceinline__ bool init_in_queue(unsigned codes, int r, int k)
+{
+    const unsigned c = (codes >> (3 * r)) & 7u;
+    return k == 2 ? (c & 4u) != 0 : (c & 3u) == (unsigned)(k + 1);
+}
+
 __global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
 {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int dest = -1;
-    bool deferred = false;
-    if (q < a.n_rays) dest = init_ray(a, q, &deferred);
-    push_box_wave(a, 0, dest, (int)q);
-    push_air_wave(a, deferred, (int)q);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long q0 = (long long)blockIdx.x * (blockDim.x * kInitRays) + threadIdx.x;
+    // the rays q0 + r * blockDim.x, r < kInitRays (coalesced for each r)
+    unsigned codes = 0;
+#pragma unroll 1
+    for (int r = 0; r < kInitRays; ++r) {
+        const long long q = q0 + (long long)r * blockDim.x;
+        if (q >= a.n_rays) continue;
+        bool deferred = false;
+        const int dest = init_ray(a, q, &deferred);
+        codes |= ((unsigned)(dest + 1) | (deferred ? 4u : 0u)) << (3 * r);
+    }
+    // wave counts per queue, block totals in LDS, one atomic per queue
+    unsigned cnt[3] = {0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < kInitRays; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) cnt[k] += (unsigned)__popcll(__ballot(init_in_queue(codes, r, k)));
+    __shared__ unsigned wcnt[4][3], base[3];
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) wcnt[wave][k] = cnt[k];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        unsigned tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wcnt[w][k];
+        unsigned* len = k == 0 ? &a.ctr->box_len[0] : (k == 1 ? &a.ctr->slow_len[0] : &a.ctr->air_len);
+        base[k] = tot ? atomicAdd(len, tot) : 0u;
+    }
+    __syncthreads();
+    unsigned off[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        off[k] = base[k];
+        for (int w = 0; w < wave; ++w) off[k] += wcnt[w][k];
+    }
+    int* const queue[3] = {a.qbox[0], a.qslow[0], a.qair};
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < kInitRays; ++r) {
+        const int q = (int)(q0 + (long long)r * blockDim.x);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const bool in = init_in_queue(codes, r, k);
+            const unsigned long long m = __ballot(in);
+            if (in) queue[k][off[k] + (unsigned)__popcll(m & below)] = q;
+            off[k] += (unsigned)__popcll(m);
+        }
+    }
 }
 
 // In-box event location in FP32: regula falsi with the Illinois
@@ -854,12 +910,16 @@ __device__ __forceinline__ void add_totals(WfTotals* tot, unsigned long long c_r
 
 // Pixel averages (render mode) and counters (totals in WfTotals).
 
+// Blocks of the folding kernels (k_wf_finish, k_wf_trace_out): a bounded
+// grid strides over the pixels or rays, so that the counters take few atomics.
+constexpr long long kFoldBlocks = 2048;
+
 __global__ void __launch_bounds__(256) k_wf_finish(WfArgs a, float* const* images, const long long* pix_off,
                                                    long long n_pix, WfTotals* tot)
 {
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long c_rays = 0, c_steps = 0, c_rej = 0, c_ev = 0, c_fail = 0, c_fb = 0;
-    if (g < n_pix) {
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n_pix;
+         g += (long long)gridDim.x * blockDim.x) {
         int lo = 0, hi = a.n_scenes - 1;
         while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
@@ -893,9 +953,9 @@ __global__ void __launch_bounds__(256) k_wf_finish(WfArgs a, float* const* image
 __global__ void __launch_bounds__(256) k_wf_trace_out(WfArgs a, double* out_org, double* out_dir, int* status,
                                                       long long* steps, int* events, WfTotals* tot)
 {
-    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long c_rays = 0, c_steps = 0, c_rej = 0, c_ev = 0, c_fail = 0, c_fb = 0;
-    if (q < a.n_rays) {
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < a.n_rays;
+         q += (long long)gridDim.x * blockDim.x) {
         if (out_org) { out_org[3 * q] = a.R.rx[q]; out_org[3 * q + 1] = a.R.ry[q]; out_org[3 * q + 2] = a.R.rz[q]; }
         out_dir[3 * q] = a.R.qx[q];
         out_dir[3 * q + 1] = a.R.qy[q];
@@ -903,12 +963,12 @@ __global__ void __launch_bounds__(256) k_wf_trace_out(WfArgs a, double* out_org,
         if (status) status[q] = a.R.status[q];
         if (steps) steps[q] = a.R.steps[q];
         if (events) events[q] = a.R.events[q];
-        c_rays = 1;
-        c_steps = (unsigned)a.R.steps[q];
-        c_rej = (unsigned)a.R.rej[q];
-        c_ev = (unsigned)a.R.events[q];
-        c_fail = a.R.status[q] != RS_OK;
-        c_fb = (unsigned)a.R.fbk[q];
+        c_rays++;
+        c_steps += (unsigned)a.R.steps[q];
+        c_rej += (unsigned)a.R.rej[q];
+        c_ev += (unsigned)a.R.events[q];
+        c_fail += a.R.status[q] != RS_OK;
+        c_fb += (unsigned)a.R.fbk[q];
     }
     add_totals(tot, c_rays, c_steps, c_rej, c_ev, c_fail, c_fb);
 }
