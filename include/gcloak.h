@@ -127,7 +127,7 @@ typedef struct {
     int64_t failed;          /* samples with status != GC_RAY_OK */
     int64_t fp64_steps;      /* FP32 path: accepted steps taken by the FP64 event kernel (rounds) */
     int64_t rounds;          /* FP32 path: in-cloak / event rounds */
-    int64_t tail_rays;       /* FP32 path: rays finished by the tail kernel */
+    int64_t tail_rays;       /* batch plan: rays put at the front of the first round's queue */
     int64_t hot_steps;       /* FP32 path: accepted steps taken by the FP32 in-cloak kernel */
     double hot_ms;           /* FP32 path: device time of the FP32 in-cloak kernel (HIP events) */
     double event_ms;         /* FP32 path: device time of the FP64 event and air kernels */
@@ -186,23 +186,30 @@ void gc_default_tune(gc_tune* tune);
 gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* tune);
 gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* tune);
 
-/* Batched FP32 render as one HIP graph (S7: one launch for many scenes and
- * their correlations).  gc_batch_plan_create renders the workload once
- * eagerly (which fixes the number of pipeline rounds it needs: every ray's
- * path is deterministic), then captures, on a stream of its own: the
- * counters' reset (a kernel, no memset node), the flight of every camera
- * ray to the box, that many rounds of the in-box / FP64 / air kernels, the
- * pixel averages into d_rgb[i], and, when d_ref is non-null, for each
- * scene the flat-mirror reference into d_ref[i] (if render_refs) and the
- * zero-shift correlation C0 (eq. (15)) of d_rgb[i] against d_ref[i].  The
- * plan owns its pipeline buffers (the context's are not touched) and keeps
- * the image pointers and the context's gc_tune of the moment: the images
- * must stay allocated while the plan lives.  Launch replays the graph on a
- * stream (asynchronous); results synchronises that stream and returns
- * C0[n_scenes] and the counters (total_ms from HIP events around the
- * replay; hot_ms, event_ms are 0).  GC_EUNSUPPORTED for prec != GC_F32 or
- * a flat-mirror scene; GC_EDEVICE if the replay left rays unfinished (the
- * workload changed under the plan). */
+/* Batched FP32 render as HIP graphs (S7: one launch sequence for many
+ * scenes and their correlations).  gc_batch_plan_create renders the
+ * workload once eagerly (which fixes the number of pipeline rounds it
+ * needs: every ray's path is deterministic), then captures, on a stream of
+ * its own: the counters' reset (a kernel, no memset node), the flight of
+ * every camera ray to the box, that many rounds of the in-box / FP64 / air
+ * kernels, the pixel averages into d_rgb[i], and, when d_ref is non-null,
+ * for each scene the flat-mirror reference into d_ref[i] (if render_refs)
+ * and the zero-shift correlation C0 (eq. (15)) of d_rgb[i] against
+ * d_ref[i]; 1 + 2 x rounds graphs, each round's in-box kernel in a graph of
+ * its own.  The plan owns its pipeline buffers (the context's are not
+ * touched) and keeps the image pointers and the context's gc_tune of the
+ * moment: the images must stay allocated while the plan lives.  The eager
+ * run also records the longest first visits of the box (at least 1000
+ * steps; the 4096 longest): the replays put those rays at the front of the
+ * first round's queue, so that they start when the launch does (scheduling
+ * only: every result is the same).  Launch enqueues the graphs back to back
+ * on a stream (asynchronous); results synchronises that stream and returns
+ * C0[n_scenes] and the counters of the last replay (total_ms from HIP
+ * events around it, hot_ms from events between the graph launches around
+ * each in-box kernel, event_ms 0; tail_rays = the number of those front
+ * rays).  GC_EUNSUPPORTED for prec != GC_F32 or a flat-mirror scene;
+ * GC_EDEVICE if the replay left rays unfinished (the workload changed under
+ * the plan). */
 typedef struct gc_batch_plan gc_batch_plan;
 gc_status gc_batch_plan_create(gc_ctx* ctx, int32_t n_scenes, const gc_scene* scenes, const gc_camera* cameras,
                                const gc_opts* opts, float* const* d_rgb, float* const* d_ref, int32_t render_refs,

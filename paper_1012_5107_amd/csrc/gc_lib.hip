@@ -769,33 +769,46 @@ static unsigned wf_air_blocks(const gc_ctx* ctx, const WfArgs& a)
 // walk in the air kernel.  Enqueues kernels only, so that a graph can hold it.
 static void wf_start(const gc_ctx* ctx, WfStore& w, const WfArgs& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, stream, w.ctr, w.tot);
+    hipLaunchKernelGGL(k_wf_zero, dim3(1), dim3(64), 0, stream, w.ctr, w.tot, a.qbox[0], a.n_front);
     hipLaunchKernelGGL(k_wf_init, dim3((unsigned)((a.n_rays + 256 * kInitRays - 1) / (256 * kInitRays))), dim3(256), 0,
                        stream, a);
     hipLaunchKernelGGL(k_wf_air, dim3(wf_air_blocks(ctx, a)), dim3(256), 0, stream, a, 0);
 }
 
-// One round: the in-box kernel takes every ray of the round's queues
-// through its visit (or to a step that needs FP64), the FP64 kernel takes
-// those steps, the air kernel walks the rays that left.  With timing, HIP
-// events bracket the in-box kernel (ev[1], ev[2]) and the other two (ev[3]).
-// Enqueues kernels only, so that a graph can hold it.
-static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, unsigned box_g, unsigned air_g,
-                          bool timing, hipStream_t stream)
+// The parts of a round: the in-box kernel takes every ray of the round's
+// queues through its visit (or to a step that needs FP64); then the FP64
+// kernel takes those steps and the air kernel walks the rays that left.
+// Enqueue kernels only, so that a graph can hold them; a batch plan
+// captures them as separate graphs, so that events between its graph
+// launches time the in-box kernel.
+static void wf_round_box(const WfArgs& a, int cur, unsigned box_g, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
-    if (timing) HIP_OK(hipEventRecord(w.ev[1], stream));
     if (a.o.integ == 0)
         hipLaunchKernelGGL(k_wf_box<0>, dim3(box_g), dim3(256), 0, stream, a, cur);
     else
         hipLaunchKernelGGL(k_wf_box<1>, dim3(box_g), dim3(256), 0, stream, a, cur);
-    if (timing) HIP_OK(hipEventRecord(w.ev[2], stream));
+}
+
+static void wf_round_post(const gc_ctx* ctx, const WfArgs& a, int cur, unsigned air_g, hipStream_t stream)
+{
     if (a.o.integ == 0)
         hipLaunchKernelGGL(k_wf_event<0>, dim3(air_g), dim3(256), 0, stream, a, cur);
     else
         hipLaunchKernelGGL(k_wf_event<1>, dim3(air_g), dim3(256), 0, stream, a, cur);
     hipLaunchKernelGGL(k_wf_air, dim3(wf_air_blocks(ctx, a)), dim3(256), 0, stream, a, cur ^ 1);
-    if (timing) HIP_OK(hipEventRecord(w.ev[3], stream));
+}
+
+// One round: its counters' reset and both parts.  With events, ev[0] and
+// ev[1] bracket the in-box kernel and ev[2] follows the other two.
+static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, unsigned box_g, unsigned air_g,
+                          const hipEvent_t* ev, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, stream, w.ctr, cur);
+    if (ev) HIP_OK(hipEventRecord(ev[0], stream));
+    wf_round_box(a, cur, box_g, stream);
+    if (ev) HIP_OK(hipEventRecord(ev[1], stream));
+    wf_round_post(ctx, a, cur, air_g, stream);
+    if (ev) HIP_OK(hipEventRecord(ev[2], stream));
     HIP_OK(hipGetLastError());
     return GC_OK;
 }
@@ -822,7 +835,7 @@ static gc_status wf_run(gc_ctx* ctx, WfStore& w, WfArgs& a, hipStream_t stream)
         const unsigned need = (len + 255) / 256;
         const unsigned box_g = std::min<unsigned>(need, box_max);
         const unsigned air_g = std::min<unsigned>(need, (unsigned)(8 * ctx->n_cu));
-        gc_status r = wf_round(ctx, w, a, cur, box_g, air_g, true, stream);
+        gc_status r = wf_round(ctx, w, a, cur, box_g, air_g, &w.ev[1], stream);
         if (r != GC_OK) return r;
         HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));

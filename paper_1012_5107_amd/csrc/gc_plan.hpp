@@ -1,15 +1,30 @@
-// gc_plan.hpp -- batched FP32 render as one HIP graph (included at the end
-// of gc_lib.hip).
+// gc_plan.hpp -- batched FP32 render as HIP graphs (included at the end of
+// gc_lib.hip).
 //
 // The pipeline's rounds read their queue lengths from device memory and
 // return at once when a queue is empty, so a fixed number of rounds can be
 // enqueued without reading anything back.  The number of rounds a workload
 // needs is a property of its rays (every ray's path is deterministic), so
-// it is measured by one eager run when the plan is made; the graph then
-// holds: zeroing of the counters, the camera rays' flight to the box, that
-// many rounds, the pixel averages, optionally the flat-mirror references,
-// and the zero-shift correlation of every scene (eq. (15)).
+// it is measured by one eager run when the plan is made; graphs launched
+// back to back then hold: zeroing of the counters, the camera rays' flight
+// to the box, that many rounds, the pixel averages, optionally the
+// flat-mirror references, and the zero-shift correlation of every scene
+// (eq. (15)).  Each round's in-box kernel is a graph of its own, so that
+// events recorded between the launches time it.
+//
+// The same eager run records the longest first visits of the box (a visit
+// cannot be split, so one that starts late ends the launch late: in a
+// high-Ak scene a ray guided along z near the crests can take 1e5 steps).
+// The replays' k_wf_init puts those rays at the front of round 0's queue, so
+// that they are claimed when the launch starts, with raised priority.  What
+// each ray computes does not depend on when it is claimed.
 #pragma once
+
+// recorded first visits: at least kRecMin steps, at most kRecCap of them;
+// the kFrontMax longest go to the front of the queue
+constexpr int kRecMin = 1000;
+constexpr unsigned kRecCap = 65536;
+constexpr int kFrontMax = 4096;
 
 struct gc_batch_plan {
     gc_ctx* ctx = nullptr;
@@ -21,22 +36,74 @@ struct gc_batch_plan {
     bool corr = false;
     double* d_cc = nullptr;      // 4 doubles per scene: C0, ncc and the two variances
     double* d_part = nullptr;    // partial moments of the correlation
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    int* d_rec = nullptr;        // (ray, steps) pairs of the eager run's long first visits
+    int* d_front = nullptr;      // the front rays (ascending) and their slots
+    unsigned* d_front_bits = nullptr;
+    int n_front = 0;
+    // the graphs, in launch order: start of the pipeline; per round, the
+    // in-box kernel and the rest of the round (after the last round: pixel
+    // means, references, correlations)
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
+    std::vector<hipEvent_t> ev_round;   // per round: before and after its in-box graph
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 
 static void plan_free(gc_batch_plan* p)
 {
     if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (hipGraphExec_t x : p->execs) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : p->graphs) (void)hipGraphDestroy(g);
     if (p->d_cc) (void)hipFree(p->d_cc);
     if (p->d_part) (void)hipFree(p->d_part);
+    if (p->d_rec) (void)hipFree(p->d_rec);
+    if (p->d_front) (void)hipFree(p->d_front);
+    if (p->d_front_bits) (void)hipFree(p->d_front_bits);
+    for (hipEvent_t e : p->ev_round) (void)hipEventDestroy(e);
     if (p->e0) (void)hipEventDestroy(p->e0);
     if (p->e1) (void)hipEventDestroy(p->e1);
     wf_free(p->w);
     delete p;
+}
+
+// The kFrontMax longest of the n_rec recorded first visits, in the order
+// of their lengths, become the front of round 0's fast queue (p->a.front_*).
+static gc_status plan_front(gc_batch_plan* p, unsigned n_rec)
+{
+    if (n_rec == 0) return GC_OK;
+    std::vector<int> rec(2 * (size_t)n_rec);
+    HIP_OK(hipMemcpy(rec.data(), p->d_rec, sizeof(int) * rec.size(), hipMemcpyDeviceToHost));
+    std::vector<unsigned> order(n_rec);
+    for (unsigned i = 0; i < n_rec; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](unsigned x, unsigned y) {
+        return rec[2 * x + 1] != rec[2 * y + 1] ? rec[2 * x + 1] > rec[2 * y + 1] : rec[2 * x] < rec[2 * y];
+    });
+    const int k = (int)std::min<unsigned>(n_rec, (unsigned)kFrontMax);
+    std::vector<std::pair<int, int>> fr((size_t)k);   // (ray, slot)
+    for (int i = 0; i < k; ++i) fr[i] = {rec[2 * order[i]], i};
+    std::sort(fr.begin(), fr.end());
+    const long long n_rays = p->a.n_rays;
+    std::vector<unsigned> bits((size_t)((n_rays + 31) / 32), 0u);
+    std::vector<int> host(2 * (size_t)k);
+    for (int i = 0; i < k; ++i) {
+        const int q = fr[i].first;
+        if (q < 0 || q >= n_rays || (i > 0 && q == fr[i - 1].first))
+            return fail(GC_EDEVICE, "batch plan: inconsistent record of long visits");
+        host[i] = q;
+        host[k + i] = fr[i].second;
+        bits[(size_t)q >> 5] |= 1u << (q & 31);
+    }
+    if (hipMalloc(&p->d_front, sizeof(int) * host.size()) != hipSuccess ||
+        hipMalloc(&p->d_front_bits, sizeof(unsigned) * bits.size()) != hipSuccess)
+        return fail(GC_ENOMEM, "batch plan: allocation failed");
+    HIP_OK(hipMemcpy(p->d_front, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->d_front_bits, bits.data(), sizeof(unsigned) * bits.size(), hipMemcpyHostToDevice));
+    p->n_front = k;
+    p->a.front_bits = p->d_front_bits;
+    p->a.front_q = p->d_front;
+    p->a.front_slot = p->d_front + k;
+    p->a.n_front = k;
+    return GC_OK;
 }
 
 extern "C" {
@@ -84,43 +151,68 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
         return bail(fail(GC_ENOMEM, "batch plan: allocation failed"));
     if ((r = wf_setup(ctx, p->w, n_scenes, sd.data(), cd.data(), o, d_rgb, cs, &p->a, &p->n_pix)) != GC_OK)
         return bail(r);
-    // one eager run: the number of rounds this workload needs
+    // one eager run: the number of rounds this workload needs, and its long
+    // first visits
+    if (hipMalloc(&p->d_rec, sizeof(int) * 2 * kRecCap) != hipSuccess)
+        return bail(fail(GC_ENOMEM, "batch plan: allocation failed"));
+    p->a.rec = p->d_rec;
+    p->a.rec_cap = kRecCap;
+    p->a.rec_min = kRecMin;
     if ((r = wf_run(ctx, p->w, p->a, cs)) != GC_OK) return bail(r);
     if (hipStreamSynchronize(cs) != hipSuccess) return bail(fail(GC_EDEVICE, "eager run failed"));
     p->rounds = (int)p->w.rounds;
+    p->a.rec = nullptr;
+    if ((r = plan_front(p, std::min<unsigned>(p->w.h_ctr->rec_len, kRecCap))) != GC_OK) return bail(r);
 
-    // capture
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return bail(fail(GC_EDEVICE, "hipStreamBeginCapture failed"));
-    gc_status cr = GC_OK;
-    do {
-        wf_start(ctx, p->w, p->a, cs);
-        const unsigned box_g = wf_box_max(ctx, p->w, o.integ);
-        const unsigned air_g = (unsigned)(8 * ctx->n_cu);
-        for (int round = 0; round < p->rounds && cr == GC_OK; ++round)
-            cr = wf_round(ctx, p->w, p->a, round & 1, box_g, air_g, false, cs);
-        if (cr != GC_OK) break;
-        if ((cr = wf_finish(p->w, p->a, n_scenes, p->n_pix, cs)) != GC_OK) break;
-        for (int i = 0; i < n_scenes && p->corr; ++i) {
-            const long long npix = (long long)cd[i].W * cd[i].H;
-            if (render_refs)
-                hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npix)), dim3(256), 0, cs, cd[i],
-                                   sd[i].K, d_ref[i], nullptr);
-            long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
-            hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, cs, (const float*)d_rgb[i],
-                               (const float*)d_ref[i], npix, 3, p->d_part);
-            hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, cs, (const double*)p->d_part, (int)nb, npix, 3,
-                               p->d_cc + 4 * i);
+    // events between the graph launches: the in-box kernel's device time
+    p->ev_round.assign(2 * (size_t)p->rounds, nullptr);
+    for (hipEvent_t& e : p->ev_round)
+        if (hipEventCreate(&e) != hipSuccess) return bail(fail(GC_EDEVICE, "hipEventCreate failed"));
+
+    // capture: 1 + 2 rounds graphs
+    const unsigned box_g = wf_box_max(ctx, p->w, o.integ);
+    const unsigned air_g = (unsigned)(8 * ctx->n_cu);
+    for (int piece = 0; piece <= 2 * p->rounds; ++piece) {
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bail(fail(GC_EDEVICE, "hipStreamBeginCapture failed"));
+        gc_status cr = GC_OK;
+        const int round = (piece - 1) / 2;   // piece 0: round 0's counters follow the start
+        if (piece == 0) {
+            wf_start(ctx, p->w, p->a, cs);
+        } else if (piece % 2 == 1) {
+            wf_round_box(p->a, round & 1, box_g, cs);
+        } else {
+            wf_round_post(ctx, p->a, round & 1, air_g, cs);
         }
-        if (hipGetLastError() != hipSuccess) cr = fail(GC_EDEVICE, "kernel launch failed during capture");
-    } while (false);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(cs, &g);
-    p->graph = g;
-    if (cr != GC_OK) return bail(cr);
-    if (ec != hipSuccess || !g) return bail(fail(GC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec)));
-    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
-        return bail(fail(GC_EDEVICE, "hipGraphInstantiate failed"));
+        // the next round's counters, or the end of the render
+        if (piece % 2 == 0 && round + (piece > 0) < p->rounds) {
+            hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, cs, p->w.ctr, (round + (piece > 0)) & 1);
+        } else if (piece == 2 * p->rounds) {
+            cr = wf_finish(p->w, p->a, n_scenes, p->n_pix, cs);
+            for (int i = 0; i < n_scenes && p->corr; ++i) {
+                const long long npix = (long long)cd[i].W * cd[i].H;
+                if (render_refs)
+                    hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npix)), dim3(256), 0, cs, cd[i],
+                                       sd[i].K, d_ref[i], nullptr);
+                long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
+                hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, cs, (const float*)d_rgb[i],
+                                   (const float*)d_ref[i], npix, 3, p->d_part);
+                hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, cs, (const double*)p->d_part, (int)nb, npix,
+                                   3, p->d_cc + 4 * i);
+            }
+        }
+        const bool launch_ok = hipGetLastError() == hipSuccess;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &g);
+        if (g) p->graphs.push_back(g);
+        if (cr != GC_OK) return bail(cr);
+        if (!launch_ok) return bail(fail(GC_EDEVICE, "kernel launch failed during capture"));
+        if (ec != hipSuccess || !g) return bail(fail(GC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec)));
+        hipGraphExec_t x = nullptr;
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x)
+            return bail(fail(GC_EDEVICE, "hipGraphInstantiate failed"));
+        p->execs.push_back(x);
+    }
     (void)hipStreamDestroy(cs);
     *out = p;
     return GC_OK;
@@ -138,7 +230,13 @@ static gc_status batch_plan_launch_impl(gc_batch_plan* p, hipStream_t stream)
     if (!p) return fail(GC_EINVAL, "plan is null");
     HIP_OK(hipSetDevice(p->ctx->device));
     HIP_OK(hipEventRecord(p->e0, stream));
-    HIP_OK(hipGraphLaunch(p->exec, stream));
+    HIP_OK(hipGraphLaunch(p->execs[0], stream));
+    for (int k = 0; k < p->rounds; ++k) {
+        HIP_OK(hipEventRecord(p->ev_round[2 * k], stream));
+        HIP_OK(hipGraphLaunch(p->execs[1 + 2 * k], stream));
+        HIP_OK(hipEventRecord(p->ev_round[2 * k + 1], stream));
+        HIP_OK(hipGraphLaunch(p->execs[2 + 2 * k], stream));
+    }
     HIP_OK(hipEventRecord(p->e1, stream));
     return GC_OK;
 }
@@ -173,9 +271,12 @@ static gc_status batch_plan_results_impl(gc_batch_plan* p, double* C0, gc_stats*
         st->fallbacks = (int64_t)tot.fallbacks;
         st->failed = (int64_t)tot.failed;
         st->rounds = p->rounds;
+        st->tail_rays = p->n_front;
         st->hot_steps = (int64_t)ctr.hot_steps;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p->e0, p->e1) == hipSuccess) st->total_ms = ms;
+        for (int k = 0; k < p->rounds; ++k)
+            if (hipEventElapsedTime(&ms, p->ev_round[2 * k], p->ev_round[2 * k + 1]) == hipSuccess) st->hot_ms += ms;
     }
     for (int i = 0; i < p->ns && p->corr; ++i) {
         if (!(cc[4 * i + 2] > 0)) return fail(GC_EINVAL, "reference image %d is constant: eq. (15) is undefined", i);

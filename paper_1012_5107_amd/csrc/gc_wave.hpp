@@ -49,6 +49,7 @@ struct QCtr {
     unsigned ev_len;
     unsigned ev_head;
     unsigned air_len;               // rays whose walk through air needs the contact search
+    unsigned rec_len;               // long first visits recorded (see WfArgs::rec)
     unsigned long long hot_steps;   // accepted steps taken by k_wf_box (all rounds)
 };
 
@@ -62,7 +63,9 @@ struct WfRays {
     float* rgb;   // 3 per ray
 };
 
-enum WfFlag { WF_LAST_REJ = 1 };
+// WF_FIRST_VISIT: the ray entered the box from k_wf_init (its first visit,
+// in round 0's queues) and has not been handed to the FP64 kernel since
+enum WfFlag { WF_LAST_REJ = 1, WF_FIRST_VISIT = 2 };
 
 // Scheduling of the in-box kernel (what is computed does not depend on it).
 struct WfSched {
@@ -88,6 +91,21 @@ struct WfArgs {
     // trace_rays mode: explicit rays in, exit rays out
     const double* in_org;
     const double* in_dir;
+    // Rays that k_wf_init puts at the front of round 0's fast box queue (so
+    // that they are claimed first): a bitmap over the rays, their indices in
+    // ascending order and the slot of each (n_front slots, filled with -1 by
+    // k_wf_zero).  A batch plan sets them from its eager run: the visits that
+    // took longest there, which would otherwise start wherever the queue
+    // order puts them and end the launch late.
+    const unsigned* front_bits;
+    const int* front_q;
+    const int* front_slot;
+    int n_front;
+    // Recording (null: off): k_wf_box appends (ray, steps) for every first
+    // visit of at least rec_min steps, up to rec_cap pairs.
+    int* rec;
+    unsigned rec_cap;
+    int rec_min;
 };
 
 __device__ __forceinline__ int scene_of(const WfArgs& a, long long q)
@@ -281,12 +299,26 @@ __device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, con
 // ---------------------------------------------------------------------------
 // Counters to zero at the start of a launch (a kernel, not a memset, so
 // that a captured graph holds no memset node).
-__global__ void __launch_bounds__(64) k_wf_zero(QCtr* c, WfTotals* t)
+__global__ void __launch_bounds__(64) k_wf_zero(QCtr* c, WfTotals* t, int* qfront, int n_front)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *c = QCtr{};
         *t = WfTotals{};
+        c->box_len[0] = (unsigned)n_front;   // the reserved front of round 0's fast queue
     }
+    for (int i = threadIdx.x; i < n_front; i += blockDim.x) qfront[i] = -1;
+}
+
+// Slot of ray q at the front of round 0's fast queue, or -1.
+__device__ __forceinline__ int front_slot_of(const WfArgs& a, long long q)
+{
+    if (!((a.front_bits[q >> 5] >> (q & 31)) & 1u)) return -1;
+    int lo = 0, hi = a.n_front - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.front_q[mid] < q) lo = mid + 1; else hi = mid;
+    }
+    return a.front_q[lo] == q ? a.front_slot[lo] : -1;
 }
 
 __global__ void __launch_bounds__(256) k_wf_reset(QCtr* c, int cur)
@@ -366,7 +398,15 @@ __global__ void __launch_bounds__(256) k_wf_init(WfArgs a)
         const long long q = q0 + (long long)r * blockDim.x;
         if (q >= a.n_rays) continue;
         bool deferred = false;
-        const int dest = init_ray(a, q, &deferred);
+        int dest = init_ray(a, q, &deferred);
+        if (dest >= 0) {
+            a.R.flags[q] |= WF_FIRST_VISIT;
+            const int slot = a.n_front > 0 ? front_slot_of(a, q) : -1;
+            if (slot >= 0) {
+                a.qbox[0][slot] = (int)q;
+                dest = -1;
+            }
+        }
         codes |= ((unsigned)(dest + 1) | (deferred ? 4u : 0u)) << (3 * r);
     }
     // wave counts per queue, block totals in LDS, one atomic per queue
@@ -449,6 +489,7 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
     int src = (a.sch.slow_div > 0 && wave % a.sch.slow_div == 0) ? 1 : 0;
     if (src == 1 ? ex1 : ex0) src ^= 1;
     bool slow_ray = false, prio = false;
+    bool rec0 = false;      // the lane's visit is the ray's first (recording)
     int q = 0;
     const SceneDev* sp = a.scenes;
     double s_hw = 0.0, s_L = 1.0;   // the lane's scene: half-width and period, kept in registers
@@ -485,6 +526,10 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                     R.rej[q] = rej;
                     R.events[q] = nev;
                     R.fbk[q] = fbk;
+                    if (rec0 && a.rec && steps >= a.rec_min) {
+                        const unsigned k = atomicAdd(&a.ctr->rec_len, 1u);
+                        if (k < a.rec_cap) { a.rec[2 * k] = q; a.rec[2 * k + 1] = steps; }
+                    }
                     if (pend >= 16) {
                         const double zero[3] = {0.0, 0.0, 0.0};
                         finish_ray(a, q, *sp, pend - 16, r, zero);
@@ -534,9 +579,13 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                 if (!active) {
                     unsigned rank = __popcll(idle & ((1ull << lane) - 1ull));
                     unsigned qi = base + rank;
-                    if (qi < qlen) {
-                        q = queue[qi];
-                        slow_ray = from != 0;
+                    // (a reserved front slot holds -1 if its ray did not come)
+                    const int qn = qi < qlen ? queue[qi] : -1;
+                    if (qn >= 0) {
+                        q = qn;
+                        // the rays at the front of round 0's fast queue run
+                        // with raised priority, as the slow queue's do
+                        slow_ray = from != 0 || (cur == 0 && qi < (unsigned)a.n_front);
                         const WfRays& R = a.R;
                         sp = a.scenes + R.scene[q];
                         const SceneDev& s = *sp;
@@ -559,7 +608,9 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                         rej = R.rej[q];
                         nev = R.events[q];
                         fbk = R.fbk[q];
-                        last_rej = (R.flags[q] & WF_LAST_REJ) != 0;
+                        const int fl = R.flags[q];
+                        last_rej = (fl & WF_LAST_REJ) != 0;
+                        rec0 = (fl & WF_FIRST_VISIT) != 0;
                         xhi = (float)(s.hw - (double)u.cell * s.L);
                         xlo = (float)(-s.hw - (double)u.cell * s.L);
                         r1.W = {R.Wr[q], R.Wi[q]};

@@ -1,4 +1,4 @@
-"""The batched FP32 render captured as one HIP graph (gc_batch_plan): every
+"""The batched FP32 render captured as HIP graphs (gc_batch_plan): every
 replay must reproduce the eager batch render bit for bit (images, flat
 references, C0 and counters), also with other work and synchronisations
 between the replays."""
@@ -66,5 +66,41 @@ def test_plan_replays_match_eager_batch(B):
             plan.close()
         with pytest.raises(B.GcError):   # flat-mirror scenes are not batched
             ctx.batch_plan([W.reference_scene(scenes[0])], cams[:1], op, outs[:1])
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("tune", [dict(slow_pxy=0.0, slow_wave_div=0), dict(slow_pxy=0.3, slow_wave_div=4)])
+def test_plan_front_of_queue_replays_match_eager(B, tune):
+    """The plan's eager run records the longest first visits of the box and
+    its graph claims those rays first (the front of the first round's
+    queue); every replay still reproduces the eager render bit for bit."""
+    sc, cam, _, op = W.plain_vs_fp32_512()
+    cam = dict(cam, width=192, height=192, spp=2)
+    ctx = B.Context(0)
+    try:
+        ctx.tune(**tune)
+        ref_e = ctx.render(W.reference_scene(sc), cam, op, prec="f32")[0]
+        imgs_e, c0_e, st_e = ctx.render_batch([sc], [cam], op, refs=[ref_e])
+        out = torch.full_like(imgs_e[0], float("nan"))
+        ref = torch.full_like(ref_e, float("nan"))
+        plan = ctx.batch_plan([sc], [cam], op, [out], refs=[ref], render_refs=True)
+        try:
+            for rep in range(3):
+                out.fill_(float("nan"))
+                ref.fill_(float("nan"))
+                torch.cuda.synchronize()
+                plan.launch()
+                c0, st = plan.results()
+                assert st["tail_rays"] > 0, "no long first visit was put at the front"
+                assert torch.equal(out, imgs_e[0]), rep
+                assert torch.equal(ref, ref_e), rep
+                assert c0 == c0_e, rep
+                for k in ("rays", "accepted_steps", "rejected_steps", "events", "failed", "fallbacks"):
+                    assert st[k] == st_e[k], (rep, k)
+                ctx.render(sc, dict(cam, width=32, height=32, spp=1), op, prec="f32")
+                torch.cuda.synchronize()
+        finally:
+            plan.close()
     finally:
         ctx.close()
