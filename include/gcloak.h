@@ -368,7 +368,10 @@ typedef enum {
  * the forward counters (rays, accepted_steps, events, failed; tail_rays =
  * samples differentiated again in FP64 with tapes long enough for any
  * trace the options allow -- tapes longer than 256 records, and in FP32 the
- * long or sensitive traces; rounds = those of more than 8000 steps, which
+ * long or sensitive traces; the first pass stops a trace once its tape has
+ * overflowed or, in FP32, once it has passed 20000 steps, and the counters
+ * of such a sample come from the FP64 pass; rounds = the hand-overs of more
+ * than 8000 steps, which
  * start first; hot_steps = steps reversed by the first pass;
  * hot_ms / tail_ms / total_ms the device time of the first pass, of the
  * FP64 passes and of the call).  Device scratch

@@ -535,12 +535,17 @@ __device__ inline void sky_vjp(double K, const double d[3], double lm, double lp
 }
 
 // ---------------------------------------------------------------------------
-// Forward trace with tape (the maps of trace_ray64, RK4 only).
+// Forward trace with tape (the maps of trace_ray64, RK4 only).  With `stop`
+// (a first pass, which hands such samples to the second), the trace ends
+// with kAdjStopped as soon as its tape has overflowed or it has taken more
+// than stop_steps steps: the second pass redoes it from the start.
 // ---------------------------------------------------------------------------
+constexpr int kAdjStopped = 16;   // not a ray status
+
 template <typename T>
 __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T wfb2, int C, const double org[3],
                                         const double dir[3], const AdjTape& tp, int& nrec, double out_dir[3],
-                                        long long& steps, int& events)
+                                        long long& steps, int& events, bool stop, long long stop_steps)
 {
     double r[3] = {org[0], org[1], org[2]};
     const double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
@@ -593,6 +598,7 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
                  pz, AK_RUN);
         long long run = 0;
         for (;;) {
+            if (stop && (nrec > tp.cap || steps > stop_steps)) return kAdjStopped;
             if (steps >= o.max_steps) return RS_MAX_STEPS;
             if (run > 0 && run % C == 0)
                 tape_put(tp, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re,
@@ -829,11 +835,12 @@ struct AdjIo {
     long long ovf_cap;            // entries of ovf
     unsigned long long* n_ovf;    // first pass: hand-overs at the front / back of ovf; second: overflows
     long long long_steps;         // hand-overs of more steps go to the front
-    unsigned long long* cnt;      // rays, steps, events, failed, inconsistent tapes, steps reversed (first pass)
+    unsigned long long* cnt;      // rays (first pass); steps, events, failed (the pass that traces the sample to
+                                  // its end); inconsistent tapes; steps reversed (first pass)
     // first FP32 pass: samples whose gradient is recomputed in FP64 -- paths
-    // longer than rerun_steps, or whose sky parameter m is more sensitive to
-    // the initial direction than rerun_sens per radian (FP32 rounding would
-    // be amplified)
+    // longer than rerun_steps (their trace stops there), or whose sky
+    // parameter m is more sensitive to the initial direction than rerun_sens
+    // per radian (FP32 rounding would be amplified)
     long long rerun_steps;
     double rerun_sens;
 };
@@ -863,7 +870,11 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         if (base >= (unsigned long long)io.n) break;
         const unsigned long long q = base + (unsigned long long)wl;
         if (q >= (unsigned long long)io.n) continue;
-        const long long sidx = io.list ? io.list[q] : (long long)q;
+        // a second pass's entry ~sidx: a sample the first pass stopped early,
+        // whose counters are taken here
+        const long long raw = io.list ? io.list[q] : (long long)q;
+        const bool redo = raw < 0;
+        const long long sidx = redo ? ~raw : raw;
         const long long pix = sidx / cam.spp;
         const int smp = (int)(sidx - pix * cam.spp);
         const int pi = (int)(pix % cam.W), pj = (int)(pix / cam.W);
@@ -871,22 +882,25 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         camera_dir(cam, pi, pj, smp, d);
         int nrec = 0, events = 0;
         long long steps = 0;
-        const int st = adj_forward<T>(s, o, wfb2, C, cam.eye, d, tp, nrec, od, steps, events);
+        const int st = adj_forward<T>(s, o, wfb2, C, cam.eye, d, tp, nrec, od, steps, events, io.ovf != nullptr,
+                                      io.rerun_steps);
+        const bool stopped = st == kAdjStopped;
         {
             // a later (FP64) pass overwrites the colour of the samples it redoes
             double rgb[3] = {0.0, 0.0, 0.0};
             if (st == RS_OK) sky_rgb<double>(s.K, od, rgb);
             for (int c = 0; c < 3; ++c) io.srgb[3 * sidx + c] = (float)rgb[c];
         }
-        if (!io.list) {
-            c_rays++;
+        if (!io.list) c_rays++;
+        if ((!io.list && !stopped) || redo) {
             c_steps += (unsigned long long)steps;
             c_ev += (unsigned long long)events;
             c_fail += (st != RS_OK);
         }
         double gA = 0.0, ghw = 0.0;
+        bool hand_over = stopped;
         if (st == RS_OK) {
-            bool hand_over = nrec > io.cap || steps > io.rerun_steps;
+            hand_over = nrec > io.cap || steps > io.rerun_steps;
             if (!hand_over) {
                 int bad = 0;
                 double sens = 0.0;
@@ -898,24 +912,25 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
                 }
                 hand_over = sens > io.rerun_sens;
             }
-            if (hand_over) {
-                // the first pass hands the sample to the second (FP64,
-                // full-length tapes): long traces from the front of the list,
-                // so that they start first, the others from its back; the
-                // second pass only counts a tape overflow (it cannot happen)
-                if (io.ovf) {
-                    if (steps > io.long_steps) {
-                        const unsigned long long k = atomicAdd(io.n_ovf, 1ull);
-                        io.ovf[k] = sidx;
-                    } else {
-                        const unsigned long long k = atomicAdd(io.n_ovf + 1, 1ull);
-                        io.ovf[io.ovf_cap - 1 - (long long)k] = sidx;
-                    }
-                    continue;
+        }
+        if (hand_over) {
+            // the first pass hands the sample to the second (FP64,
+            // full-length tapes): long traces from the front of the list,
+            // so that they start first, the others from its back; the
+            // second pass only counts a tape overflow (it cannot happen)
+            if (io.ovf) {
+                const long long entry = stopped ? ~sidx : sidx;
+                if (steps > io.long_steps) {
+                    const unsigned long long k = atomicAdd(io.n_ovf, 1ull);
+                    io.ovf[k] = entry;
+                } else {
+                    const unsigned long long k = atomicAdd(io.n_ovf + 1, 1ull);
+                    io.ovf[io.ovf_cap - 1 - (long long)k] = entry;
                 }
-                atomicAdd(io.n_ovf, 1ull);
-                gA = ghw = 0.0;
+                continue;
             }
+            atomicAdd(io.n_ovf, 1ull);
+            gA = ghw = 0.0;
         }
         io.sgrad[2 * sidx] = gA;
         io.sgrad[2 * sidx + 1] = ghw;
