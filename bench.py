@@ -51,6 +51,9 @@ TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.04e8, (3e-7, 0.2, "dopri5"): 5.02e8
 # the same for the 64-scene batch, summed over the two pipeline rounds of one
 # render (profiles/k_wf_box_dopri5_batch64.txt); keyed by (rtol, h_max)
 TRAFFIC_K_WF_BOX_BATCH = {(1e-7 / 3, 0.1): 5.83e10, (1e-7, 0.02): 5.61e10}
+# the same for the 1024 x 1024 x 8 stress render, summed over its three
+# rounds (profiles/k_wf_box_dopri5_1024x1024x8_stress.txt); keyed by rtol
+TRAFFIC_K_WF_BOX_STRESS = {(1e-7,): 3.03e9}
 
 
 def _measured(table, key):
@@ -429,8 +432,8 @@ def main_stress(args):
                       "rtol_fp32": op32["rtol"], "rays": st["rays"], "ray_steps": stk["accepted_steps"]},
            "ray_steps_per_s": stk["accepted_steps"] / dt, "cc_fp32": c32,
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                        "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_wf_box<DOPRI5>",
-                        "kernel_ms": stk["hot_ms"], "kernel_steps": stk["hot_steps"]},
+                        "frac": achieved / PEAK_FP32, "traffic": _measured(TRAFFIC_K_WF_BOX_STRESS, (op32["rtol"],)),
+                        "kernel": "k_wf_box<DOPRI5>", "kernel_ms": stk["hot_ms"], "kernel_steps": stk["hot_steps"]},
            "fp32_counters": stk}
     print(json.dumps(out), flush=True)
 
@@ -460,8 +463,10 @@ def main_grad(args):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     st = r["stats"]
-    fwd, rev = st["accepted_steps"], st["hot_steps"]
-    achieved = (fwd * FLOP_PER_STEP["rk4"] + rev * FLOP_PER_REVERSED_STEP) / (st["hot_ms"] * 1e-3)
+    # the first pass's own work: the forward steps it took (the traces it
+    # stops and hands over included) and the steps it reversed
+    fwd, fwd1, rev = st["accepted_steps"], st["first_pass_steps"], st["hot_steps"]
+    achieved = (fwd1 * FLOP_PER_STEP["rk4"] + rev * FLOP_PER_REVERSED_STEP) / (st["hot_ms"] * 1e-3)
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
         "value": fwd / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -474,7 +479,7 @@ def main_grad(args):
         "loss": r["loss"], "dL_dA": r["dA"], "dL_dhw": r["dhw"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_adj<float>",
-                     "kernel_ms": st["hot_ms"], "forward_steps": fwd, "reversed_steps": rev},
+                     "kernel_ms": st["hot_ms"], "forward_steps": fwd1, "reversed_steps": rev},
         "adjoint_breakdown": {"fp32_pass_ms": st["hot_ms"], "fp64_passes_ms": st["tail_ms"],
                               "total_ms": st["total_ms"], "fp64_samples": st["tail_rays"],
                               "long_tape_samples": st["rounds"], "failed": st["failed"]},

@@ -133,6 +133,7 @@ typedef struct {
     double event_ms;         /* FP32 path: device time of the FP64 event and air kernels */
     double tail_ms;          /* FP32 path: device time of the tail kernel */
     double total_ms;         /* FP32 path: device time of the whole call */
+    int64_t first_pass_steps; /* gc_render_grad: forward steps the first pass took (stopped traces included) */
 } gc_stats;
 
 typedef struct gc_ctx gc_ctx;
@@ -373,6 +374,7 @@ typedef enum {
  * of such a sample come from the FP64 pass; rounds = the hand-overs of more
  * than 8000 steps, which
  * start first; hot_steps = steps reversed by the first pass;
+ * first_pass_steps = forward steps the first pass took;
  * hot_ms / tail_ms / total_ms the device time of the first pass, of the
  * FP64 passes and of the call).  Device scratch
  * (tapes of up to 8 GiB) is owned by the context.  Synchronises the

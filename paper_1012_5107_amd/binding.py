@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
                 ("events", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("fp64_steps", ctypes.c_int64), ("rounds", ctypes.c_int64), ("tail_rays", ctypes.c_int64), ("hot_steps", ctypes.c_int64),
                 ("hot_ms", ctypes.c_double), ("event_ms", ctypes.c_double), ("tail_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("first_pass_steps", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))

@@ -836,7 +836,8 @@ struct AdjIo {
     unsigned long long* n_ovf;    // first pass: hand-overs at the front / back of ovf; second: overflows
     long long long_steps;         // hand-overs of more steps go to the front
     unsigned long long* cnt;      // rays (first pass); steps, events, failed (the pass that traces the sample to
-                                  // its end); inconsistent tapes; steps reversed (first pass)
+                                  // its end); inconsistent tapes; steps reversed and forward steps taken (first
+                                  // pass)
     // first FP32 pass: samples whose gradient is recomputed in FP64 -- paths
     // longer than rerun_steps (their trace stops there), or whose sky
     // parameter m is more sensitive to the initial direction than rerun_sens
@@ -862,7 +863,7 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
     const AdjTape tp = {io.tape, stride, lane, io.cap};
     const AdjSeg<T> sg = {(T*)io.seg, stride, lane};
     const int wl = threadIdx.x & 63;
-    unsigned long long c_rays = 0, c_steps = 0, c_ev = 0, c_fail = 0, c_rev = 0;
+    unsigned long long c_rays = 0, c_steps = 0, c_ev = 0, c_fail = 0, c_rev = 0, c_fwd = 0;
     for (;;) {
         unsigned long long base = 0;
         if (wl == 0) base = atomicAdd(io.claim, 64ull);
@@ -891,7 +892,10 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
             if (st == RS_OK) sky_rgb<double>(s.K, od, rgb);
             for (int c = 0; c < 3; ++c) io.srgb[3 * sidx + c] = (float)rgb[c];
         }
-        if (!io.list) c_rays++;
+        if (!io.list) {
+            c_rays++;
+            c_fwd += (unsigned long long)steps;
+        }
         if ((!io.list && !stopped) || redo) {
             c_steps += (unsigned long long)steps;
             c_ev += (unsigned long long)events;
@@ -940,12 +944,14 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
     c_ev = adj_wave_sum(c_ev);
     c_fail = adj_wave_sum(c_fail);
     c_rev = adj_wave_sum(c_rev);
+    c_fwd = adj_wave_sum(c_fwd);
     if (wl == 0) {
         atomicAdd(&io.cnt[0], c_rays);
         atomicAdd(&io.cnt[1], c_steps);
         atomicAdd(&io.cnt[2], c_ev);
         atomicAdd(&io.cnt[3], c_fail);
         atomicAdd(&io.cnt[5], c_rev);
+        atomicAdd(&io.cnt[6], c_fwd);
     }
 }
 

@@ -449,17 +449,13 @@ static gc_status read_counters(gc_ctx* ctx, gc_stats* st, hipStream_t stream)
     DevCounters h;
     HIP_OK(hipMemcpyAsync(&h, ctx->d_cnt, sizeof h, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
+    std::memset(st, 0, sizeof *st);
     st->rays = (int64_t)h.rays;
     st->accepted_steps = (int64_t)h.steps;
     st->rejected_steps = (int64_t)h.rejected;
     st->events = (int64_t)h.events;
     st->fallbacks = (int64_t)h.fallbacks;
     st->failed = (int64_t)h.failed;
-    st->fp64_steps = 0;
-    st->rounds = 0;
-    st->hot_ms = st->event_ms = st->total_ms = st->tail_ms = 0.0;
-    st->tail_rays = 0;
-    st->hot_steps = 0;
     return GC_OK;
 }
 
@@ -471,9 +467,9 @@ constexpr size_t kAdjTapeBudget = (size_t)8 << 30;    // bytes of tape per pass
 constexpr int kAdjMaxC = 256;
 // Counters of the adjoint (unsigned long long, device): claims of the two
 // passes, hand-overs of the first pass (front, back of the list), overflows
-// of the second, then rays, steps, events, failed, inconsistent tapes and
-// steps reversed in the first pass.
-enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_N = 12 };
+// of the second, then rays, steps, events, failed, inconsistent tapes,
+// steps reversed in the first pass and forward steps it took.
+enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_N = 13 };
 // FP32 samples handed to the FP64 second pass: paths of more steps, or
 // colours more sensitive to the initial direction (per unit seed) than this
 constexpr long long kAdjRerunSteps = 20000;
@@ -620,14 +616,14 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
     HIP_OK(hipEventRecord(a.ev[3], stream));
     HIP_OK(hipMemcpyAsync(a.h_ctr, a.ctr, sizeof(unsigned long long) * AC_N, hipMemcpyDeviceToHost, stream));
     AdjCC hc;
-    HIP_OK(hipMemcpyAsync((double*)(a.h_ctr + 12), a.red, sizeof(double) * 2, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync((double*)(a.h_ctr + 16), a.red, sizeof(double) * 2, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipMemcpyAsync(&hc, a.cs, sizeof hc, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     if (a.h_ctr[AC_OVF + 2] != 0)
         return fail(GC_EDEVICE, "adjoint: %llu samples overflowed the full-length tape", a.h_ctr[AC_OVF + 2]);
     if (a.h_ctr[AC_CNT + 4] != 0)
         return fail(GC_EDEVICE, "adjoint: %llu samples with an inconsistent tape", a.h_ctr[AC_CNT + 4]);
-    const double* hd = (const double*)(a.h_ctr + 12);
+    const double* hd = (const double*)(a.h_ctr + 16);
     if (!(hc.sff > 0)) return fail(GC_EINVAL, "reference image is constant: eq. (15) is undefined");
     if (kind == 1 && !(hc.sgg > 0)) return fail(GC_EINVAL, "rendered image is constant: NCC is undefined");
     out[0] = 1.0 - (kind == 0 ? hc.c0 : hc.ncc);
@@ -642,6 +638,7 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
         st->tail_rays = handed;
         st->rounds = n_front;
         st->hot_steps = (int64_t)a.h_ctr[AC_CNT + 5];
+        st->first_pass_steps = (int64_t)a.h_ctr[AC_CNT + 6];
         float ms = 0.0f;
         HIP_OK(hipEventElapsedTime(&ms, a.ev[0], a.ev[1]));
         st->hot_ms = ms;
