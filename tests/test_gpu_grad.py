@@ -145,8 +145,13 @@ def test_grad_checkpoint_interval_does_not_change_result(B):
               f"p99={np.quantile(rel, 0.99):.3e} tail_rays={r['stats']['tail_rays']}", flush=True)
         assert np.quantile(rel, 0.99) <= 1e-12 and rel.max() <= 1e-6, C
         assert r["loss"] == base["loss"]
+        # a trace the first pass stops (its tape overflowed) is counted by the
+        # pass that finishes it: the totals do not depend on which pass that is
+        for k in ("rays", "accepted_steps", "events", "failed"):
+            assert r["stats"][k] == base["stats"][k], (C, k)
         if C == 1:
             assert r["stats"]["tail_rays"] > base["stats"]["tail_rays"]
+            assert r["stats"]["first_pass_steps"] < base["stats"]["first_pass_steps"]
 
 
 def test_grad_halfwidth_zero_when_side_faces_unseen(B):
