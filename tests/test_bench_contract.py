@@ -33,3 +33,19 @@ def test_help_lists_the_workloads():
     assert r.returncode == 0
     for w in ("single", "batch", "stress", "grad"):
         assert w in r.stdout
+
+
+def test_traffic_tables_resolve_the_options_the_benchmark_uses():
+    """The measured HBM bytes per launch are found for the options the
+    autotuner forms by products (3 x 1e-7, 1e-7 / 3), for every workload
+    whose roofline reports them; an unmeasured setting gives None."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX, (3 * 1e-7, 0.5, "dopri5")) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX, (3e-7, 0.5, "rk4")) is None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7 / 3, 0.1)) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.02)) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (1e-7,)) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (3e-7,)) is None
+    for table in (bench.TRAFFIC_K_WF_BOX, bench.TRAFFIC_K_WF_BOX_BATCH, bench.TRAFFIC_K_WF_BOX_STRESS):
+        assert all(isinstance(k, tuple) and v > 0 for k, v in table.items())
