@@ -867,6 +867,69 @@ void gco_cross_correlate_f64(const double* f, const double* g, long npix, int nc
     out[1] = (double)(sfg / sqrtl(sff * sgg));
 }
 
+/* eq. (15) at every shift (Sec. 5): the correlation map C(dx, dy) of the
+   image g against the reference f, both H x W pixels of nch channels
+   (channel fastest) stored with a row pitch of `pitch` pixels, so that a
+   window of a larger image can be passed.  dx is the shift along a row
+   (columns, to the right), dy along a column (rows, downwards: row 0 is the
+   top of the image), in pixels, |dx| <= rx, |dy| <= ry.
+   Eq. (14): each channel's mean over the whole window is subtracted.  The
+   numerator of eq. (15) is the sum over the pixels (j, i) for which both
+   (j, i) and (j + dy, i + dx) lie in the window -- the finite photograph
+   holds nothing outside -- pooled over channels; the denominator is the
+   sum of f'^2 over the whole window.  So C(0, 0) is the zero-shift
+   coefficient, and an image that is f shifted within the frame gives a
+   maximum below 1 at that shift (equal to 1 only for an infinite
+   photograph, as Sec. 5 notes).
+   map: (2 ry + 1) x (2 rx + 1) doubles, row-major, C(dx, dy) at
+   (dy + ry) (2 rx + 1) + (dx + rx).  peak: { maximum of the map, its dx,
+   its dy }, the first maximum in that row-major order on ties.  Direct
+   sums in long double. */
+void gco_cross_correlate_map(const float* f, const float* g, long H, long W, long pitch, int nch,
+                             int rx, int ry, double* map, double peak[3])
+{
+    long double mf[8], mg[8];
+    long double sff = 0;
+    for (int c = 0; c < nch; ++c) {
+        long double a = 0, b = 0;
+        for (long j = 0; j < H; ++j)
+            for (long i = 0; i < W; ++i) {
+                a += f[(j * pitch + i) * nch + c];
+                b += g[(j * pitch + i) * nch + c];
+            }
+        mf[c] = a / (long double)(H * W);
+        mg[c] = b / (long double)(H * W);
+        for (long j = 0; j < H; ++j)
+            for (long i = 0; i < W; ++i) {
+                long double d = f[(j * pitch + i) * nch + c] - mf[c];
+                sff += d * d;
+            }
+    }
+    long nx = 2L * rx + 1;
+    double best = -INFINITY;
+    int bdx = 0, bdy = 0;
+    for (int dy = -ry; dy <= ry; ++dy)
+        for (int dx = -rx; dx <= rx; ++dx) {
+            long double s = 0;
+            for (long j = 0; j < H; ++j) {
+                long jj = j + dy;
+                if (jj < 0 || jj >= H) continue;
+                for (long i = 0; i < W; ++i) {
+                    long ii = i + dx;
+                    if (ii < 0 || ii >= W) continue;
+                    for (int c = 0; c < nch; ++c)
+                        s += (f[(j * pitch + i) * nch + c] - mf[c]) * (g[(jj * pitch + ii) * nch + c] - mg[c]);
+                }
+            }
+            double v = (double)(s / sff);
+            map[(long)(dy + ry) * nx + (dx + rx)] = v;
+            if (v > best) { best = v; bdx = dx; bdy = dy; }
+        }
+    peak[0] = best;
+    peak[1] = bdx;
+    peak[2] = bdy;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Forward-mode derivatives with respect to the parameters (A, half_width)  */
 /* of the discrete RK4 tracer above.  Every map the tracer applies -- RK4   */

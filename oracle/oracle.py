@@ -58,6 +58,9 @@ def lib():
         L.gco_cross_correlate.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                           ctypes.c_long, ctypes.c_int, dp]
         L.gco_cross_correlate_f64.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, dp]
+        L.gco_cross_correlate_map.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                              ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, dp, dp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.gco_accel_jac.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
         L.gco_trace_rays_tan.argtypes = [dp, dp, ctypes.c_long, dp, dp, dp, dp,
@@ -218,6 +221,28 @@ def cross_correlate(f, g):
         gg = np.ascontiguousarray(g, dtype=np.float64)
         lib().gco_cross_correlate_f64(_dp(ff), _dp(gg), npix, nch, _dp(out))
     return float(out[0]), float(out[1])
+
+
+def cross_correlate_map(f, g, rx, ry, cols=None):
+    """eq. (15) at every shift |dx| <= rx, |dy| <= ry of the image g against
+    the reference f (H x W x C float32, or H x W): returns (map, peak, dx,
+    dy) with map[dy + ry, dx + rx] = C(dx, dy) (dx along a row, dy down the
+    rows) and the first maximum in row-major order.  cols = (c0, c1) takes
+    the column window [c0, c1) of both images (passed with their row pitch,
+    not copied)."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    if f.ndim == 2:
+        f, g = f[:, :, None], g[:, :, None]
+    H, Wfull, nch = f.shape
+    c0, c1 = (0, Wfull) if cols is None else cols
+    out = np.zeros((2 * ry + 1, 2 * rx + 1))
+    pk = np.zeros(3)
+    off = c0 * nch
+    fp = ctypes.cast(f.ctypes.data + 4 * off, ctypes.POINTER(ctypes.c_float))
+    gp = ctypes.cast(g.ctypes.data + 4 * off, ctypes.POINTER(ctypes.c_float))
+    lib().gco_cross_correlate_map(fp, gp, H, c1 - c0, Wfull, nch, int(rx), int(ry), _dp(out), _dp(pk))
+    return out, float(pk[0]), int(pk[1]), int(pk[2])
 
 
 # --- derivatives with respect to the scene parameters (A, half_width) --------
