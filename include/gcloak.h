@@ -396,6 +396,33 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
                              int64_t npix, int32_t nch, double* C0, double* ncc,
                              hipStream_t stream);
 
+/* Correlation map: eq. (15) at every shift (Sec. 5), the "more generous"
+ * measure of cloaking quality whose peak value and location also quantify
+ * an image displacement.  d_img (g) and d_ref (f) are device windows of
+ * height x width pixels, nch float32 channels each (channel fastest), whose
+ * rows lie `pitch` pixels apart (pitch = width for a whole image; a column
+ * window of a W-wide image is base + col0 * nch with pitch W).
+ *   - eq. (14): each channel's mean over the window is subtracted;
+ *   - C(dx, dy) = sum f'(j, i) g'(j + dy, i + dx) / sum f'^2, the
+ *     numerator over the pixels whose shifted partner lies in the window (the
+ *     photograph holds nothing outside it), pooled over channels; the
+ *     denominator over the whole window.  dx is the shift along a row
+ *     (columns, to the right), dy down the rows (row 0 at the top), in pixels;
+ *     C(0, 0) is the zero-shift coefficient of gc_cross_correlate.
+ * d_map (device, (2 ry + 1) x (2 rx + 1) doubles, caller-owned) receives
+ * C(dx, dy) at (dy + ry) (2 rx + 1) + (dx + rx).  peak / peak_dx / peak_dy
+ * (host, each may be null) receive the maximum of the map and its shift, the
+ * first maximum in that row-major order on ties.  Sums in FP64.
+ * Synchronises the stream.  GC_EINVAL for null pointers, height or width < 1,
+ * pitch < width, nch outside 1..4, rx outside [0, width), ry outside
+ * [0, height), or a constant reference window; GC_EUNSUPPORTED for
+ * 2 rx + 1 > 1024 or (2 width + 2 rx) nch > 8192 (two rows of the window
+ * are staged in 64 KiB of LDS).  Scratch (partial sums) is owned by the
+ * context and grown on demand. */
+gc_status gc_cross_correlate_map(gc_ctx* ctx, const float* d_img, const float* d_ref, int32_t height, int32_t width,
+                                 int64_t pitch, int32_t nch, int32_t rx, int32_t ry, double* d_map, double* peak,
+                                 int32_t* peak_dx, int32_t* peak_dy, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

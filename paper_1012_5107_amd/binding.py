@@ -102,7 +102,7 @@ class AutotuneReport(ctypes.Structure):
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
            "gc_render_batch", "gc_render_grad", "gc_cross_correlate", "gc_default_tune", "gc_set_tune",
            "gc_get_tune", "gc_default_autotune_opts", "gc_autotune", "gc_batch_plan_create", "gc_batch_plan_launch",
-           "gc_batch_plan_results", "gc_batch_plan_destroy"]
+           "gc_batch_plan_results", "gc_batch_plan_destroy", "gc_cross_correlate_map"]
 
 _lib = None
 
@@ -140,6 +140,10 @@ def load():
     L.gc_cross_correlate.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), vp]
     L.gc_cross_correlate.restype = ctypes.c_int
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.gc_cross_correlate_map.argtypes = [vp, vp, vp, i32, i32, i64, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double),
+                                         i32p, i32p, vp]
+    L.gc_cross_correlate_map.restype = ctypes.c_int
     L.gc_default_tune.argtypes = [ctypes.POINTER(Tune)]
     L.gc_default_tune.restype = None
     L.gc_set_tune.argtypes = [vp, ctypes.POINTER(Tune)]
@@ -354,6 +358,26 @@ class Context:
                                          ctypes.byref(ncc), _stream_handle(stream)))
         return c0.value, ncc.value
 
+    def cross_correlate_map(self, img, ref, rx, ry, cols=None, stream=None):
+        """eq. (15) at every shift |dx| <= rx, |dy| <= ry of the device image
+        img (g, H x W x C float32) against ref (f).  cols = (c0, c1) takes the
+        column window [c0, c1) of both (passed with the row pitch, not
+        copied).  Returns (map (2 ry + 1) x (2 rx + 1) float64 device tensor,
+        map[dy + ry, dx + rx] = C(dx, dy), peak value, peak dx, peak dy)."""
+        img = img.to(self.device, torch.float32).contiguous()
+        ref = ref.to(self.device, torch.float32).contiguous()
+        if img.dim() == 2:
+            img, ref = img[:, :, None], ref[:, :, None]
+        H, Wfull, nch = img.shape
+        c0, c1 = (0, Wfull) if cols is None else cols
+        m = torch.empty((2 * ry + 1, 2 * rx + 1), dtype=torch.float64, device=self.device)
+        pk, dx, dy = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32()
+        off = c0 * nch * 4
+        _check(load().gc_cross_correlate_map(self._h, img.data_ptr() + off, ref.data_ptr() + off, H, c1 - c0, Wfull,
+                                             nch, int(rx), int(ry), m.data_ptr(), ctypes.byref(pk), ctypes.byref(dx),
+                                             ctypes.byref(dy), _stream_handle(stream)))
+        return m, pk.value, dx.value, dy.value
+
 
 _default = {}
 
@@ -428,6 +452,10 @@ def render_batch(scenes, cameras, opts, refs=None, device=0):
 
 def cross_correlate(img, ref, device=0):
     return context(device).cross_correlate(img, ref)
+
+
+def cross_correlate_map(img, ref, rx, ry, cols=None, device=0):
+    return context(device).cross_correlate_map(img, ref, rx, ry, cols)
 
 
 def render_grad(scene, camera, opts, ref, prec="f64", loss="ncc", checkpoint_every=64, device=0):

@@ -14,6 +14,7 @@
 #include "gc_lane64.hpp"
 #include "gc_wave.hpp"
 #include "gc_adjoint.hpp"
+#include "gc_corr.hpp"
 
 using namespace gc;
 
@@ -154,97 +155,6 @@ static unsigned flat_blocks(int n_cu, long long npx)
 }
 
 // ---------------------------------------------------------------------------
-// Cross-correlation, eqs. (14)-(15): one pass of FP64 moments per channel
-// (sum f, sum g, sum f^2, sum g^2, sum f g), then centred sums from them.
-// Partials: per block, 5 x nch doubles; a single block folds them.
-// ---------------------------------------------------------------------------
-constexpr int kCCMaxCh = 4;
-constexpr int kCCBlocks = 1024;
-
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__global__ void __launch_bounds__(256) k_cc_moments(const float* __restrict__ g, const float* __restrict__ f,
-                                                    long long npix, int nch, double* __restrict__ part)
-{
-    // moments of the values shifted by the first pixel's (keeps the
-    // centred sums free of cancellation)
-    double m[5][kCCMaxCh];
-    double f0[kCCMaxCh], g0[kCCMaxCh];
-#pragma unroll
-    for (int c = 0; c < kCCMaxCh; ++c) {
-        f0[c] = c < nch ? (double)f[c] : 0.0;
-        g0[c] = c < nch ? (double)g[c] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) m[q][c] = 0.0;
-    }
-    long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
-#pragma unroll
-        for (int c = 0; c < kCCMaxCh; ++c) {
-            if (c < nch) {
-                double a = (double)f[p * nch + c] - f0[c], b = (double)g[p * nch + c] - g0[c];
-                m[0][c] += a;
-                m[1][c] += b;
-                m[2][c] += a * a;
-                m[3][c] += b * b;
-                m[4][c] += a * b;
-            }
-        }
-    }
-    __shared__ double red[4][5 * kCCMaxCh];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-#pragma unroll
-        for (int c = 0; c < kCCMaxCh; ++c) {
-            double v = wave_sum_d(m[q][c]);
-            if (lane == 0) red[wave][q * kCCMaxCh + c] = v;
-        }
-    __syncthreads();
-    if (threadIdx.x < 5 * kCCMaxCh) {
-        double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        part[(long long)blockIdx.x * 5 * kCCMaxCh + threadIdx.x] = v;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_cc_final(const double* __restrict__ part, int nblocks, long long npix,
-                                                  int nch, double* __restrict__ out)
-{
-    __shared__ double tot[5 * kCCMaxCh];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __shared__ double red[4][5 * kCCMaxCh];
-    for (int q = 0; q < 5 * kCCMaxCh; ++q) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += part[(long long)b * 5 * kCCMaxCh + q];
-        v = wave_sum_d(v);
-        if (lane == 0) red[wave][q] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5 * kCCMaxCh)
-        tot[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sfg = 0.0, sff = 0.0, sgg = 0.0;
-        double N = (double)npix;
-        for (int c = 0; c < nch; ++c) {
-            double mf = tot[0 * kCCMaxCh + c] / N, mg = tot[1 * kCCMaxCh + c] / N;
-            sff += tot[2 * kCCMaxCh + c] - N * mf * mf;
-            sgg += tot[3 * kCCMaxCh + c] - N * mg * mg;
-            sfg += tot[4 * kCCMaxCh + c] - N * mf * mg;
-        }
-        out[0] = sfg / sff;
-        out[1] = sfg / sqrt(sff * sgg);
-        out[2] = sff;
-        out[3] = sgg;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 // Device buffers of the FP32 pipeline, grown on demand.
@@ -291,6 +201,9 @@ struct gc_ctx {
     DevCounters* d_cnt;
     double* d_part;
     double* d_ccout;
+    double* d_map_part = nullptr;   // correlation map: partial sums per (dy, row chunk, dx), grown on demand
+    size_t map_part_bytes = 0;
+    double* d_peak = nullptr;       // correlation map: { peak, dx, dy }
     WfStore wf;
     AdjStore adj;
 };
@@ -609,7 +522,8 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
     HIP_OK(hipEventRecord(a.ev[2], stream));
     hipLaunchKernelGGL(k_adj_image, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, a.srgb, npix, c.spp,
                        img);
-    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nbm), dim3(256), 0, stream, img, ref, npix, 3, ctx->d_part);
+    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nbm), dim3(256), 0, stream, img, ref, npix, npix, npix, 3,
+                       ctx->d_part);
     hipLaunchKernelGGL(k_adj_ccstat, dim3(1), dim3(64), 0, stream, ctx->d_part, (int)nbm, npix, img, ref, a.cs);
     hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(1024), 0, stream, sgrad, n, c.spp, img, ref, a.cs, kind, a.red);
     HIP_OK(hipGetLastError());
@@ -1062,7 +976,8 @@ static gc_status create_impl(gc_ctx** out, int hip_device)
     }
     if (hipMalloc(&c->d_cnt, sizeof(DevCounters)) != hipSuccess ||
         hipMalloc(&c->d_part, sizeof(double) * kCCBlocks * 5 * kCCMaxCh) != hipSuccess ||
-        hipMalloc(&c->d_ccout, sizeof(double) * 4) != hipSuccess) {
+        hipMalloc(&c->d_ccout, sizeof(double) * kCCOut) != hipSuccess ||
+        hipMalloc(&c->d_peak, sizeof(double) * 3) != hipSuccess) {
         gc_destroy(c);
         return fail(GC_ENOMEM, "device scratch allocation failed");
     }
@@ -1082,6 +997,8 @@ void gc_destroy(gc_ctx* c)
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_ccout) (void)hipFree(c->d_ccout);
+    if (c->d_map_part) (void)hipFree(c->d_map_part);
+    if (c->d_peak) (void)hipFree(c->d_peak);
     wf_free(c->wf);
     AdjStore& a = c->adj;
     void* bufs[] = {a.tape, a.seg, a.srgb, a.sgrad, a.ovf, a.img, a.cs, a.ctr, a.red};
@@ -1255,10 +1172,10 @@ static gc_status cross_correlate_impl(gc_ctx* ctx, const float* d_img, const flo
     HIP_OK(hipSetDevice(ctx->device));
     long long nb = (npix + 255) / 256;
     if (nb > kCCBlocks) nb = kCCBlocks;
-    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, stream, d_img, d_ref, (long long)npix, nch,
-                       ctx->d_part);
-    hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, stream, ctx->d_part, (int)nb, (long long)npix, nch,
-                       ctx->d_ccout);
+    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, stream, d_img, d_ref, (long long)npix,
+                       (long long)npix, (long long)npix, nch, ctx->d_part);
+    hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, stream, ctx->d_part, (int)nb, (long long)npix, nch, d_img,
+                       d_ref, ctx->d_ccout);
     HIP_OK(hipGetLastError());
     double h[4];
     HIP_OK(hipMemcpyAsync(h, ctx->d_ccout, sizeof h, hipMemcpyDeviceToHost, stream));
@@ -1273,6 +1190,65 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
                              double* C0, double* ncc, hipStream_t stream)
 {
     GC_GUARD(cross_correlate_impl(ctx, d_img, d_ref, npix, nch, C0, ncc, stream));
+}
+
+static gc_status cross_correlate_map_impl(gc_ctx* ctx, const float* d_img, const float* d_ref, int32_t height,
+                                         int32_t width, int64_t pitch, int32_t nch, int32_t rx, int32_t ry,
+                                         double* d_map, double* peak, int32_t* peak_dx, int32_t* peak_dy,
+                                         hipStream_t stream)
+{
+    if (!ctx) return fail(GC_EINVAL, "ctx is null");
+    if (!d_img || !d_ref || !d_map) return fail(GC_EINVAL, "img, ref and map must be non-null");
+    if (height < 1 || width < 1 || pitch < width) return fail(GC_EINVAL, "need height, width >= 1 and pitch >= width");
+    if (nch < 1 || nch > kCCMaxCh) return fail(GC_EINVAL, "need 1 <= nch <= %d", kCCMaxCh);
+    if (rx < 0 || ry < 0 || rx >= width || ry >= height)
+        return fail(GC_EINVAL, "need 0 <= rx < width and 0 <= ry < height");
+    const int ndx = 2 * rx + 1, ndy = 2 * ry + 1;
+    if (ndx > kCCMapMaxDx) return fail(GC_EUNSUPPORTED, "rx = %d: at most %d shifts along a row", rx, kCCMapMaxDx);
+    const size_t lds = std::max<size_t>(sizeof(double) * (size_t)(2 * width + 2 * rx) * nch, sizeof(double) * 256);
+    if (lds > (size_t)kCCMapLds)
+        return fail(GC_EUNSUPPORTED, "(2 width + 2 rx) nch = %lld exceeds the %d doubles of LDS for two rows",
+                    (long long)(2 * width + 2 * rx) * nch, kCCMapLds / 8);
+    HIP_OK(hipSetDevice(ctx->device));
+    // eq. (14): means and sum f'^2 of the window
+    const long long npix = (long long)height * width;
+    const long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
+    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, stream, d_img, d_ref, npix, (long long)width,
+                       (long long)pitch, nch, ctx->d_part);
+    hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, stream, ctx->d_part, (int)nb, npix, nch, d_img, d_ref,
+                       ctx->d_ccout);
+    // rows in chunks so that the grid holds about 4 blocks per CU
+    const int n_chunks = (int)std::max<long long>(1, std::min<long long>(height, (4LL * ctx->n_cu + ndy - 1) / ndy));
+    const int rpc = (height + n_chunks - 1) / n_chunks;
+    const size_t need = sizeof(double) * (size_t)ndy * n_chunks * ndx;
+    gc_status r;
+    if ((r = grow((void**)&ctx->d_map_part, &ctx->map_part_bytes, need, "correlation map partials")) != GC_OK) return r;
+    hipLaunchKernelGGL(k_cc_map_rows, dim3((unsigned)ndy, (unsigned)n_chunks), dim3(256), lds, stream, d_img, d_ref,
+                       height, width, (long long)pitch, nch, rx, ry, rpc, (const double*)ctx->d_ccout,
+                       ctx->d_map_part);
+    hipLaunchKernelGGL(k_cc_map_final, dim3((unsigned)((ndx * ndy + 255) / 256)), dim3(256), 0, stream,
+                       (const double*)ctx->d_map_part, ndx, ndy, n_chunks, (const double*)ctx->d_ccout, d_map);
+    hipLaunchKernelGGL(k_cc_map_peak, dim3(1), dim3(256), 0, stream, (const double*)d_map, ndx, ndy, rx, ry,
+                       ctx->d_peak);
+    HIP_OK(hipGetLastError());
+    double h[kCCOut];
+    HIP_OK(hipMemcpyAsync(h, ctx->d_ccout, sizeof h, hipMemcpyDeviceToHost, stream));
+    double pk[3];
+    HIP_OK(hipMemcpyAsync(pk, ctx->d_peak, sizeof pk, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    if (!(h[2] > 0)) return fail(GC_EINVAL, "reference window is constant: eq. (15) is undefined");
+    if (peak) *peak = pk[0];
+    if (peak_dx) *peak_dx = (int32_t)pk[1];
+    if (peak_dy) *peak_dy = (int32_t)pk[2];
+    return GC_OK;
+}
+
+gc_status gc_cross_correlate_map(gc_ctx* ctx, const float* d_img, const float* d_ref, int32_t height, int32_t width,
+                                 int64_t pitch, int32_t nch, int32_t rx, int32_t ry, double* d_map, double* peak,
+                                 int32_t* peak_dx, int32_t* peak_dy, hipStream_t stream)
+{
+    GC_GUARD(cross_correlate_map_impl(ctx, d_img, d_ref, height, width, pitch, nch, rx, ry, d_map, peak, peak_dx,
+                                      peak_dy, stream));
 }
 
 }  // extern "C"

@@ -34,7 +34,7 @@ struct gc_batch_plan {
     int rounds = 0;
     long long n_pix = 0;
     bool corr = false;
-    double* d_cc = nullptr;      // 4 doubles per scene: C0, ncc and the two variances
+    double* d_cc = nullptr;      // kCCOut doubles per scene: C0, ncc, the two variances, the means
     double* d_part = nullptr;    // partial moments of the correlation
     int* d_rec = nullptr;        // (ray, steps) pairs of the eager run's long first visits
     int* d_front = nullptr;      // the front rays (ascending) and their slots
@@ -145,7 +145,7 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
         return e;
     };
     if (hipStreamCreate(&cs) != hipSuccess) return bail(fail(GC_EDEVICE, "hipStreamCreate failed"));
-    if (hipMalloc(&p->d_cc, sizeof(double) * 4 * n_scenes) != hipSuccess ||
+    if (hipMalloc(&p->d_cc, sizeof(double) * kCCOut * n_scenes) != hipSuccess ||
         hipMalloc(&p->d_part, sizeof(double) * kCCBlocks * 5 * kCCMaxCh) != hipSuccess ||
         hipEventCreate(&p->e0) != hipSuccess || hipEventCreate(&p->e1) != hipSuccess)
         return bail(fail(GC_ENOMEM, "batch plan: allocation failed"));
@@ -196,9 +196,9 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
                                        sd[i].K, d_ref[i], nullptr);
                 long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
                 hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, cs, (const float*)d_rgb[i],
-                                   (const float*)d_ref[i], npix, 3, p->d_part);
+                                   (const float*)d_ref[i], npix, npix, npix, 3, p->d_part);
                 hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, cs, (const double*)p->d_part, (int)nb, npix,
-                                   3, p->d_cc + 4 * i);
+                                   3, (const float*)d_rgb[i], (const float*)d_ref[i], p->d_cc + kCCOut * i);
             }
         }
         const bool launch_ok = hipGetLastError() == hipSuccess;
@@ -254,7 +254,7 @@ static gc_status batch_plan_results_impl(gc_batch_plan* p, double* C0, gc_stats*
     HIP_OK(hipSetDevice(p->ctx->device));
     WfTotals tot;
     QCtr ctr;
-    std::vector<double> cc(4 * (size_t)p->ns);
+    std::vector<double> cc(kCCOut * (size_t)p->ns);
     HIP_OK(hipMemcpyAsync(&tot, p->w.tot, sizeof tot, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipMemcpyAsync(&ctr, p->w.ctr, sizeof ctr, hipMemcpyDeviceToHost, stream));
     if (p->corr) HIP_OK(hipMemcpyAsync(cc.data(), p->d_cc, sizeof(double) * cc.size(), hipMemcpyDeviceToHost, stream));
@@ -279,8 +279,8 @@ static gc_status batch_plan_results_impl(gc_batch_plan* p, double* C0, gc_stats*
             if (hipEventElapsedTime(&ms, p->ev_round[2 * k], p->ev_round[2 * k + 1]) == hipSuccess) st->hot_ms += ms;
     }
     for (int i = 0; i < p->ns && p->corr; ++i) {
-        if (!(cc[4 * i + 2] > 0)) return fail(GC_EINVAL, "reference image %d is constant: eq. (15) is undefined", i);
-        C0[i] = cc[4 * i];
+        if (!(cc[kCCOut * i + 2] > 0)) return fail(GC_EINVAL, "reference image %d is constant: eq. (15) is undefined", i);
+        C0[i] = cc[kCCOut * i];
     }
     return GC_OK;
 }
