@@ -396,6 +396,27 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
                              int64_t npix, int32_t nch, double* C0, double* ncc,
                              hipStream_t stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * zero-shift correlation as gc_cross_correlate, computed by the same
+ * kernels, but with no allocation and no synchronisation: the block
+ * partials live in a fixed scratch array compiled into the library (160 KiB
+ * per GPU, held until the process ends; its device address is taken when the
+ * first context on that GPU is created), and the results stay on the device.
+ * d_img (g), d_ref (f): npix x nch float32, channel fastest.  d_out (device,
+ * caller-owned, 12 doubles) receives { C0 = sum f'g' / sum f'^2 (eq. (15)
+ * at (0, 0)), ncc, sum f'^2, sum g'^2, the 4 channel means of f, the 4
+ * channel means of g } (unused channels 0); a constant reference gives
+ * sum f'^2 = 0 and C0 = NaN.  Any npix >= 1 fits (the scratch holds 1024
+ * block partials, and the blocks stride over the pixels); nch above 4 is
+ * rejected with GC_EINVAL.  Every call on one GPU shares that GPU's scratch
+ * (the last call's partials stay in it), so calls that overlap on one GPU --
+ * on different streams, from different contexts or threads -- race and
+ * must be ordered by the caller.  Asynchronous on `stream`; calls no
+ * hipMalloc, hipFree or memset. */
+gc_status gc_cross_correlate_noalloc(gc_ctx* ctx, const float* d_img, const float* d_ref, int64_t npix, int32_t nch,
+                                     double* d_out, hipStream_t stream);
+
 /* Correlation map: eq. (15) at every shift (Sec. 5), the "more generous"
  * measure of cloaking quality whose peak value and location also quantify
  * an image displacement.  d_img (g) and d_ref (f) are device windows of

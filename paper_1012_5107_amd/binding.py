@@ -102,7 +102,8 @@ class AutotuneReport(ctypes.Structure):
 EXPORTS = ["gc_create", "gc_destroy", "gc_last_error", "gc_default_opts", "gc_trace_rays", "gc_render",
            "gc_render_batch", "gc_render_grad", "gc_cross_correlate", "gc_default_tune", "gc_set_tune",
            "gc_get_tune", "gc_default_autotune_opts", "gc_autotune", "gc_batch_plan_create", "gc_batch_plan_launch",
-           "gc_batch_plan_results", "gc_batch_plan_destroy", "gc_cross_correlate_map"]
+           "gc_batch_plan_results", "gc_batch_plan_destroy", "gc_cross_correlate_map",
+           "gc_cross_correlate_noalloc"]
 
 _lib = None
 
@@ -144,6 +145,8 @@ def load():
     L.gc_cross_correlate_map.argtypes = [vp, vp, vp, i32, i32, i64, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double),
                                          i32p, i32p, vp]
     L.gc_cross_correlate_map.restype = ctypes.c_int
+    L.gc_cross_correlate_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, vp]
+    L.gc_cross_correlate_noalloc.restype = ctypes.c_int
     L.gc_default_tune.argtypes = [ctypes.POINTER(Tune)]
     L.gc_default_tune.restype = None
     L.gc_set_tune.argtypes = [vp, ctypes.POINTER(Tune)]
@@ -357,6 +360,17 @@ class Context:
         _check(load().gc_cross_correlate(self._h, img.data_ptr(), ref.data_ptr(), npix, nch, ctypes.byref(c0),
                                          ctypes.byref(ncc), _stream_handle(stream)))
         return c0.value, ncc.value
+
+    def cross_correlate_noalloc(self, img, ref, out, stream=None):
+        """gc_cross_correlate_noalloc: the zero-shift correlation into the
+        device tensor out (12 float64: C0, ncc, sum f'^2, sum g'^2, 4 means
+        of f, 4 of g), asynchronously, with no allocation in the library.
+        img and ref must be contiguous float32 device tensors."""
+        nch = img.shape[-1] if img.dim() == 3 else 1
+        npix = img.numel() // nch
+        _check(load().gc_cross_correlate_noalloc(self._h, img.data_ptr(), ref.data_ptr(), npix, nch, out.data_ptr(),
+                                                 _stream_handle(stream)))
+        return out
 
     def cross_correlate_map(self, img, ref, rx, ry, cols=None, stream=None):
         """eq. (15) at every shift |dx| <= rx, |dy| <= ry of the device image

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -204,9 +205,21 @@ struct gc_ctx {
     double* d_map_part = nullptr;   // correlation map: partial sums per (dy, row chunk, dx), grown on demand
     size_t map_part_bytes = 0;
     double* d_peak = nullptr;       // correlation map: { peak, dx, dy }
+    double* d_scratch = nullptr;    // this device's copy of `scratch` (device address)
     WfStore wf;
     AdjStore adj;
 };
+
+// Scratch of gc_cross_correlate_noalloc: the block partials of the moments
+// pass (kCCBlocks x 5 moments x kCCMaxCh channels), one copy per GPU for the
+// life of the process.  Host code never passes this name to a kernel (on the
+// host it only stands in for the symbol): it takes the device address that
+// hipGetSymbolAddress returns for the current device, recorded once per
+// device when the first context on it is created.
+static __device__ __align__(256) double scratch[kCCBlocks * 5 * kCCMaxCh];
+constexpr int kMaxDevices = 256;
+static std::mutex g_scratch_mu;
+static double* g_scratch_addr[kMaxDevices] = {};
 
 static thread_local std::string g_err;
 
@@ -974,6 +987,22 @@ static gc_status create_impl(gc_ctx** out, int hip_device)
         if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return fail(GC_EDEVICE, "hipGetDeviceProperties failed"); }
         c->n_cu = prop.multiProcessorCount;
     }
+    if (hip_device >= kMaxDevices) { delete c; return fail(GC_EINVAL, "device %d: at most %d devices", hip_device, kMaxDevices); }
+    {
+        // the device address of this GPU's `scratch`, once per device (with
+        // the device current)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_addr[hip_device]) {
+            void* addr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !addr) {
+                delete c;
+                return fail(GC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            }
+            g_scratch_addr[hip_device] = static_cast<double*>(addr);
+        }
+        c->d_scratch = g_scratch_addr[hip_device];
+    }
     if (hipMalloc(&c->d_cnt, sizeof(DevCounters)) != hipSuccess ||
         hipMalloc(&c->d_part, sizeof(double) * kCCBlocks * 5 * kCCMaxCh) != hipSuccess ||
         hipMalloc(&c->d_ccout, sizeof(double) * kCCOut) != hipSuccess ||
@@ -1190,6 +1219,34 @@ gc_status gc_cross_correlate(gc_ctx* ctx, const float* d_img, const float* d_ref
                              double* C0, double* ncc, hipStream_t stream)
 {
     GC_GUARD(cross_correlate_impl(ctx, d_img, d_ref, npix, nch, C0, ncc, stream));
+}
+
+static gc_status cross_correlate_noalloc_impl(gc_ctx* ctx, const float* d_img, const float* d_ref, int64_t npix,
+                                              int32_t nch, double* d_out, hipStream_t stream)
+{
+    if (!ctx) return fail(GC_EINVAL, "ctx is null");
+    if (!d_img || !d_ref || !d_out) return fail(GC_EINVAL, "img, ref and out must be non-null");
+    if (npix < 1) return fail(GC_EINVAL, "need npix >= 1");
+    if (nch < 1 || nch > kCCMaxCh)
+        return fail(GC_EINVAL, "nch = %d: the scratch holds the moments of at most %d channels", nch, kCCMaxCh);
+    if (!ctx->d_scratch) return fail(GC_EDEVICE, "scratch address not set up");
+    HIP_OK(hipSetDevice(ctx->device));
+    // the blocks stride over the pixels, so any npix fits the kCCBlocks
+    // partials; k_cc_moments writes every partial k_cc_final reads, so
+    // nothing needs clearing
+    const long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
+    hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, stream, d_img, d_ref, (long long)npix,
+                       (long long)npix, (long long)npix, nch, ctx->d_scratch);
+    hipLaunchKernelGGL(k_cc_final, dim3(1), dim3(256), 0, stream, (const double*)ctx->d_scratch, (int)nb,
+                       (long long)npix, nch, d_img, d_ref, d_out);
+    HIP_OK(hipGetLastError());
+    return GC_OK;
+}
+
+gc_status gc_cross_correlate_noalloc(gc_ctx* ctx, const float* d_img, const float* d_ref, int64_t npix, int32_t nch,
+                                     double* d_out, hipStream_t stream)
+{
+    GC_GUARD(cross_correlate_noalloc_impl(ctx, d_img, d_ref, npix, nch, d_out, stream));
 }
 
 static gc_status cross_correlate_map_impl(gc_ctx* ctx, const float* d_img, const float* d_ref, int32_t height,
