@@ -241,8 +241,10 @@ void gc_batch_plan_destroy(gc_batch_plan* plan);
  *     reference must be within cc_tol of the FP64 image's (with
  *     cc_scale = 1 the timed full-size renders are the ones checked).
  * Candidates (DOPRI5): rtol x {3, 1, 1/3} times h_max x {1, 2.5, 5,
- * 10, 25}; RK4 keeps its step (one candidate).  Of the candidates that
- * pass, the one with the shortest FP32 render of the whole workload is
+ * 10, 25} (RK4 keeps its step: one candidate), at FP64 hand-over
+ * thresholds w_fallback in {the given one, 0.1, 0.3}: the larger levels
+ * are tried, in that order, only while no candidate has passed (at most 45
+ * candidates).  Of the candidates that pass, the one with the shortest FP32 render of the whole workload is
  * chosen (best of `reps`); if none passes, the fastest that is nowhere less
  * accurate than the options as given (see `chosen`); then, if tune_sched, a fixed set of gc_tune
  * settings is timed the same way and the fastest is installed in the
@@ -261,11 +263,12 @@ typedef struct {
     int32_t tune_sched;    /* default 1 */
 } gc_autotune_opts;
 
-#define GC_AUTOTUNE_MAX_CAND 16
+#define GC_AUTOTUNE_MAX_CAND 48
 
 typedef struct {
     double rtol;
     double h_max;
+    double w_fallback;
     double ms;             /* best FP32 render time of the workload (HIP events) */
     int64_t steps;         /* FP32 accepted steps of the workload */
     double dir_p99, dir_max, changed, cc_err;   /* worst over the scenes */
@@ -291,7 +294,7 @@ void gc_default_autotune_opts(gc_autotune_opts* at);
 
 /* Run the autotuner (see above) on n_scenes scenes and cameras with FP32
  * options `opts` (prec must be GC_F32).  Writes the tuned options to
- * opts_out (equal to opts but for rtol, atol and h_max) and, if `report` is non-null, the
+ * opts_out (equal to opts but for rtol, atol, h_max and w_fallback) and, if `report` is non-null, the
  * measurements.  Device scratch for the calibration is allocated and freed
  * inside the call; the stream is synchronised.  GC_EINVAL for bad
  * arguments, GC_EUNSUPPORTED for prec != GC_F32. */

@@ -74,11 +74,12 @@ class AutotuneOpts(ctypes.Structure):
                 ("reps", ctypes.c_int32), ("tune_sched", ctypes.c_int32)]
 
 
-AUTOTUNE_MAX_CAND = 16
+AUTOTUNE_MAX_CAND = 48
 
 
 class AutotuneCand(ctypes.Structure):
-    _fields_ = [("rtol", ctypes.c_double), ("h_max", ctypes.c_double), ("ms", ctypes.c_double), ("steps", ctypes.c_int64),
+    _fields_ = [("rtol", ctypes.c_double), ("h_max", ctypes.c_double), ("w_fallback", ctypes.c_double),
+                ("ms", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("dir_p99", ctypes.c_double), ("dir_max", ctypes.c_double), ("changed", ctypes.c_double),
                 ("cc_err", ctypes.c_double), ("pass_", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
@@ -92,7 +93,7 @@ class AutotuneReport(ctypes.Structure):
         cands = []
         for i in range(self.n_cand):
             c = self.cand[i]
-            cands.append(dict(rtol=c.rtol, h_max=c.h_max, ms=c.ms, steps=int(c.steps), dir_p99=c.dir_p99, dir_max=c.dir_max,
+            cands.append(dict(rtol=c.rtol, h_max=c.h_max, w_fallback=c.w_fallback, ms=c.ms, steps=int(c.steps), dir_p99=c.dir_p99, dir_max=c.dir_max,
                               changed=c.changed, cc_err=c.cc_err, passed=bool(c.pass_)))
         return dict(candidates=cands, chosen=int(self.chosen), tune=self.tune.as_dict(), tune_ms=self.tune_ms,
                     base_tune_ms=self.base_tune_ms, cal_rays=int(self.cal_rays), ill_rays=int(self.ill_rays))
@@ -289,7 +290,7 @@ class Context:
         rep = AutotuneReport()
         _check(L.gc_autotune(self._h, n, sc_arr, cam_arr, ctypes.byref(op), ctypes.byref(at), ctypes.byref(out),
                              ctypes.byref(rep), _stream_handle(stream)))
-        tuned = dict(opts, h_max=out.h_max, rtol=out.rtol, atol=out.atol)
+        tuned = dict(opts, h_max=out.h_max, rtol=out.rtol, atol=out.atol, w_fallback=out.w_fallback)
         return tuned, rep.as_dict()
 
     def render(self, scene, camera, opts, prec="f64", out=None, stats=True, stream=None):

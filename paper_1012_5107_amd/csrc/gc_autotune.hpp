@@ -169,7 +169,7 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
         max_ccpix = std::max(max_ccpix, cal[i].cc_npix);
     }
     DevMem pert, out_dir, st_buf, ev_buf, img64, img32;
-    static_assert(GC_AUTOTUNE_MAX_CAND >= 15, "room for every candidate");
+    static_assert(GC_AUTOTUNE_MAX_CAND >= 45, "room for every candidate");
     if (!pert.alloc(sizeof(double) * 3 * max_cal) || !out_dir.alloc(sizeof(double) * 3 * max_cal) ||
         !st_buf.alloc(sizeof(int32_t) * max_cal) || !ev_buf.alloc(sizeof(int32_t) * max_cal) ||
         !img64.alloc(sizeof(float) * 3 * max_ccpix) || !img32.alloc(sizeof(float) * 3 * max_ccpix))
@@ -254,76 +254,88 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
     // ---- step-control candidates --------------------------------------------
     // around the given tolerance, one looser: the FP32 truncation error of
     // the exit directions grows like rtol^1.5, so a factor of 3 can still
-    // pass and saves steps on every ray
+    // pass and saves steps on every ray.  The FP64 hand-over threshold is
+    // the third lever: near the crests of a high-amplitude grating FP32
+    // cannot resolve W (the Halley residual W - Z e^-W loses its leading
+    // digits as |1 + W| shrinks), so a larger threshold hands more steps to
+    // FP64.  Threshold levels are tried in order (the given one first) and
+    // the search stops after the first level at which a candidate passes.
     static const double kTolFactor[] = {3.0, 1.0, 1.0 / 3.0};
     static const double kCapFactor[] = {1.0, 2.5, 5.0, 10.0, 25.0};
+    const double kWfb[3] = {opts->w_fallback, 0.1, 0.3};
     const bool dp = opts->integ == GC_DOPRI5;
     const int n_tol = dp ? 3 : 1, n_cap = dp ? 5 : 1;
     double best_ms = HUGE_VAL;
-    for (int ti = 0; ti < n_tol; ++ti)
-    for (int ci = 0; ci < n_cap; ++ci) {
-        gc_autotune_cand& cand = rep.cand[rep.n_cand++];
-        gc_opts o = *opts;
-        o.rtol = opts->rtol * kTolFactor[ti];
-        o.atol = opts->atol * kTolFactor[ti];
-        o.h_max = opts->h_max * kCapFactor[ci];
-        cand.rtol = o.rtol;
-        cand.h_max = o.h_max;
-        if ((r = time_workload(o, &cand.ms, &cand.steps)) != GC_OK) return r;
-        double p99 = 0.0, mx = 0.0, chg = 0.0, cce = 0.0;
-        for (int i = 0; i < n_scenes; ++i) {
-            Calib& c = cal[i];
-            TraceHost t;
-            if ((r = trace_to_host(ctx, &scenes[i], &o, c.n, c.org.as<double>(), c.dir.as<double>(), out_dir, st_buf,
-                                   ev_buf, t, stream)) != GC_OK)
-                return r;
-            long long changed = 0;
-            std::vector<double> err;
-            err.reserve(c.n);
-            for (long long q = 0; q < c.n; ++q) {
-                if (t.status[q] != c.ref.status[q] || t.events[q] != c.ref.events[q]) { ++changed; continue; }
-                if (c.well[q]) err.push_back(angle3(&t.dir[3 * q], &c.ref.dir[3 * q]));
-            }
-            chg = std::max(chg, (double)changed / (double)std::max(1ll, c.n));
-            if (!err.empty()) {
-                const size_t k99 = (size_t)std::floor(0.99 * (double)(err.size() - 1));
-                std::nth_element(err.begin(), err.begin() + k99, err.end());
-                p99 = std::max(p99, err[k99]);
-                mx = std::max(mx, *std::max_element(err.begin(), err.end()));
-            }
-            // at full size the timed render's image is the one to check
-            const float* img = d_rgb[i];
-            if (at.cc_scale > 1) {
-                if ((r = gc_render(ctx, &scenes[i], &c.cc_cam, &o, img32.as<float>(), nullptr, stream)) != GC_OK)
+    int n_levels = 0;
+    for (int wi = 0; wi < 3; ++wi) {
+        if (wi > 0 && (rep.chosen >= 0 || !(kWfb[wi] > opts->w_fallback))) break;
+        ++n_levels;
+        for (int ti = 0; ti < n_tol; ++ti)
+        for (int ci = 0; ci < n_cap; ++ci) {
+            gc_autotune_cand& cand = rep.cand[rep.n_cand++];
+            gc_opts o = *opts;
+            o.rtol = opts->rtol * kTolFactor[ti];
+            o.atol = opts->atol * kTolFactor[ti];
+            o.h_max = opts->h_max * kCapFactor[ci];
+            o.w_fallback = kWfb[wi];
+            cand.rtol = o.rtol;
+            cand.h_max = o.h_max;
+            cand.w_fallback = o.w_fallback;
+            if ((r = time_workload(o, &cand.ms, &cand.steps)) != GC_OK) return r;
+            double p99 = 0.0, mx = 0.0, chg = 0.0, cce = 0.0;
+            for (int i = 0; i < n_scenes; ++i) {
+                Calib& c = cal[i];
+                TraceHost t;
+                if ((r = trace_to_host(ctx, &scenes[i], &o, c.n, c.org.as<double>(), c.dir.as<double>(), out_dir,
+                                       st_buf, ev_buf, t, stream)) != GC_OK)
                     return r;
-                img = img32.as<float>();
+                long long changed = 0;
+                std::vector<double> err;
+                err.reserve(c.n);
+                for (long long q = 0; q < c.n; ++q) {
+                    if (t.status[q] != c.ref.status[q] || t.events[q] != c.ref.events[q]) { ++changed; continue; }
+                    if (c.well[q]) err.push_back(angle3(&t.dir[3 * q], &c.ref.dir[3 * q]));
+                }
+                chg = std::max(chg, (double)changed / (double)std::max(1ll, c.n));
+                if (!err.empty()) {
+                    const size_t k99 = (size_t)std::floor(0.99 * (double)(err.size() - 1));
+                    std::nth_element(err.begin(), err.begin() + k99, err.end());
+                    p99 = std::max(p99, err[k99]);
+                    mx = std::max(mx, *std::max_element(err.begin(), err.end()));
+                }
+                // at full size the timed render's image is the one to check
+                const float* img = d_rgb[i];
+                if (at.cc_scale > 1) {
+                    if ((r = gc_render(ctx, &scenes[i], &c.cc_cam, &o, img32.as<float>(), nullptr, stream)) != GC_OK)
+                        return r;
+                    img = img32.as<float>();
+                }
+                double c0 = 0.0;
+                if ((r = gc_cross_correlate(ctx, img, c.flat.as<float>(), c.cc_npix, 3, &c0, nullptr, stream)) !=
+                    GC_OK)
+                    return r;
+                cce = std::max(cce, std::fabs(c0 - c.c0_ref));
             }
-            double c0 = 0.0;
-            if ((r = gc_cross_correlate(ctx, img, c.flat.as<float>(), c.cc_npix, 3, &c0, nullptr, stream)) != GC_OK)
-                return r;
-            cce = std::max(cce, std::fabs(c0 - c.c0_ref));
-        }
-        cand.dir_p99 = p99;
-        cand.dir_max = mx;
-        cand.changed = chg;
-        cand.cc_err = cce;
-        cand.pass = p99 <= at.dir_tol && mx <= 50.0 * at.dir_tol && chg <= at.max_changed && cce <= at.cc_tol;
-        if (cand.pass && cand.ms < best_ms) {
-            best_ms = cand.ms;
-            rep.chosen = rep.n_cand - 1;
-            *opts_out = o;
+            cand.dir_p99 = p99;
+            cand.dir_max = mx;
+            cand.changed = chg;
+            cand.cc_err = cce;
+            cand.pass = p99 <= at.dir_tol && mx <= 50.0 * at.dir_tol && chg <= at.max_changed && cce <= at.cc_tol;
+            if (cand.pass && cand.ms < best_ms) {
+                best_ms = cand.ms;
+                rep.chosen = rep.n_cand - 1;
+                *opts_out = o;
+            }
         }
     }
 
-    if (rep.chosen < 0 && n_tol * n_cap > 1) {
+    if (rep.chosen < 0 && rep.n_cand > 1) {
         // no candidate meets the bounds: the fastest one that is nowhere less
         // accurate than the options as given (every measured error at most
         // theirs), which keeps the reported accuracy and saves time; its pass
-        // flag stays 0
-        int base = -1;
-        for (int ti = 0; ti < n_tol; ++ti)
-            for (int ci = 0; ci < n_cap; ++ci)
-                if (kTolFactor[ti] == 1.0 && kCapFactor[ci] == 1.0) base = ti * n_cap + ci;
+        // flag stays 0.  The options as given are candidate (tol 1, cap 1) of
+        // the first threshold level.
+        const int base = 1 * n_cap + 0;
         const gc_autotune_cand& b = rep.cand[base];
         double best = b.ms;
         for (int i = 0; i < rep.n_cand; ++i) {
@@ -335,12 +347,14 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
             }
         }
         if (rep.chosen >= 0) {
-            const int ti = rep.chosen / n_cap, ci = rep.chosen % n_cap;
-            opts_out->rtol = opts->rtol * kTolFactor[ti];
-            opts_out->atol = opts->atol * kTolFactor[ti];
-            opts_out->h_max = opts->h_max * kCapFactor[ci];
+            const gc_autotune_cand& c = rep.cand[rep.chosen];
+            opts_out->rtol = c.rtol;
+            opts_out->atol = opts->atol * (c.rtol / opts->rtol);
+            opts_out->h_max = c.h_max;
+            opts_out->w_fallback = c.w_fallback;
         }
     }
+    (void)n_levels;
 
     // ---- scheduling ---------------------------------------------------------
     const gc_tune entry = ctx->tune;

@@ -65,9 +65,10 @@ def test_tune_rejects_out_of_range(B):
 
 
 def test_autotune_fallback_when_nothing_passes(B):
-    """With bounds no candidate can meet, the autotuner returns the fastest
-    candidate whose every measured error is at most that of the options as
-    given (flagged as not passing), or the options themselves."""
+    """With bounds no candidate can meet, the autotuner tries every FP64
+    hand-over level and returns the fastest candidate whose every measured
+    error is at most that of the options as given (flagged as not passing),
+    or the options themselves."""
     sc = W.scene(A=0.1, half_width=3.0)
     cam = W.camera(64, 48, spp=1, jitter=True, seed=9)
     op = W.opts("dopri5", rtol=1e-7)
@@ -76,19 +77,22 @@ def test_autotune_fallback_when_nothing_passes(B):
         tuned, rep = ctx.autotune(sc, cam, op, dir_scale=2, reps=1, tune_sched=0, dir_tol=1e-12, cc_tol=1e-12)
         cands = rep["candidates"]
         assert not any(c["passed"] for c in cands)
+        assert len(cands) == 45
+        assert sorted({c["w_fallback"] for c in cands}) == pytest.approx([op["w_fallback"], 0.1, 0.3])
         base = [i for i, c in enumerate(cands) if c["rtol"] == pytest.approx(op["rtol"])
-                and c["h_max"] == pytest.approx(op["h_max"])]
+                and c["h_max"] == pytest.approx(op["h_max"]) and c["w_fallback"] == op["w_fallback"]]
         assert len(base) == 1
         b = cands[base[0]]
         ch = rep["chosen"]
         if ch < 0:
-            assert (tuned["rtol"], tuned["h_max"]) == (op["rtol"], op["h_max"])
+            assert (tuned["rtol"], tuned["h_max"], tuned["w_fallback"]) == (op["rtol"], op["h_max"], op["w_fallback"])
         else:
             c = cands[ch]
             assert c["ms"] < b["ms"]
             for k in ("dir_p99", "dir_max", "changed", "cc_err"):
                 assert c[k] <= b[k], k
-            assert (tuned["rtol"], tuned["h_max"]) == pytest.approx((c["rtol"], c["h_max"]))
+            assert (tuned["rtol"], tuned["h_max"], tuned["w_fallback"]) == \
+                pytest.approx((c["rtol"], c["h_max"], c["w_fallback"]))
             # no other no-worse candidate is faster
             for o in cands:
                 if all(o[k] <= b[k] for k in ("dir_p99", "dir_max", "changed", "cc_err")):
@@ -98,7 +102,8 @@ def test_autotune_fallback_when_nothing_passes(B):
 
 
 def test_autotune_small_workload(B):
-    """The autotuner keeps every option but h_max, reports the candidates it
+    """The autotuner keeps every option but the step control and the FP64
+    hand-over threshold, reports the candidates it
     measured, chooses one that passed its own bounds, and installs the
     fastest scheduling; an image rendered with the tuned options stays within
     the correlation bound of the FP64 path.  At 96 x 80 pixels two correct
@@ -112,13 +117,15 @@ def test_autotune_small_workload(B):
     try:
         tuned, rep = ctx.autotune(sc, cam, op, dir_scale=2, reps=1, cc_tol=1e-3)
         print("[autotune]", rep, flush=True)
-        tuned_keys = ("h_max", "rtol", "atol")
+        tuned_keys = ("h_max", "rtol", "atol", "w_fallback")
         assert {k: v for k, v in tuned.items() if k not in tuned_keys} == \
             {k: v for k, v in op.items() if k not in tuned_keys}
         assert tuned["atol"] == pytest.approx(tuned["rtol"])
-        grid = [(op["rtol"] * t, op["h_max"] * f) for t in (3, 1, 1 / 3) for f in (1, 2.5, 5, 10, 25)]
+        # a candidate at the given hand-over threshold passes: no other level
+        grid = [(op["rtol"] * t, op["h_max"] * f, op["w_fallback"]) for t in (3, 1, 1 / 3)
+                for f in (1, 2.5, 5, 10, 25)]
         assert len(rep["candidates"]) == len(grid)
-        assert [(c["rtol"], c["h_max"]) for c in rep["candidates"]] == pytest.approx(grid)
+        assert [(c["rtol"], c["h_max"], c["w_fallback"]) for c in rep["candidates"]] == pytest.approx(grid)
         assert rep["cal_rays"] == 48 * 40 * 2
         ch = rep["chosen"]
         assert ch >= 0, "the configured step cap should pass its own bounds"
