@@ -28,13 +28,24 @@
  *
  * Parameter blocks are flat arrays so that this file needs no header shared
  * with anything else:
- *   scene[8]  = { Lambda, A, half_width, y_top, cloak, mirror, sky_K, unused }
- *               cloak: 0 -> n = 1 everywhere, 1 -> eq. (1) inside the box
+ *   scene[11] = { Lambda, A, half_width, y_top, cloak, mirror, sky_K, fresnel,
+ *                 backdrop, backdrop_y, backdrop_period }
+ *               cloak: 0 -> n = 1 everywhere, 1 -> eq. (1) inside the box,
+ *                      2 -> referenced cloak: eq. (1) / n_min inside the box,
+ *                           n_min = 1 / (1 + A k) (Sec. 4, Figs. 5-7),
+ *                      3 -> homogeneous dielectric plate of index
+ *                           1 / n_min = 1 + A k filling the box (Sec. 4)
  *               mirror: 0 -> trochoid eq. (2), 1 -> flat mirror y = 0
+ *               fresnel: 0 -> Snell + total internal reflection, weight 1;
+ *                        1 -> Fresnel-weighted faces with one reflected
+ *                             branch per crossing of the primary ray (Sec. 3)
+ *               backdrop: 0 -> sky at infinity; 1 -> patterned plane
+ *                         y = backdrop_y (the photograph, Sec. 4)
  *   opts[10]  = { integrator (0 RK4, 1 DOPRI5), h, rtol, atol, h_max,
  *                 max_events, max_steps, h0, h_min, diagnostics }
- *   camera[12]= { eye xyz, target xyz, fov_y_deg, width, height, spp,
- *                 jitter, scene_index }  (seed passed separately)
+ *   camera[16]= { eye xyz, target xyz, fov_y_deg, width, height, spp,
+ *                 jitter, scene_index, up xyz, fov_x_deg }  (seed passed
+ *                 separately; up = 0 -> +y; fov_x_deg = 0 -> square pixels)
  */
 #include <complex.h>
 #include <float.h>
@@ -55,9 +66,15 @@ enum { RAY_OK = 0, RAY_MAX_STEPS = 1, RAY_MAX_EVENTS = 2, RAY_NONFINITE = 3,
 
 typedef struct {
     double L, A, hw, ytop, K;
-    int cloak, mirror;
-    double k, e;   /* k = 2 pi / Lambda, e = A k */
+    int cloak, mirror, fresnel, backdrop;
+    double bd_y, bd_P;   /* backdrop plane height and pattern period */
+    double k, e;         /* k = 2 pi / Lambda, e = A k */
+    double nscale;       /* index multiplier inside the box: 1 / n_min = 1 + A k for cloak 2, else 1 */
 } oscene;
+
+enum { CLOAK_NONE = 0, CLOAK_EQ1 = 1, CLOAK_REF = 2, CLOAK_PLATE = 3 };
+
+void gco_sky(double K, const double d[3], double rgb[3]);
 
 typedef struct {
     int integ;
@@ -71,8 +88,12 @@ static void load_scene(const double* s, oscene* o)
 {
     o->L = s[0]; o->A = s[1]; o->hw = s[2]; o->ytop = s[3];
     o->cloak = (int)s[4]; o->mirror = (int)s[5]; o->K = s[6];
+    o->fresnel = (int)s[7]; o->backdrop = (int)s[8]; o->bd_y = s[9]; o->bd_P = s[10];
     o->k = 2.0 * ORC_PI / o->L;
     o->e = o->A * o->k;
+    /* Sec. 4: referencing divides every index of the cloak by its minimum,
+       n_min = 1 / (1 + A k) (the trough of the grating, on the surface) */
+    o->nscale = (o->cloak == CLOAK_REF) ? 1.0 + o->e : 1.0;
 }
 
 static void load_opts(const double* p, oopts* o)
@@ -187,6 +208,14 @@ static void orc_accel(const oscene* s, double x, double y, double* ax, double* a
     *ay = cimag(a);
 }
 
+/* Index inside the box: eq. (1) (cloak 1), eq. (1) / n_min (cloak 2, the
+   referenced cloak of Sec. 4) or the plate's 1 / n_min = 1 + A k (cloak 3). */
+static double box_index(const oscene* s, double x, double y, int* bad)
+{
+    if (s->cloak == CLOAK_PLATE) return 1.0 + s->e;
+    return s->nscale * orc_index_raw(s, x, y, bad);
+}
+
 /* eq. (12), literally: grad n in terms of W0. */
 static void orc_grad_n_eq12(const oscene* s, double x, double y, double* gx, double* gy)
 {
@@ -247,14 +276,17 @@ static void orc_grating_normal(const oscene* s, double E, double* nx, double* ny
 /* ------------------------------------------------------------------------ */
 typedef struct { double v[4]; } st4;   /* x, y, px, py */
 
+/* dr/dtau = p, dp/dtau = grad(n^2)/2 with n the box index: for the
+   referenced cloak n = s n1 (s = 1 / n_min) and grad(n^2)/2 = s^2 n1 grad n1. */
 static void rhs(const oscene* s, const st4* u, st4* du, int* bad)
 {
     double ax, ay;
     orc_accel(s, u->v[0], u->v[1], &ax, &ay, bad);
+    const double s2 = s->nscale * s->nscale;
     du->v[0] = u->v[2];
     du->v[1] = u->v[3];
-    du->v[2] = ax;
-    du->v[3] = ay;
+    du->v[2] = s2 * ax;
+    du->v[3] = s2 * ay;
 }
 
 static void axpy(st4* out, const st4* u, double h, const st4* k)
@@ -450,6 +482,9 @@ typedef struct {
     double min_cos;   /* smallest |p_hat . N| over all contacts and face crossings */
     long bad_w;       /* Lambert-W evaluations that failed their check */
     double max_H;     /* diagnostics: max | |p|^2 - n^2 | / n^2 at step ends */
+    long bsteps, brejected;  /* steps / rejections taken in Fresnel-reflected branches */
+    long branch_events;  /* events of Fresnel-reflected branches */
+    long branch_failed;  /* Fresnel-reflected branches that failed (they add nothing) */
 } trace_info;
 
 static int all_finite(const double* a, int n)
@@ -461,9 +496,10 @@ static int all_finite(const double* a, int n)
 /* Integration inside the box from (r, p) on entry until the ray leaves B
    through a face into air.  Grating contacts and total internal reflections
    at faces are handled inside.  Returns a ray status; on RAY_OK, r and p hold
-   the exit point and the refracted momentum (|p| = 1). */
+   the exit point and the refracted momentum (|p| = 1), p_in the momentum
+   just inside the face and n_face the face's outward normal. */
 static int integrate_box(const oscene* s, const oopts* o, double r[3], double p[3],
-                         trace_info* ti)
+                         trace_info* ti, double p_in[3], double n_face[3])
 {
     st4 u = { { r[0], r[1], p[0], p[1] } };
     double z = r[2], pz = p[2];
@@ -526,7 +562,7 @@ static int integrate_box(const oscene* s, const oopts* o, double r[3], double p[
             if (hi < theta) { theta = hi; hit = ev; }
         }
         if (o->diag) {
-            double n = orc_index_raw(s, y5.v[0], y5.v[1], NULL);
+            double n = box_index(s, y5.v[0], y5.v[1], NULL);
             double H = fabs(y5.v[2] * y5.v[2] + y5.v[3] * y5.v[3] + pz * pz - n * n) / (n * n);
             if (H > ti->max_H) ti->max_H = H;
         }
@@ -567,34 +603,175 @@ static int integrate_box(const oscene* s, const oopts* o, double r[3], double p[
             double c = fabs(pp[0] * nf[0] + pp[1] * nf[1]) / pabs;
             if (c < ti->min_cos) ti->min_cos = c;
         }
+        double pin[3] = { pp[0], pp[1], pp[2] };
         int through = snell(pp, nf, 1.0);
         u.v[2] = pp[0]; u.v[3] = pp[1];
         if (!through) continue;   /* total internal reflection: stay inside */
         r[0] = u.v[0]; r[1] = u.v[1]; r[2] = z;
         p[0] = pp[0]; p[1] = pp[1]; p[2] = pp[2];
+        for (int i = 0; i < 3; ++i) { p_in[i] = pin[i]; n_face[i] = nf[i]; }
         if (bad) ti->bad_w++;
         return RAY_OK;
     }
 }
 
-/* Full path of one ray from (org, dir) until it escapes to the sky.
-   Returns the ray status; exit position and unit direction in out_*. */
-static int trace_one(const oscene* s, const oopts* o, const double org[3], const double dir[3],
-                     double out_org[3], double out_dir[3], trace_info* ti)
+/* Inside the homogeneous plate (cloak 3) rays are straight (the index is
+   constant, so the acceleration of eq. (11) vanishes): from (r, p) just
+   inside a face, |p| = n_plate, to the nearest of the top face, a side face
+   or the mirror (reflection, as in air).  Faces refract into air by Snell's
+   law or reflect totally.  Same outputs as integrate_box. */
+static int plate_walk(const oscene* s, const oopts* o, double r[3], double p[3], trace_info* ti,
+                      double p_in[3], double n_face[3])
 {
-    double r[3] = { org[0], org[1], org[2] };
-    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-    double p[3] = { dir[0] / nd, dir[1] / nd, dir[2] / nd };
-    memset(ti, 0, sizeof(*ti));
-    ti->min_cos = 1.0;
     for (;;) {
         if (!all_finite(r, 3) || !all_finite(p, 3)) return RAY_NONFINITE;
+        double pa = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        double d[3] = { p[0] / pa, p[1] / pa, p[2] / pa };
+        /* faces ahead, from inside: distances along the unit direction */
+        double tf = INFINITY;
+        int face = EV_NONE;
+        if (d[1] > 0.0) { double t = (s->ytop - r[1]) / d[1]; if (t < tf) { tf = t; face = EV_TOP; } }
+        if (d[0] > 0.0 && isfinite(s->hw)) { double t = (s->hw - r[0]) / d[0]; if (t < tf) { tf = t; face = EV_RIGHT; } }
+        if (d[0] < 0.0 && isfinite(s->hw)) { double t = (-s->hw - r[0]) / d[0]; if (t < tf) { tf = t; face = EV_LEFT; } }
+        double tg = air_contact(s, r, d);
+        if (++ti->events > o->max_events) return RAY_MAX_EVENTS;
+        if (tg <= tf) {
+            for (int i = 0; i < 3; ++i) r[i] += tg * d[i];
+            double E, nx, ny;
+            orc_surface(s, r[0], &E);
+            orc_grating_normal(s, E, &nx, &ny);
+            double c = fabs(d[0] * nx + d[1] * ny);
+            if (c < ti->min_cos) ti->min_cos = c;
+            reflect(p, nx, ny);
+            ti->contacts++;
+            continue;
+        }
+        if (!isfinite(tf)) return RAY_NONFINITE;   /* no face ahead: cannot happen in a finite box */
+        for (int i = 0; i < 3; ++i) r[i] += tf * d[i];
+        if (face == EV_TOP) r[1] = s->ytop;
+        else if (face == EV_RIGHT) r[0] = s->hw;
+        else r[0] = -s->hw;
+        double nf[3];
+        face_normal(face, nf);
+        {
+            double c = fabs(d[0] * nf[0] + d[1] * nf[1]);
+            if (c < ti->min_cos) ti->min_cos = c;
+        }
+        double pin[3] = { p[0], p[1], p[2] };
+        if (!snell(p, nf, 1.0)) continue;   /* total internal reflection */
+        for (int i = 0; i < 3; ++i) { p_in[i] = pin[i]; n_face[i] = nf[i]; }
+        return RAY_OK;
+    }
+}
+
+/* Fresnel reflectance of unpolarised light at a face (Sec. 3: the Fresnel
+   equations), from the normal components of the momentum on the two sides:
+   pn = |p . N| in the medium of index n1 (= n1 cos of incidence) and
+   qn = |q . N| of the transmitted momentum in index n2 (= n2 cos of
+   transmission).  r_s = (pn - qn) / (pn + qn),
+   r_p = (n2^2 pn - n1^2 qn) / (n2^2 pn + n1^2 qn), R = (r_s^2 + r_p^2) / 2. */
+static double fresnel_R(double pn, double qn, double n1, double n2)
+{
+    double rs = (pn - qn) / (pn + qn);
+    double a = n2 * n2 * pn, b = n1 * n1 * qn;
+    double rp = (a - b) / (a + b);
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+/* Backdrop colour for a ray leaving the scene from r along the unit
+   direction d.  backdrop 0: the sky at infinity (gco_sky).  backdrop 1: the
+   plane y = bd_y (the photograph in front of which the camera sits, Sec. 4)
+   patterned with m = 1/2 + 1/2 tanh(K cos(2 pi x / P)) tanh(K cos(2 pi z / P))
+   at the point the ray meets it; a ray that does not rise to the plane sees
+   m = 0.  rgb = Cb + m (Ca - Cb) with the sky's two colours. */
+static void backdrop_rgb(const oscene* s, const double r[3], const double d[3], double rgb[3])
+{
+    if (s->backdrop == 0) { gco_sky(s->K, d, rgb); return; }
+    const double Ca[3] = { 0.95, 0.85, 0.30 }, Cb[3] = { 0.10, 0.20, 0.55 };
+    double m = 0.0;
+    if (d[1] > 0.0 && r[1] < s->bd_y) {
+        double t = (s->bd_y - r[1]) / d[1];
+        double X = r[0] + t * d[0], Zc = r[2] + t * d[2];
+        double a = cos(2.0 * ORC_PI * X / s->bd_P), b = cos(2.0 * ORC_PI * Zc / s->bd_P);
+        double ta = isinf(s->K) ? (a > 0 ? 1.0 : (a < 0 ? -1.0 : 0.0)) : tanh(s->K * a);
+        double tb = isinf(s->K) ? (b > 0 ? 1.0 : (b < 0 ? -1.0 : 0.0)) : tanh(s->K * b);
+        m = 0.5 + 0.5 * ta * tb;
+    }
+    for (int c = 0; c < 3; ++c) rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);
+}
+
+static int trace_path(const oscene* s, const oopts* o, const double r0[3], const double p0[3], int inside,
+                      double w, int split, double rgb[3], double out_org[3], double out_dir[3],
+                      trace_info* ti);
+
+/* A Fresnel-reflected branch from r with momentum q: traced as a path of
+   its own, never split again.  It continues the light path up to the
+   split, so its caps (max_steps, max_events) count from the primary path's
+   counts there; the work it does is added to the branch counters, the
+   primary path's own counts are left as they were. */
+static void run_branch(const oscene* s, const oopts* o, const double r[3], const double q[3], int inside, double w,
+                       double rgb[3], trace_info* ti)
+{
+    trace_info tb = *ti;
+    double so[3], sd[3];
+    int st = trace_path(s, o, r, q, inside, w, 0, rgb, so, sd, &tb);
+    ti->bsteps += tb.steps - ti->steps;
+    ti->brejected += tb.rejected - ti->rejected;
+    ti->branch_events += tb.events - ti->events;
+    if (st != RAY_OK) ti->branch_failed++;
+}
+
+/* One path from (r, p) until it escapes: in air (inside = 0, |p| = 1) or
+   just inside a face of the box (inside = 1, |p| = the box index there).
+   w is the path's weight.  At every face crossing that transmits, Fresnel
+   (fresnel = 1) splits the ray: the path goes on with weight w T, and when
+   `split` is set the reflected part (weight w R) is traced as a path of its
+   own that is never split again -- rays reflected more than once are
+   neglected (Sec. 3); without `split` the reflected part is dropped.  Total
+   internal reflection keeps the whole weight.  On escape w times the
+   backdrop colour is added to rgb (may be NULL); out_org / out_dir receive
+   where and in which direction this path left.  Failures of a reflected
+   branch contribute nothing and do not change the returned status. */
+static int trace_path(const oscene* s, const oopts* o, const double r0[3], const double p0[3], int inside,
+                      double w, int split, double rgb[3], double out_org[3], double out_dir[3],
+                      trace_info* ti)
+{
+    double r[3] = { r0[0], r0[1], r0[2] };
+    double p[3] = { p0[0], p0[1], p0[2] };
+    for (;;) {
+        if (!all_finite(r, 3) || !all_finite(p, 3)) return RAY_NONFINITE;
+        if (inside) {
+            double pin[3], nf[3];
+            int st = (s->cloak == CLOAK_PLATE) ? plate_walk(s, o, r, p, ti, pin, nf)
+                                               : integrate_box(s, o, r, p, ti, pin, nf);
+            if (st != RAY_OK) return st;
+            if (s->fresnel) {
+                double n1 = sqrt(pin[0] * pin[0] + pin[1] * pin[1] + pin[2] * pin[2]);
+                double pn = fabs(pin[0] * nf[0] + pin[1] * nf[1] + pin[2] * nf[2]);
+                double qn = fabs(p[0] * nf[0] + p[1] * nf[1] + p[2] * nf[2]);
+                double R = fresnel_R(pn, qn, n1, 1.0);
+                if (split) {
+                    double q[3];
+                    double pd = pin[0] * nf[0] + pin[1] * nf[1] + pin[2] * nf[2];
+                    for (int i = 0; i < 3; ++i) q[i] = pin[i] - 2.0 * pd * nf[i];
+                    run_branch(s, o, r, q, 1, w * R, rgb, ti);
+                }
+                w *= 1.0 - R;
+            }
+            inside = 0;
+            continue;
+        }
         /* in air: straight line (the acceleration of eq. (11) vanishes) */
         int face;
         double tb = air_box_entry(s, r, p, &face);
         double tg = air_contact(s, r, p);
         if (!isfinite(tb) && !isfinite(tg)) {
             for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
+            if (rgb) {
+                double c[3];
+                backdrop_rgb(s, r, p, c);
+                for (int k = 0; k < 3; ++k) rgb[k] += w * c[k];
+            }
             return RAY_OK;
         }
         if (++ti->events > o->max_events) return RAY_MAX_EVENTS;
@@ -621,12 +798,54 @@ static int trace_one(const oscene* s, const oopts* o, const double org[3], const
             if (c < ti->min_cos) ti->min_cos = c;
         }
         int bad = 0;
-        double n2 = orc_index_raw(s, r[0], r[1], &bad);
+        double n2 = box_index(s, r[0], r[1], &bad);
         if (bad) ti->bad_w++;
+        double pa[3] = { p[0], p[1], p[2] };
         if (!snell(p, nf, n2)) continue;   /* reflected back into air */
-        int st = integrate_box(s, o, r, p, ti);
-        if (st != RAY_OK) return st;
+        if (s->fresnel) {
+            double pn = fabs(pa[0] * nf[0] + pa[1] * nf[1] + pa[2] * nf[2]);
+            double qn = fabs(p[0] * nf[0] + p[1] * nf[1] + p[2] * nf[2]);
+            double R = fresnel_R(pn, qn, 1.0, n2);
+            if (split) {
+                double q[3];
+                double pd = pa[0] * nf[0] + pa[1] * nf[1] + pa[2] * nf[2];
+                for (int i = 0; i < 3; ++i) q[i] = pa[i] - 2.0 * pd * nf[i];
+                run_branch(s, o, r, q, 0, w * R, rgb, ti);
+            }
+            w *= 1.0 - R;
+        }
+        inside = 1;
     }
+}
+
+/* Full path of one ray from (org, dir) until it escapes (the primary path:
+   Fresnel-reflected parts are not followed).  Returns the ray status; exit
+   position and unit direction in out_*. */
+static int trace_one(const oscene* s, const oopts* o, const double org[3], const double dir[3],
+                     double out_org[3], double out_dir[3], trace_info* ti)
+{
+    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double p[3] = { dir[0] / nd, dir[1] / nd, dir[2] / nd };
+    memset(ti, 0, sizeof(*ti));
+    ti->min_cos = 1.0;
+    return trace_path(s, o, org, p, 0, 1.0, 0, NULL, out_org, out_dir, ti);
+}
+
+/* Colour of one camera sample: every path of the sample (the primary one
+   and, with Fresnel, its once-reflected branches) adds its weight times the
+   backdrop.  Returns the primary path's status; a failed sample is black. */
+static int shade_one(const oscene* s, const oopts* o, const double org[3], const double dir[3], double rgb[3],
+                     trace_info* ti)
+{
+    double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double p[3] = { dir[0] / nd, dir[1] / nd, dir[2] / nd };
+    double oo[3], od[3];
+    memset(ti, 0, sizeof(*ti));
+    ti->min_cos = 1.0;
+    rgb[0] = rgb[1] = rgb[2] = 0.0;
+    int st = trace_path(s, o, org, p, 0, 1.0, s->fresnel, rgb, oo, od, ti);
+    if (st != RAY_OK) rgb[0] = rgb[1] = rgb[2] = 0.0;
+    return st;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -655,22 +874,26 @@ static void normalize3(double v[3])
 }
 
 /* Pinhole camera (Sec. 4: a point camera).  Forward f = target - eye, right
-   r = f x y_hat, up u = r x f; square pixels, row 0 at the top; the vertical
-   opening angle is fov_y and the horizontal one follows from the aspect
-   ratio.  Sample s of pixel (i, j) goes through (i + u, j + v) with u, v the
-   jitter values (1/2 without jitter). */
+   r = f x up (up = the camera's up hint, +y when it is zero), image up
+   u = r x f; row 0 at the top.  The vertical opening angle is fov_y; the
+   horizontal one is fov_x, or follows from square pixels when fov_x = 0
+   (the paper's camera: 50 deg horizontally, 42 vertically).  Sample s of
+   pixel (i, j) goes through (i + u, j + v) with u, v the jitter values (1/2
+   without jitter). */
 void gco_camera_ray(const double* cam, uint64_t seed, int i, int j, int s,
                     double org[3], double dir[3])
 {
     double f[3] = { cam[3] - cam[0], cam[4] - cam[1], cam[5] - cam[2] };
     normalize3(f);
-    double r[3] = { -f[2], 0.0, f[0] };   /* f x (0,1,0) */
+    double hint[3] = { cam[12], cam[13], cam[14] };
+    if (hint[0] == 0.0 && hint[1] == 0.0 && hint[2] == 0.0) hint[1] = 1.0;
+    double r[3] = { f[1] * hint[2] - f[2] * hint[1], f[2] * hint[0] - f[0] * hint[2], f[0] * hint[1] - f[1] * hint[0] };
     normalize3(r);
     double up[3] = { r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0] };
     int W = (int)cam[7], H = (int)cam[8], spp = (int)cam[9], jitter = (int)cam[10];
     long scene = (long)cam[11];
     double t = tan(0.5 * cam[6] * ORC_PI / 180.0);
-    double aspect = (double)W / (double)H;
+    double aspect = cam[15] > 0.0 ? tan(0.5 * cam[15] * ORC_PI / 180.0) / t : (double)W / (double)H;
     double du = 0.5, dv = 0.5;
     if (jitter) {
         uint64_t c = ((((uint64_t)scene * (uint64_t)H + (uint64_t)j) * (uint64_t)W + (uint64_t)i) *
@@ -784,7 +1007,8 @@ void gco_trace_rays(const double* scene, const double* opts, long n,
 
 /* Render selected pixels (or all when npix < 0) of a scene.
    rgb: 3 floats per listed pixel (or H x W x 3).  Each pixel is the mean of
-   its spp sky colours; a failed sample contributes black.
+   its spp sample colours (shade_one: the backdrop seen along every path of
+   the sample, weighted); a failed sample contributes black.
    counters[4] (may be NULL): rays, accepted steps, rejected steps, failed. */
 void gco_render_pixels(const double* scene, const double* cam, uint64_t seed, const double* opts,
                        long npix, const long* pix, double* rgb, double* counters, int nthreads)
@@ -805,15 +1029,14 @@ void gco_render_pixels(const double* scene, const double* cam, uint64_t seed, co
         int i = (int)(pidx % W), j = (int)(pidx / W);
         double acc[3] = { 0, 0, 0 };
         for (int smp = 0; smp < spp; ++smp) {
-            double org[3], dir[3], oo[3], od[3], c[3];
+            double org[3], dir[3], c[3];
             trace_info ti;
             gco_camera_ray(cam, seed, i, j, smp, org, dir);
-            int st = trace_one(&s, &o, org, dir, oo, od, &ti);
+            int st = shade_one(&s, &o, org, dir, c, &ti);
             c_rays += 1;
-            c_steps += (double)ti.steps;
-            c_rej += (double)ti.rejected;
+            c_steps += (double)(ti.steps + ti.bsteps);
+            c_rej += (double)(ti.rejected + ti.brejected);
             if (st != RAY_OK) { c_fail += 1; continue; }
-            gco_sky(s.K, od, c);
             for (int k = 0; k < 3; ++k) acc[k] += c[k];
         }
         for (int k = 0; k < 3; ++k) rgb[3 * q + k] = acc[k] / spp;
@@ -1301,7 +1524,7 @@ int gco_render_samples_tan(const double* scene, const double* cam, uint64_t seed
     oopts o;
     load_scene(scene, &s);
     load_opts(opts, &o);
-    if (o.integ != 0 || s.mirror == 1 || !isfinite(s.K)) return -1;
+    if (o.integ != 0 || s.mirror == 1 || !isfinite(s.K) || s.cloak > CLOAK_EQ1 || s.fresnel || s.backdrop) return -1;
     int W = (int)cam[7], H = (int)cam[8], spp = (int)cam[9];
     long total = npix < 0 ? (long)W * H : npix;
 #ifdef _OPENMP
@@ -1352,7 +1575,7 @@ int gco_trace_rays_tan(const double* scene, const double* opts, long n, const do
     oopts o;
     load_scene(scene, &s);
     load_opts(opts, &o);
-    if (o.integ != 0 || s.mirror == 1) return -1;
+    if (o.integ != 0 || s.mirror == 1 || s.cloak > CLOAK_EQ1 || s.fresnel || s.backdrop) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)

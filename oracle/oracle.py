@@ -80,7 +80,9 @@ def _dp(a):
 
 def scene_array(sc):
     return np.array([sc["Lambda"], sc["A"], sc["half_width"], sc["y_top"],
-                     sc["cloak"], sc["mirror"], sc["sky_K"], 0.0], dtype=np.float64)
+                     sc["cloak"], sc["mirror"], sc["sky_K"], sc.get("fresnel", 0),
+                     sc.get("backdrop", 0), sc.get("backdrop_y", 0.0), sc.get("backdrop_period", 1.0)],
+                    dtype=np.float64)
 
 
 def opts_array(o):
@@ -93,7 +95,8 @@ def opts_array(o):
 def camera_array(c):
     return np.array(list(c["eye"]) + list(c["target"]) +
                     [c["fov_y_deg"], c["width"], c["height"], c["spp"], c["jitter"],
-                     c["scene_index"]], dtype=np.float64)
+                     c["scene_index"]] + list(c.get("up", (0.0, 0.0, 0.0))) + [c.get("fov_x_deg", 0.0)],
+                    dtype=np.float64)
 
 
 # --- pointwise functions -----------------------------------------------------

@@ -17,15 +17,33 @@ import numpy as np
 SQRT45 = math.sqrt(45.0)
 
 
-def scene(A=0.1, half_width=2.0, y_top=1.5, Lambda=1.0, cloak=1, mirror=0, sky_K=16.0):
+# cloak kinds: none, eq. (1), eq. (1) divided by its minimum n_min = 1 / (1 + A k)
+# (the referenced cloak of Sec. 4), homogeneous dielectric plate of index 1 / n_min
+CLOAK_NONE, CLOAK_EQ1, CLOAK_REFERENCED, CLOAK_PLATE = 0, 1, 2, 3
+# backdrops: the sky at infinity, or a patterned plane (the photograph)
+BACKDROP_SKY, BACKDROP_PLANE = 0, 1
+
+
+def scene(A=0.1, half_width=2.0, y_top=1.5, Lambda=1.0, cloak=1, mirror=0, sky_K=16.0, fresnel=0,
+          backdrop=BACKDROP_SKY, backdrop_y=0.0, backdrop_period=1.0):
     return dict(Lambda=float(Lambda), A=float(A), half_width=float(half_width),
-                y_top=float(y_top), cloak=int(cloak), mirror=int(mirror), sky_K=float(sky_K))
+                y_top=float(y_top), cloak=int(cloak), mirror=int(mirror), sky_K=float(sky_K),
+                fresnel=int(fresnel), backdrop=int(backdrop), backdrop_y=float(backdrop_y),
+                backdrop_period=float(backdrop_period))
 
 
 def reference_scene(sc):
     """Flat mirror at y = 0 in air (no grating, no cloak)."""
     r = dict(sc)
     r.update(cloak=0, mirror=1)
+    return r
+
+
+def plate_reference_scene(sc):
+    """Flat mirror at y = 0 under a homogeneous dielectric plate of index
+    1 / n_min = 1 + A k filling the cloak's box (Sec. 4, Figs. 5-7 (a))."""
+    r = dict(sc)
+    r.update(cloak=CLOAK_PLATE, mirror=1)
     return r
 
 
@@ -37,11 +55,13 @@ def uncloaked_scene(sc):
 
 
 def camera(width, height, spp=1, jitter=False, seed=0, eye=(0.0, 3.0, 6.0),
-           target=(0.0, 0.0, 0.0), fov_y_deg=40.0, scene_index=0):
+           target=(0.0, 0.0, 0.0), fov_y_deg=40.0, scene_index=0, up=(0.0, 0.0, 0.0), fov_x_deg=0.0):
+    """Pinhole camera; up = (0, 0, 0) means +y; fov_x_deg = 0 means square
+    pixels (the horizontal opening from the vertical one and the aspect)."""
     return dict(eye=tuple(float(v) for v in eye), target=tuple(float(v) for v in target),
                 fov_y_deg=float(fov_y_deg), width=int(width), height=int(height),
                 spp=int(spp), jitter=int(bool(jitter)), seed=int(seed),
-                scene_index=int(scene_index))
+                scene_index=int(scene_index), up=tuple(float(v) for v in up), fov_x_deg=float(fov_x_deg))
 
 
 def orbit_eye(az_deg, el_deg, R):
