@@ -414,13 +414,22 @@ static double air_contact(const oscene* s, const double r[3], const double d[3])
         if (y0 > A || y0 < -A || dx == 0.0) return INFINITY;
         t1 = s->L / fabs(dx);
     }
+    if (dx == 0.0) {
+        /* a vertical line x = x0 meets the trochoid of eq. (2) only at
+           (x0, S(x0)): a contact when it moves down onto that point */
+        double S = orc_surface(s, x0, NULL);
+        if (dy < 0.0 && y0 > S) return (S - y0) / dy;
+        return INFINITY;
+    }
     double L = fabs(dy) + fabs(dx) * s->e / sqrt(1.0 - s->e * s->e);
     double t = t0, tprev = t0;
     /* a ray that starts on the surface (just reflected) is not in contact */
     int at_origin = (t0 == 0.0);
     for (long it = 0; it < 100000000L; ++it) {
         double g = y0 + t * dy - orc_surface(s, x0 + t * dx, NULL);
-        if (g <= 0.0 && !(at_origin && t == t0)) {
+        /* a rising ray leaves the band at y = A >= S(x): there g >= 0
+           exactly, so a g <= 0 at that end is rounding, not a crossing */
+        if (g <= 0.0 && !(at_origin && t == t0) && !(dy > 0.0 && t >= t1)) {
             if (t == t0) return t0;   /* touches the surface where it enters the band */
             double lo = tprev, hi = t;
             for (int b = 0; b < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++b) {
