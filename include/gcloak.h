@@ -63,25 +63,63 @@ typedef enum {
     GC_RAY_STEP_UNDERFLOW = 4   /* DOPRI5 step fell below h_min */
 } gc_ray_status;
 
+/* What fills the box |x| <= half_width, grating < y <= y_top (n = 1 outside):
+ *   GC_CLOAK_NONE        nothing (the box does not exist);
+ *   GC_CLOAK_EQ1         the index of eq. (1) (Sec. 2);
+ *   GC_CLOAK_REFERENCED  eq. (1) divided by its minimum n_min = 1 / (1 + A k),
+ *                        so that no index is below the air's (Sec. 4,
+ *                        Figs. 5-7 (c));
+ *   GC_CLOAK_PLATE       a homogeneous dielectric plate of index
+ *                        1 / n_min = 1 + A k (Sec. 4: with the flat mirror,
+ *                        the ideal image of the referenced cloak, Figs. 5-7
+ *                        (a); with the grating, Figs. 5-7 (b)). */
+typedef enum { GC_CLOAK_NONE = 0, GC_CLOAK_EQ1 = 1, GC_CLOAK_REFERENCED = 2, GC_CLOAK_PLATE = 3 } gc_cloak;
+
+/* What a ray that leaves the scene shows:
+ *   GC_BACKDROP_SKY    a sky at infinity, an 8 x 8 latitude-longitude
+ *                      checkerboard smoothed by tanh of sharpness sky_K;
+ *   GC_BACKDROP_PLANE  the plane y = backdrop_y (the photograph in front of
+ *                      which the camera sits, Sec. 4), patterned with
+ *                      m = 1/2 + 1/2 tanh(sky_K cos(2 pi x / P))
+ *                      tanh(sky_K cos(2 pi z / P)), P = backdrop_period, at
+ *                      the point the ray meets it; a ray that does not rise
+ *                      to the plane sees m = 0.
+ * Both colour a ray Cb + m (Ca - Cb), Ca = (0.95, 0.85, 0.30),
+ * Cb = (0.10, 0.20, 0.55). */
+typedef enum { GC_BACKDROP_SKY = 0, GC_BACKDROP_PLANE = 1 } gc_backdrop;
+
 /* Scene (Sec. 2).  Grating x = xi - A sin(k xi), y = A cos(k xi) (eq. (2)),
- * infinite in x and z.  With cloak = 1 the index of eq. (1) fills the box
- * |x| <= half_width, grating < y <= y_top (n = 1 elsewhere); half_width and
+ * infinite in x and z; the box holds `cloak` (gc_cloak); half_width and
  * y_top may be +inf.  mirror = 1 replaces the grating by the flat mirror
- * y = 0 (only with cloak = 0: the reference image).  sky_K is the sky's
- * tanh sharpness (+inf: hard squares). */
+ * y = 0 (with cloak = GC_CLOAK_NONE: the reference image; with the plate:
+ * the plate reference).  sky_K is the backdrop's tanh sharpness (+inf:
+ * hard squares).  fresnel = 0: the box faces refract by Snell's law (total
+ * internal reflection where it allows no transmission), weight 1;
+ * fresnel = 1: Fresnel-weighted faces (Sec. 3): the primary ray goes on with
+ * the transmitted fraction T of unpolarised light at each face crossing, and
+ * the reflected fraction R starts a branch that is traced to its end without
+ * further splitting (rays reflected more than once are neglected); the
+ * sample's colour sums the weighted backdrop of all its paths (gc_render in
+ * FP64 only). */
 typedef struct {
     double Lambda;
     double A;
     double half_width;
     double y_top;
-    int32_t cloak;
+    int32_t cloak;          /* gc_cloak */
     int32_t mirror;
     double sky_K;
+    int32_t fresnel;
+    int32_t backdrop;       /* gc_backdrop */
+    double backdrop_y;
+    double backdrop_period;
 } gc_scene;
 
-/* Pinhole camera (Sec. 4: a virtual point camera).  World up is +y; right
- * = forward x up; square pixels, row 0 at the top; fov_y_deg is the full
- * vertical opening angle.  Sample s of pixel (i, j) passes through
+/* Pinhole camera (Sec. 4: a virtual point camera).  right = forward x up,
+ * image up = right x forward, with `up` the up hint (all zero: +y); row 0
+ * at the top.  fov_y_deg is the full vertical opening angle; fov_x_deg the
+ * horizontal one, or 0 for square pixels (the paper's camera opens 50 deg
+ * horizontally and 42 vertically).  Sample s of pixel (i, j) passes through
  * (i + u, j + v), with u, v the SplitMix64 outputs number 2c and 2c + 1
  * (c = ((scene_index H + j) W + i) spp + s) of the generator seeded with
  * `seed`, each mapped to [0,1) by its top 53 bits; u = v = 1/2 when
@@ -96,6 +134,8 @@ typedef struct {
     int32_t jitter;
     uint64_t seed;
     int64_t scene_index;
+    double up[3];
+    double fov_x_deg;
 } gc_camera;
 
 /* Integration options.  RK4: classical 4-stage, fixed step h.  DOPRI5:
@@ -258,7 +298,7 @@ typedef struct {
     double dir_tol;        /* default 1e-4 rad */
     double cc_tol;         /* default 1e-4 */
     double max_changed;    /* default 0.01 */
-    double ref_rtol;       /* default 1e-8 */
+    double ref_rtol;       /* default 1e-10 */
     int32_t reps;          /* default 2 */
     int32_t tune_sched;    /* default 1 */
 } gc_autotune_opts;

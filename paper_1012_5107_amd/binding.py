@@ -32,13 +32,15 @@ class GcError(RuntimeError):
 class Scene(ctypes.Structure):
     _fields_ = [("Lambda", ctypes.c_double), ("A", ctypes.c_double), ("half_width", ctypes.c_double),
                 ("y_top", ctypes.c_double), ("cloak", ctypes.c_int32), ("mirror", ctypes.c_int32),
-                ("sky_K", ctypes.c_double)]
+                ("sky_K", ctypes.c_double), ("fresnel", ctypes.c_int32), ("backdrop", ctypes.c_int32),
+                ("backdrop_y", ctypes.c_double), ("backdrop_period", ctypes.c_double)]
 
 
 class Camera(ctypes.Structure):
     _fields_ = [("eye", ctypes.c_double * 3), ("target", ctypes.c_double * 3), ("fov_y_deg", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
-                ("jitter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("scene_index", ctypes.c_int64)]
+                ("jitter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("scene_index", ctypes.c_int64),
+                ("up", ctypes.c_double * 3), ("fov_x_deg", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -181,7 +183,8 @@ def _check(st):
 
 def make_scene(sc):
     return Scene(sc["Lambda"], sc["A"], sc["half_width"], sc["y_top"], int(sc["cloak"]), int(sc["mirror"]),
-                 sc["sky_K"])
+                 sc["sky_K"], int(sc.get("fresnel", 0)), int(sc.get("backdrop", 0)), float(sc.get("backdrop_y", 0.0)),
+                 float(sc.get("backdrop_period", 1.0)))
 
 
 def make_camera(c):
@@ -193,6 +196,8 @@ def make_camera(c):
     cam.jitter = int(c["jitter"])
     cam.seed = c["seed"]
     cam.scene_index = c.get("scene_index", 0)
+    cam.up[:] = list(c.get("up", (0.0, 0.0, 0.0)))
+    cam.fov_x_deg = c.get("fov_x_deg", 0.0)
     return cam
 
 

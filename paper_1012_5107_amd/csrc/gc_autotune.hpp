@@ -118,7 +118,11 @@ void gc_default_autotune_opts(gc_autotune_opts* at)
     at->dir_tol = 1e-4;
     at->cc_tol = 1e-4;
     at->max_changed = 0.01;
-    at->ref_rtol = 1e-8;
+    // a converged reference: the C0 of a high-amplitude scene moves by up
+    // to ~1e-4 between FP64 solves at rtol 1e-8 and 1e-10 (a few dozen
+    // samples trapped near the crests flip between escaping and the step
+    // cap), and by ~5e-6 between 1e-10 solves at step caps 0.02 and 0.005
+    at->ref_rtol = 1e-10;
     at->reps = 2;
     at->tune_sched = 1;
 }

@@ -20,6 +20,7 @@ namespace gc {
 // per-scene FP32 constants of the hot loop
 struct Sc32 {
     float L, invL, k, invk, ne, mkl2e, ybp, wfb2;
+    float kacc;   // k times the box index multiplier squared (the acceleration's scale)
 };
 
 
@@ -34,6 +35,7 @@ __device__ __forceinline__ Sc32 make_sc32(const SceneDev& s, double wfb2)
     c.mkl2e = (float)(-s.k * kLog2e);
     c.ybp = (float)s.ybp;
     c.wfb2 = (float)wfb2;
+    c.kacc = (float)(s.k * s.nsc2);
     return c;
 }
 
@@ -72,7 +74,7 @@ __device__ __forceinline__ float accel32(const Sc32& c, Rhs32& r)
     float d2 = norm2(D);
     float rr = __builtin_amdgcn_rcpf(d2);
     cx<float> t = conjg(r.W) * (D * D);
-    float kr3 = c.k * rr * rr * rr;
+    float kr3 = c.kacc * rr * rr * rr;
     r.ax = -kr3 * t.im;
     r.ay = kr3 * t.re;
     cx<float> u = r.W * conjg(D);

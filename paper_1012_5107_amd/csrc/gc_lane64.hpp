@@ -455,7 +455,8 @@ __device__ inline double locate_event(const SceneDev& s, const OptsDev& o, int e
 // out_z advanced accordingly).  *dtau receives the tau advanced.
 __device__ inline bool handle_events64(const SceneDev& s, const OptsDev& o, St64& u, Rhs64& r1, double pz,
                                        double h, const St64& ue, const Rhs64& re, double* dtau,
-                                       double out_p[3], double* min_cos)
+                                       double out_p[3], double* min_cos, double* pin_out = nullptr,
+                                       int* face_out = nullptr)
 {
     double best = 2.0;
     int hit = -1;
@@ -492,6 +493,7 @@ __device__ inline bool handle_events64(const SceneDev& s, const OptsDev& o, St64
     double p[3] = {u.px, u.py, pz};
     double pa = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
     *min_cos = fmin(*min_cos, fabs(p[0] * nf[0] + p[1] * nf[1]) / pa);
+    const double pin[3] = {p[0], p[1], p[2]};
     bool through = snell(p, nf, 1.0);
     u.px = p[0];
     u.py = p[1];
@@ -499,6 +501,8 @@ __device__ inline bool handle_events64(const SceneDev& s, const OptsDev& o, St64
     out_p[0] = p[0];
     out_p[1] = p[1];
     out_p[2] = p[2];
+    if (pin_out) { pin_out[0] = pin[0]; pin_out[1] = pin[1]; pin_out[2] = pin[2]; }
+    if (face_out) *face_out = hit;
     return true;
 }
 
@@ -518,7 +522,8 @@ struct Box64 {
 // point where the ray left the box and its momentum in air.  On SO_FAIL
 // *status holds the reason.
 __device__ inline int box_step64(const SceneDev& s, const OptsDev& o, Box64& b, LaneCount& cnt,
-                                 double* min_cos, double r_out[3], double p_out[3], int* status)
+                                 double* min_cos, double r_out[3], double p_out[3], int* status,
+                                 double* pin_out = nullptr, int* face_out = nullptr)
 {
     St64 ue;
     Rhs64 re;
@@ -559,7 +564,7 @@ __device__ inline int box_step64(const SceneDev& s, const OptsDev& o, Box64& b, 
         return SO_INSIDE;
     }
     double dtau, pout[3];
-    bool out = handle_events64(s, o, b.u, b.r1, b.pz, h, ue, re, &dtau, pout, min_cos);
+    bool out = handle_events64(s, o, b.u, b.r1, b.pz, h, ue, re, &dtau, pout, min_cos, pin_out, face_out);
     b.z += b.pz * dtau;
     b.h = (o.integ == 0) ? o.h : hnext;
     if (++cnt.events > o.max_events) { *status = RS_MAX_EVENTS; return SO_FAIL; }
@@ -587,15 +592,17 @@ __device__ inline Box64 box_enter64(const SceneDev& s, const OptsDev& o, const d
 }
 
 // Integrate inside the box from (r, p) just inside a face.  On RS_OK r, p
-// hold the exit point and the momentum in air.
+// hold the exit point and the momentum in air (pin_out, face_out: the
+// momentum just inside the exit face and the face, 0 top, 1 right, 2 left).
 __device__ inline int integrate_box64(const SceneDev& s, const OptsDev& o, double r[3], double p[3],
-                                      cx<double> W, LaneCount& cnt, double* min_cos)
+                                      cx<double> W, LaneCount& cnt, double* min_cos, double* pin_out = nullptr,
+                                      int* face_out = nullptr)
 {
     Box64 b = box_enter64(s, o, r, p, W);
     for (;;) {
         if (cnt.steps >= o.max_steps) return RS_MAX_STEPS;
         int st = RS_OK;
-        int so = box_step64(s, o, b, cnt, min_cos, r, p, &st);
+        int so = box_step64(s, o, b, cnt, min_cos, r, p, &st, pin_out, face_out);
         if (so == SO_FAIL) return st;
         if (so == SO_EXITED) return RS_OK;
     }
@@ -609,7 +616,8 @@ enum AirOutcome { AO_ESCAPED = 0, AO_ENTERED = 1, AO_FAIL = 2 };
 // face, p refracted inside, *w_in = W0 at r).  The acceleration of eq. (11)
 // vanishes outside the cloak.
 __device__ inline int air_walk(const SceneDev& s, const OptsDev& o, double r[3], double p[3], LaneCount& cnt,
-                               double* min_cos, int* status, cx<double>* w_in)
+                               double* min_cos, int* status, cx<double>* w_in, double* pair_out = nullptr,
+                               int* face_out = nullptr)
 {
     // highest point of the metal: a ray that enters through the top face
     // above it has met no metal on the way
@@ -648,11 +656,88 @@ __device__ inline int air_walk(const SceneDev& s, const OptsDev& o, double r[3],
         else if (face == 1) { r[0] = s.hw; nf[0] = -1.0; }
         else { r[0] = -s.hw; nf[0] = 1.0; }
         *min_cos = fmin(*min_cos, fabs(p[0] * nf[0] + p[1] * nf[1]));
-        cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
-        double n2 = 1.0 / sqrt(norm2(mk(1.0 + W.re, W.im)));
+        // the box index at the entry point: eq. (1) (times 1 / n_min for the
+        // referenced cloak) or the plate's
+        cx<double> W = {0.0, 0.0};
+        double n2 = s.nplate;
+        if (s.cloak != CK_PLATE) {
+            W = w0_cold(zarg64(s, r[0], r[1]));
+            n2 = s.nsc / sqrt(norm2(mk(1.0 + W.re, W.im)));
+        }
+        const double pa[3] = {p[0], p[1], p[2]};
         if (!snell(p, nf, n2)) continue;
         *w_in = W;
+        if (pair_out) { pair_out[0] = pa[0]; pair_out[1] = pa[1]; pair_out[2] = pa[2]; }
+        if (face_out) *face_out = face;
         return AO_ENTERED;
+    }
+}
+
+// Straight flight inside the homogeneous plate (CK_PLATE: the index is
+// constant, so the acceleration of eq. (11) vanishes) from (r, p) just
+// inside a face, |p| = nplate: to the top or a side face ahead, or to the
+// mirror (reflection, as in air).  A face refracts into air by Snell's law or
+// reflects totally.  On RS_OK r, p hold the exit point and the momentum in
+// air (pin_out, face_out as for integrate_box64).
+__device__ inline int plate_walk64(const SceneDev& s, const OptsDev& o, double r[3], double p[3], LaneCount& cnt,
+                                   double* min_cos, double* pin_out = nullptr, int* face_out = nullptr)
+{
+    for (;;) {
+        if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(p[0]) && isfinite(p[1]) &&
+              isfinite(p[2])))
+            return RS_NONFINITE;
+        const double pa = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        const double d[3] = {p[0] / pa, p[1] / pa, p[2] / pa};
+        double tf = kInf;
+        int face = -1;
+        if (d[1] > 0.0) { const double t = (s.ytop - r[1]) / d[1]; if (t < tf) { tf = t; face = 0; } }
+        if (d[0] > 0.0 && isfinite(s.hw)) { const double t = (s.hw - r[0]) / d[0]; if (t < tf) { tf = t; face = 1; } }
+        if (d[0] < 0.0 && isfinite(s.hw)) { const double t = (-s.hw - r[0]) / d[0]; if (t < tf) { tf = t; face = 2; } }
+        double xi = 0.0;
+        const double tg = air_contact(s, r, d, &xi);
+        if (++cnt.events > o.max_events) return RS_MAX_EVENTS;
+        if (tg <= tf) {
+            for (int i = 0; i < 3; ++i) r[i] += tg * d[i];
+            double nx = 0.0, ny = 1.0;
+            if (!(s.mirror == 1 || s.A == 0.0)) {
+                double sn, c;
+                sincos(s.k * xi, &sn, &c);
+                nx = s.e * sn;
+                ny = 1.0 - s.e * c;
+                const double inv = 1.0 / sqrt(nx * nx + ny * ny);
+                nx *= inv;
+                ny *= inv;
+            }
+            *min_cos = fmin(*min_cos, fabs(d[0] * nx + d[1] * ny));
+            reflect2(p[0], p[1], nx, ny);
+            continue;
+        }
+        if (!(tf < kInf)) return RS_NONFINITE;
+        for (int i = 0; i < 3; ++i) r[i] += tf * d[i];
+        double nf[3] = {0.0, 0.0, 0.0};
+        if (face == 0) { r[1] = s.ytop; nf[1] = 1.0; }
+        else if (face == 1) { r[0] = s.hw; nf[0] = 1.0; }
+        else { r[0] = -s.hw; nf[0] = -1.0; }
+        *min_cos = fmin(*min_cos, fabs(d[0] * nf[0] + d[1] * nf[1]));
+        const double pin[3] = {p[0], p[1], p[2]};
+        if (!snell(p, nf, 1.0)) continue;   // total internal reflection
+        if (pin_out) { pin_out[0] = pin[0]; pin_out[1] = pin[1]; pin_out[2] = pin[2]; }
+        if (face_out) *face_out = face;
+        return RS_OK;
+    }
+}
+
+// The walk through air for the pipeline's FP64 kernels: the plate (straight
+// flights) is crossed in place, so that a plate scene never enters the
+// in-box queues; returns as air_walk does.
+__device__ inline int air_walk_plates(const SceneDev& s, const OptsDev& o, double r[3], double p[3], LaneCount& cnt,
+                                      double* min_cos, int* status, cx<double>* w_in)
+{
+    for (;;) {
+        const int ao = air_walk(s, o, r, p, cnt, min_cos, status, w_in);
+        if (ao != AO_ENTERED || s.cloak != CK_PLATE) return ao;
+        const int st = plate_walk64(s, o, r, p, cnt, min_cos);
+        if (st != RS_OK) { *status = st; return AO_FAIL; }
     }
 }
 
@@ -673,8 +758,131 @@ __device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const dou
             for (int i = 0; i < 3; ++i) { out_org[i] = r[i]; out_dir[i] = p[i]; }
             return RS_OK;
         }
-        st = integrate_box64(s, o, r, p, W, cnt, min_cos);
+        st = (s.cloak == CK_PLATE) ? plate_walk64(s, o, r, p, cnt, min_cos) : integrate_box64(s, o, r, p, W, cnt, min_cos);
         if (st != RS_OK) return st;
+    }
+}
+
+// Fresnel reflectance of unpolarised light at a face (Sec. 3: the Fresnel
+// equations), from the normal components of the momentum on the two sides:
+// pn = |p . N| in the medium of index n1 (= n1 cos of incidence), qn = |q . N|
+// of the transmitted momentum in index n2 (= n2 cos of transmission).
+__device__ inline double fresnel_R(double pn, double qn, double n1, double n2)
+{
+    const double rs = (pn - qn) / (pn + qn);
+    const double a = n2 * n2 * pn, b = n1 * n1 * qn;
+    const double rp = (a - b) / (a + b);
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+// R at a crossing of the face with outward normal of index `face` (0 top,
+// 1 right, 2 left): p1 the momentum on the incoming side, p2 the
+// transmitted one; and p1 reflected about the face into refl.
+__device__ inline double crossing_R(int face, const double p1[3], const double p2[3], double refl[3])
+{
+    double nf[3] = {0.0, 0.0, 0.0};
+    if (face == 0) nf[1] = 1.0; else if (face == 1) nf[0] = 1.0; else nf[0] = -1.0;
+    const double n1 = sqrt(p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2]);
+    const double n2 = sqrt(p2[0] * p2[0] + p2[1] * p2[1] + p2[2] * p2[2]);
+    const double d1 = p1[0] * nf[0] + p1[1] * nf[1] + p1[2] * nf[2];
+    const double d2 = p2[0] * nf[0] + p2[1] * nf[1] + p2[2] * nf[2];
+    for (int i = 0; i < 3; ++i) refl[i] = p1[i] - 2.0 * d1 * nf[i];
+    return fresnel_R(fabs(d1), fabs(d2), n1, n2);
+}
+
+// Colour of one camera sample in FP64 (the plain path): the backdrop seen
+// along the primary path, weighted by the Fresnel transmissions of its face
+// crossings, plus, with Fresnel, the path reflected at each of those
+// crossings (weight the primary's times R), traced to its end without
+// further splits -- rays reflected more than once are neglected (Sec. 3).
+// A branch continues the light path up to its crossing, so its caps count
+// from the primary's counts there; it runs when it is created, the primary
+// waiting in `held`.  Returns the primary's status (a failed sample is
+// black); a branch that fails adds nothing.  cnt receives the work of all
+// paths.
+__device__ inline int shade_ray64(const SceneDev& s, const OptsDev& o, const double org[3], const double dir[3],
+                                  LaneCount& cnt, double rgb[3])
+{
+    struct Leg {
+        double r[3], p[3];
+        cx<double> W;      // W0 at r for a leg that starts inside (eq. (1) scenes)
+        double w;
+        bool inside;
+        LaneCount pc;      // the path's own counts (its caps)
+    };
+    const double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    Leg cur = {{org[0], org[1], org[2]}, {dir[0] / nd, dir[1] / nd, dir[2] / nd}, {0.0, 0.0}, 1.0, false,
+               {0, 0, 0, 0}};
+    Leg held;
+    bool branch = false;   // cur is a reflected branch (the primary is held)
+    rgb[0] = rgb[1] = rgb[2] = 0.0;
+    long long work_steps = 0, work_rej = 0;
+    int work_ev = 0;
+    for (;;) {
+        double mc = 1.0;
+        int st = RS_OK;
+        bool ended = false, crossed = false;
+        double p1[3], p2[3];
+        int face = 0;
+        const LaneCount before = cur.pc;
+        if (!cur.inside) {
+            const int ao = air_walk(s, o, cur.r, cur.p, cur.pc, &mc, &st, &cur.W, p1, &face);
+            if (ao == AO_FAIL) {
+                ended = true;
+            } else if (ao == AO_ESCAPED) {
+                double c[3];
+                backdrop_rgb64(s, cur.r, cur.p, c);
+                for (int k = 0; k < 3; ++k) rgb[k] += cur.w * c[k];
+                ended = true;
+            } else {
+                for (int i = 0; i < 3; ++i) p2[i] = cur.p[i];
+                cur.inside = true;
+                crossed = true;
+            }
+        } else {
+            st = (s.cloak == CK_PLATE) ? plate_walk64(s, o, cur.r, cur.p, cur.pc, &mc, p1, &face)
+                                       : integrate_box64(s, o, cur.r, cur.p, cur.W, cur.pc, &mc, p1, &face);
+            if (st != RS_OK) {
+                ended = true;
+            } else {
+                for (int i = 0; i < 3; ++i) p2[i] = cur.p[i];
+                cur.inside = false;
+                crossed = true;
+            }
+        }
+        work_steps += cur.pc.steps - before.steps;
+        work_rej += cur.pc.rejected - before.rejected;
+        work_ev += cur.pc.events - before.events;
+        if (ended) {
+            if (!branch) {
+                if (st != RS_OK) rgb[0] = rgb[1] = rgb[2] = 0.0;
+                cnt.steps += work_steps;
+                cnt.rejected += work_rej;
+                cnt.events += work_ev;
+                return st;
+            }
+            cur = held;        // the branch is done: back to the primary
+            branch = false;
+            continue;
+        }
+        if (crossed && s.fresnel) {
+            double refl[3];
+            const double R = crossing_R(face, p1, p2, refl);
+            if (!branch) {
+                held = cur;
+                held.w = cur.w * (1.0 - R);
+                // the reflected path stays on the incoming side of the face
+                Leg b = cur;
+                b.w = cur.w * R;
+                b.inside = !cur.inside;
+                for (int i = 0; i < 3; ++i) b.p[i] = refl[i];
+                if (b.inside && s.cloak != CK_PLATE) b.W = w0_cold(zarg64(s, b.r[0], b.r[1]));
+                cur = b;
+                branch = true;
+            } else {
+                cur.w *= 1.0 - R;
+            }
+        }
     }
 }
 

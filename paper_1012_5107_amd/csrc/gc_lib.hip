@@ -91,6 +91,7 @@ __global__ void __launch_bounds__(256) k_trace_rays64(SceneDev s, OptsDev o, lon
     add_counters(cnt, c_rays, c_steps, c_rej, c_ev, 0, c_fail);
 }
 
+template <bool FRESNEL>
 __global__ void __launch_bounds__(256) k_render64(SceneDev s, CamDev cam, OptsDev o, float* rgb,
                                                   DevCounters* cnt)
 {
@@ -101,18 +102,23 @@ __global__ void __launch_bounds__(256) k_render64(SceneDev s, CamDev cam, OptsDe
         int i = (int)(pix % cam.W), j = (int)(pix / cam.W);
         double acc[3] = {0, 0, 0};
         for (int smp = 0; smp < cam.spp; ++smp) {
-            double d[3], oo[3], od[3];
+            double d[3], c[3];
             camera_dir(cam, i, j, smp, d);
             LaneCount lc = {0, 0, 0, 0};
-            double mc = 1.0;
-            int st = trace_ray64(s, o, cam.eye, d, oo, od, lc, &mc);
+            int st;
+            if (FRESNEL) {
+                // every path of the sample: the primary and its reflected branches
+                st = shade_ray64(s, o, cam.eye, d, lc, c);
+            } else {
+                double oo[3], od[3], mc = 1.0;
+                st = trace_ray64(s, o, cam.eye, d, oo, od, lc, &mc);
+                if (st == RS_OK) backdrop_rgb64(s, oo, od, c);
+            }
             c_rays++;
             c_steps += lc.steps;
             c_rej += lc.rejected;
             c_ev += lc.events;
             if (st != RS_OK) { c_fail++; continue; }
-            double c[3];
-            sky_rgb<double>(s.K, od, c);
             for (int a = 0; a < 3; ++a) acc[a] += c[a];
         }
         for (int a = 0; a < 3; ++a) rgb[3 * pix + a] = (float)(acc[a] / cam.spp);
@@ -121,10 +127,11 @@ __global__ void __launch_bounds__(256) k_render64(SceneDev s, CamDev cam, OptsDe
 }
 
 // Reference image: flat mirror y = 0 in air.  A downward ray leaves with
-// d_y negated; an upward one sees the sky directly.  The camera ray and the
-// sky's angles are FP64, its tanh FP32 (sky_rgb_image); the same reference
-// serves both precisions of the cloaked image.
-__global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float* rgb, DevCounters* cnt)
+// d_y negated from its reflection point; an upward one sees the backdrop
+// directly.  The camera ray and the backdrop's angles or landing point are
+// FP64, its tanh FP32 (backdrop_rgb_image); the same reference serves both
+// precisions of the cloaked image.
+__global__ void __launch_bounds__(256) k_render_flat(CamDev cam, SceneDev s, float* rgb, DevCounters* cnt)
 {
     const long long npx = (long long)cam.W * cam.H;
     unsigned long long c_rays = 0, c_ev = 0;
@@ -136,11 +143,19 @@ __global__ void __launch_bounds__(256) k_render_flat(CamDev cam, double K, float
         const int i = (int)(pix % cam.W), j = (int)(pix / cam.W);
         double acc[3] = {0, 0, 0};
         for (int smp = 0; smp < cam.spp; ++smp) {
-            double d[3];
+            double d[3], r[3] = {cam.eye[0], cam.eye[1], cam.eye[2]};
             camera_dir(cam, i, j, smp, d);
-            if (d[1] < 0.0 && cam.eye[1] > 0.0) { d[1] = -d[1]; c_ev++; }
+            if (d[1] < 0.0 && cam.eye[1] > 0.0) {
+                // the reflection point on y = 0 (the backdrop plane needs it)
+                const double t = -cam.eye[1] / d[1];
+                r[0] += t * d[0];
+                r[1] = 0.0;
+                r[2] += t * d[2];
+                d[1] = -d[1];
+                c_ev++;
+            }
             float c[3];
-            sky_rgb_image(K, d, c);
+            backdrop_rgb_image(s, r, d, c);
             for (int a = 0; a < 3; ++a) acc[a] += (double)c[a];
         }
         c_rays += cam.spp;
@@ -289,10 +304,16 @@ static gc_status make_scene(const gc_scene* sc, SceneDev* s)
     if (sc->A * k >= 1.0) return fail(GC_EDOMAIN, "A k = %g >= 1: W0 is not single-valued on the cloak", sc->A * k);
     if (std::isnan(sc->half_width) || !(sc->half_width > 0)) return fail(GC_EINVAL, "half_width must be > 0");
     if (std::isnan(sc->y_top) || !(sc->y_top > sc->A)) return fail(GC_EINVAL, "y_top must exceed A");
-    if (sc->cloak != 0 && sc->cloak != 1) return fail(GC_EINVAL, "cloak must be 0 or 1");
+    if (sc->cloak < GC_CLOAK_NONE || sc->cloak > GC_CLOAK_PLATE) return fail(GC_EINVAL, "cloak must be 0, 1, 2 or 3");
     if (sc->mirror != 0 && sc->mirror != 1) return fail(GC_EINVAL, "mirror must be 0 or 1");
-    if (sc->mirror == 1 && sc->cloak == 1) return fail(GC_EUNSUPPORTED, "the flat mirror is only provided without cloak");
+    if (sc->mirror == 1 && (sc->cloak == GC_CLOAK_EQ1 || sc->cloak == GC_CLOAK_REFERENCED))
+        return fail(GC_EUNSUPPORTED, "the flat mirror is only provided without cloak or under the plate");
     if (std::isnan(sc->sky_K) || !(sc->sky_K > 0)) return fail(GC_EINVAL, "sky_K must be > 0");
+    if (sc->fresnel != 0 && sc->fresnel != 1) return fail(GC_EINVAL, "fresnel must be 0 or 1");
+    if (sc->backdrop != GC_BACKDROP_SKY && sc->backdrop != GC_BACKDROP_PLANE) return fail(GC_EINVAL, "backdrop must be 0 or 1");
+    if (sc->backdrop == GC_BACKDROP_PLANE &&
+        !(std::isfinite(sc->backdrop_y) && std::isfinite(sc->backdrop_period) && sc->backdrop_period > 0))
+        return fail(GC_EINVAL, "the backdrop plane needs a finite backdrop_y and backdrop_period > 0");
     s->L = sc->Lambda;
     s->A = sc->A;
     s->hw = sc->half_width;
@@ -306,6 +327,15 @@ static gc_status make_scene(const gc_scene* sc, SceneDev* s)
     s->S_hw = (sc->mirror == 0 && std::isfinite(sc->half_width)) ? host_kepler_height(sc->A, sc->Lambda, sc->half_width) : 0.0;
     s->cloak = sc->cloak;
     s->mirror = sc->mirror;
+    // Sec. 4: the referenced cloak divides every index of eq. (1) by its
+    // minimum n_min = 1 / (1 + A k); the plate has index 1 / n_min
+    s->nsc = sc->cloak == GC_CLOAK_REFERENCED ? 1.0 + s->e : 1.0;
+    s->nsc2 = s->nsc * s->nsc;
+    s->nplate = 1.0 + s->e;
+    s->fresnel = sc->fresnel;
+    s->backdrop = sc->backdrop;
+    s->bd_y = sc->backdrop == GC_BACKDROP_PLANE ? sc->backdrop_y : 0.0;
+    s->bd_P = sc->backdrop == GC_BACKDROP_PLANE ? sc->backdrop_period : 1.0;
     return GC_OK;
 }
 
@@ -324,11 +354,16 @@ static gc_status make_camera(const gc_camera* c, CamDev* d)
     }
     if (!(n2 > 0)) return fail(GC_EINVAL, "eye and target coincide");
     for (int a = 0; a < 3; ++a) f[a] /= std::sqrt(n2);
-    double r[3] = {-f[2], 0.0, f[0]};   // f x (0, 1, 0)
-    double rn = std::sqrt(r[0] * r[0] + r[2] * r[2]);
-    if (!(rn > 1e-12)) return fail(GC_EINVAL, "camera looks straight along y: right vector undefined");
-    r[0] /= rn;
-    r[2] /= rn;
+    // right = forward x up hint (+y when the hint is zero)
+    double hint[3] = {c->up[0], c->up[1], c->up[2]};
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(hint[a])) return fail(GC_EINVAL, "camera up must be finite");
+    if (hint[0] == 0.0 && hint[1] == 0.0 && hint[2] == 0.0) hint[1] = 1.0;
+    double r[3] = {f[1] * hint[2] - f[2] * hint[1], f[2] * hint[0] - f[0] * hint[2], f[0] * hint[1] - f[1] * hint[0]};
+    double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rn > 1e-12)) return fail(GC_EINVAL, "camera looks along its up vector: right vector undefined");
+    for (int a = 0; a < 3; ++a) r[a] /= rn;
+    if (!(c->fov_x_deg >= 0 && c->fov_x_deg < 180)) return fail(GC_EINVAL, "fov_x_deg must be in [0, 180)");
     double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
     for (int a = 0; a < 3; ++a) {
         d->eye[a] = c->eye[a];
@@ -337,7 +372,8 @@ static gc_status make_camera(const gc_camera* c, CamDev* d)
         d->u[a] = u[a];
     }
     d->t = std::tan(0.5 * c->fov_y_deg * M_PI / 180.0);
-    d->aspect = (double)c->width / (double)c->height;
+    d->aspect = c->fov_x_deg > 0 ? std::tan(0.5 * c->fov_x_deg * M_PI / 180.0) / d->t
+                                 : (double)c->width / (double)c->height;
     d->W = c->width;
     d->H = c->height;
     d->spp = c->spp;
@@ -1089,11 +1125,15 @@ static gc_status render_impl(gc_ctx* ctx, const gc_scene* scene, const gc_camera
     HIP_OK(hipMemsetAsync(ctx->d_cnt, 0, sizeof(DevCounters), stream));
     long long npx = (long long)c.W * c.H;
     unsigned nb = (unsigned)((npx + 255) / 256);
-    if (scene->mirror == 1)
-        hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npx)), dim3(256), 0, stream, c, s.K, d_rgb,
+    if (scene->mirror == 1 && scene->cloak == GC_CLOAK_NONE)
+        hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npx)), dim3(256), 0, stream, c, s, d_rgb,
                            stats ? ctx->d_cnt : nullptr);
+    else if (opts->prec == GC_F64 && scene->fresnel)
+        hipLaunchKernelGGL(k_render64<true>, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
     else if (opts->prec == GC_F64)
-        hipLaunchKernelGGL(k_render64, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
+        hipLaunchKernelGGL(k_render64<false>, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
+    else if (scene->fresnel)
+        return fail(GC_EUNSUPPORTED, "Fresnel-weighted faces are rendered by the FP64 path (prec = GC_F64)");
     else
         return wf_render(ctx, 1, &s, &c, o, &d_rgb, stats, stream);
     HIP_OK(hipGetLastError());
@@ -1122,7 +1162,10 @@ static gc_status render_batch_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene
     std::vector<CamDev> cd(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
         if ((r = make_scene(&scenes[i], &sd[i])) != GC_OK) return fail(r, "scene %d: %s", i, g_err.c_str());
-        if (scenes[i].mirror == 1) return fail(GC_EUNSUPPORTED, "scene %d: flat-mirror scenes are rendered by gc_render", i);
+        if (scenes[i].mirror == 1 && scenes[i].cloak == GC_CLOAK_NONE)
+            return fail(GC_EUNSUPPORTED, "scene %d: flat-mirror scenes are rendered by gc_render", i);
+        if (scenes[i].fresnel)
+            return fail(GC_EUNSUPPORTED, "scene %d: Fresnel-weighted faces are rendered by the FP64 path", i);
         if ((r = make_camera(&cameras[i], &cd[i])) != GC_OK) return fail(r, "camera %d: %s", i, g_err.c_str());
         if (!d_rgb[i]) return fail(GC_EINVAL, "image pointer %d is null", i);
     }
@@ -1161,6 +1204,8 @@ static gc_status render_grad_impl(gc_ctx* ctx, const gc_scene* scene, const gc_c
     if ((r = make_camera(camera, &c)) != GC_OK) return r;
     if ((r = make_opts(opts, &o)) != GC_OK) return r;
     if (scene->mirror == 1) return fail(GC_EUNSUPPORTED, "the flat-mirror reference does not depend on A or half_width");
+    if (scene->cloak != GC_CLOAK_EQ1 || scene->fresnel || scene->backdrop != GC_BACKDROP_SKY)
+        return fail(GC_EUNSUPPORTED, "the adjoint differentiates the cloak of eq. (1) with Snell faces and the sky");
     if (opts->integ != GC_RK4) return fail(GC_EUNSUPPORTED, "the adjoint differentiates the RK4 tracer (integ = GC_RK4)");
     if (!std::isfinite(scene->sky_K)) return fail(GC_EUNSUPPORTED, "sky_K = inf has no gradient");
     if (!d_ref) return fail(GC_EINVAL, "ref is null");

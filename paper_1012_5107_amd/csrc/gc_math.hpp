@@ -27,13 +27,23 @@ constexpr double kInvE = 0.36787944117144232160;
 // ---------------------------------------------------------------------------
 // Launch-time parameter blocks (kernel arguments live in constant memory).
 // ---------------------------------------------------------------------------
+// cloak kinds: none; eq. (1); eq. (1) / n_min with n_min = 1 / (1 + A k) (the
+// referenced cloak of Sec. 4); a homogeneous plate of index 1 / n_min
+enum CloakKind { CK_NONE = 0, CK_EQ1 = 1, CK_REF = 2, CK_PLATE = 3 };
+
 struct SceneDev {
     double L, A, hw, ytop, K;
     double k, e, invL;
     double invk;       // 1 / k
     double ybp;        // branch-point height (1 + ln(A k)) / k: Z crosses the cut only below it
     double S_hw;       // grating height at x = +-half_width
+    double nsc;        // index multiplier inside the box: 1 + A k for the referenced cloak, else 1
+    double nsc2;       // nsc^2 (the acceleration grad(n^2)/2 scales by it)
+    double nplate;     // the plate's index 1 + A k (cloak CK_PLATE)
+    double bd_y, bd_P; // backdrop plane y = bd_y and its pattern period (backdrop 1)
     int cloak, mirror;
+    int fresnel;       // 1: Fresnel-weighted faces with one reflected branch per crossing
+    int backdrop;      // 0: sky at infinity, 1: patterned plane
 };
 
 struct CamDev {
@@ -275,6 +285,9 @@ __device__ inline void rhs64(const SceneDev& s, double x, double y, cx<double>& 
     }
     double d2;
     accel_from_w<double>(s, W, ax, ay, dW, d2);
+    // grad(n^2)/2 of the box index: the referenced cloak's is nsc^2 times eq. (1)'s
+    ax *= s.nsc2;
+    ay *= s.nsc2;
 }
 
 // Z = -A k e^{-ky} e^{ikx} lies on the branch cut (-inf, -1/e] exactly on the
@@ -392,6 +405,75 @@ __device__ inline void sky_rgb_image(double K, const double d[3], float rgb[3])
         tb = tanhf((float)(K * s8));
     }
     const float m = 0.5f + 0.5f * ta * tb;
+    const float Ca[3] = {0.95f, 0.85f, 0.30f};
+    const float Cb[3] = {0.10f, 0.20f, 0.55f};
+    for (int c = 0; c < 3; ++c) rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);
+}
+
+// Backdrop plane (backdrop 1): the ray from r along d meets y = bd_y at
+// (X, Z) (FP64), where the pattern is m = 1/2 + 1/2 tanh(K cos(2 pi X / P))
+// tanh(K cos(2 pi Z / P)); a ray that does not rise to the plane sees
+// m = 0.  Returns m.
+__device__ inline double plane_m64(const SceneDev& s, const double r[3], const double d[3], double* ca,
+                                   double* cb)
+{
+    *ca = 0.0;
+    *cb = 0.0;
+    if (!(d[1] > 0.0 && r[1] < s.bd_y)) return -1.0;
+    const double t = (s.bd_y - r[1]) / d[1];
+    const double X = r[0] + t * d[0], Z = r[2] + t * d[2];
+    const double iP = 1.0 / s.bd_P;
+    // cos(2 pi u) with u reduced to [-1/2, 1/2]
+    double sa, sb;
+    sincospi(2.0 * (X * iP - rint(X * iP)), &sa, ca);
+    sincospi(2.0 * (Z * iP - rint(Z * iP)), &sb, cb);
+    return 0.0;
+}
+
+// Colour of the backdrop seen by a ray leaving from r along the unit d:
+// the sky at infinity (backdrop 0) or the plane (backdrop 1), FP64.
+__device__ inline void backdrop_rgb64(const SceneDev& s, const double r[3], const double d[3], double rgb[3])
+{
+    if (s.backdrop == 0) { sky_rgb<double>(s.K, d, rgb); return; }
+    double ca, cb, m = 0.0;
+    if (plane_m64(s, r, d, &ca, &cb) == 0.0) {
+        double ta, tb;
+        if (isinf(s.K)) {
+            ta = ca > 0 ? 1.0 : (ca < 0 ? -1.0 : 0.0);
+            tb = cb > 0 ? 1.0 : (cb < 0 ? -1.0 : 0.0);
+        } else {
+            ta = tanh(s.K * ca);
+            tb = tanh(s.K * cb);
+        }
+        m = 0.5 + 0.5 * ta * tb;
+    }
+    const double Ca[3] = {0.95, 0.85, 0.30};
+    const double Cb[3] = {0.10, 0.20, 0.55};
+    for (int c = 0; c < 3; ++c) rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);
+}
+
+// The same for an FP32 image: the landing point and the cosines in FP64,
+// tanh in FP32 on the FP64-formed argument (as sky_rgb_image does for the
+// sky); the sky at infinity in FP32 from the FP64 direction.
+__device__ inline void backdrop_rgb_image(const SceneDev& s, const double r[3], const double d[3], float rgb[3])
+{
+    if (s.backdrop == 0) {
+        sky_rgb_image(s.K, d, rgb);
+        return;
+    }
+    double ca, cb;
+    float m = 0.0f;
+    if (plane_m64(s, r, d, &ca, &cb) == 0.0) {
+        float ta, tb;
+        if (isinf(s.K)) {
+            ta = ca > 0 ? 1.0f : (ca < 0 ? -1.0f : 0.0f);
+            tb = cb > 0 ? 1.0f : (cb < 0 ? -1.0f : 0.0f);
+        } else {
+            ta = tanhf((float)(s.K * ca));
+            tb = tanhf((float)(s.K * cb));
+        }
+        m = 0.5f + 0.5f * ta * tb;
+    }
     const float Ca[3] = {0.95f, 0.85f, 0.30f};
     const float Cb[3] = {0.10f, 0.20f, 0.55f};
     for (int c = 0; c < 3; ++c) rgb[c] = Cb[c] + m * (Ca[c] - Cb[c]);

@@ -127,7 +127,10 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
     std::vector<CamDev> cd(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
         if ((r = make_scene(&scenes[i], &sd[i])) != GC_OK) return fail(r, "scene %d: %s", i, g_err.c_str());
-        if (scenes[i].mirror == 1) return fail(GC_EUNSUPPORTED, "scene %d: flat-mirror scenes are rendered by gc_render", i);
+        if (scenes[i].mirror == 1 && scenes[i].cloak == GC_CLOAK_NONE)
+            return fail(GC_EUNSUPPORTED, "scene %d: flat-mirror scenes are rendered by gc_render", i);
+        if (scenes[i].fresnel)
+            return fail(GC_EUNSUPPORTED, "scene %d: Fresnel-weighted faces are rendered by the FP64 path", i);
         if ((r = make_camera(&cameras[i], &cd[i])) != GC_OK) return fail(r, "camera %d: %s", i, g_err.c_str());
         if (!d_rgb[i]) return fail(GC_EINVAL, "image pointer %d is null", i);
         if (d_ref && !d_ref[i]) return fail(GC_EINVAL, "reference pointer %d is null", i);
@@ -193,7 +196,7 @@ static gc_status batch_plan_create_impl(gc_ctx* ctx, int32_t n_scenes, const gc_
                 const long long npix = (long long)cd[i].W * cd[i].H;
                 if (render_refs)
                     hipLaunchKernelGGL(k_render_flat, dim3(flat_blocks(ctx->n_cu, npix)), dim3(256), 0, cs, cd[i],
-                                       sd[i].K, d_ref[i], nullptr);
+                                       sd[i], d_ref[i], nullptr);
                 long long nb = std::min<long long>((npix + 255) / 256, kCCBlocks);
                 hipLaunchKernelGGL(k_cc_moments, dim3((unsigned)nb), dim3(256), 0, cs, (const float*)d_rgb[i],
                                    (const float*)d_ref[i], npix, npix, npix, 3, p->d_part);

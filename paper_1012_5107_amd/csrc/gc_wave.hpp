@@ -269,24 +269,30 @@ __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const S
     R.qx[q] = p[0]; R.qy[q] = p[1]; R.qz[q] = p[2];
     float c3[3] = {0.0f, 0.0f, 0.0f};
     if (status == RS_OK) {
-        // the image is FP32: so is the sky lookup
-        const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
-        sky_rgb<float>((float)s.K, pf, c3);
+        if (s.backdrop == 0) {
+            // the image is FP32: so is the sky lookup
+            const float pf[3] = {(float)p[0], (float)p[1], (float)p[2]};
+            sky_rgb<float>((float)s.K, pf, c3);
+        } else {
+            // the backdrop plane: where the ray meets it, from the FP64 exit
+            backdrop_rgb_image(s, r, p, c3);
+        }
     }
     R.rgb[3 * q + 0] = c3[0];
     R.rgb[3 * q + 1] = c3[1];
     R.rgb[3 * q + 2] = c3[2];
 }
 
-// Walk through air from (r, p) and either finish the ray (returns -1) or
-// set up its in-box state (returns the box queue it goes to).
+// Walk through air from (r, p) (a plate is crossed on the way) and either
+// finish the ray (returns -1) or set up its in-box state (returns the box
+// queue it goes to).
 __device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, const SceneDev& s, double r[3],
                                                double p[3], LaneCount& cnt)
 {
     double mc = 1.0;
     int st = RS_OK;
     cx<double> W;
-    int ao = air_walk(s, a.o, r, p, cnt, &mc, &st, &W);
+    int ao = air_walk_plates(s, a.o, r, p, cnt, &mc, &st, &W);
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return -1; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return -1; }
@@ -879,7 +885,7 @@ __device__ __forceinline__ int air_body(const WfArgs& a, long long q, const Scen
     double mc = 1.0;
     int st = RS_OK;
     cx<double> W;
-    int ao = air_walk(s, a.o, r, p, cnt, &mc, &st, &W);
+    int ao = air_walk_plates(s, a.o, r, p, cnt, &mc, &st, &W);
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return 2; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return 2; }

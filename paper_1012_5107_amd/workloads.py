@@ -8,7 +8,8 @@ Scene fields follow the paper's notation (Sec. 2): grating period ``Lambda``,
 half peak-to-peak amplitude ``A`` (eq. (2)); the cloak of eq. (1) fills the
 box |x| <= half_width, grating < y <= y_top.  There is no public dataset for
 this method: the backdrop of the paper's renderings is a photograph that is
-not available, so every workload uses the procedural sky instead.
+not available, so the workloads use a procedural sky, or, for the paper's
+own scene, a procedural pattern on the plane of the photograph.
 """
 import math
 
@@ -125,6 +126,50 @@ def batch_64(seed=1012, n_scenes=64, jitter_seed=1, resolutions=(256, 512, 1024)
         cams.append(camera(res, res, spp=4, jitter=True, seed=jitter_seed,
                            eye=orbit_eye(az, el, SQRT45), scene_index=s))
     return scenes, cams
+
+
+# --- the paper's scene (Sec. 4, Figs. 2-7; Sec. 5, Table 1) -----------------
+# The observer stands d = 2.64 units above the mirror and looks down at it
+# with a 50 x 42 degree field of view; the grating (Lambda = 1,
+# A = 3 / (16 pi)) runs along the image's vertical (tan(21 deg) = Lambda / d:
+# three maxima in view).  The photograph she stands in front of is replaced
+# by a patterned plane at her height; the cloak covers the whole mirror.
+PAPER_A = 3.0 / (16.0 * math.pi)
+PAPER_D = 2.64
+PAPER_HEIGHTS = (1.1, 0.55, 0.41)
+PAPER_FOVS = (0.0, 10.0, 25.0, 50.0)
+
+
+def paper_scene(kind, height=1.1, fresnel=1, period=0.5, sky_K=16.0):
+    """kind: 'flat' (Fig. 3 (a)), 'grating' (3 (b)), 'cloak' (3 (c), eq. (1)),
+    'plate' (5-7 (a): plate of index 1 / n_min on the flat mirror),
+    'plate_grating' (5-7 (b)), 'referenced' (5-7 (c))."""
+    cloak, mirror = {"flat": (CLOAK_NONE, 1), "grating": (CLOAK_NONE, 0), "cloak": (CLOAK_EQ1, 0),
+                     "plate": (CLOAK_PLATE, 1), "plate_grating": (CLOAK_PLATE, 0),
+                     "referenced": (CLOAK_REFERENCED, 0)}[kind]
+    return scene(A=PAPER_A, half_width=math.inf, y_top=height, cloak=cloak, mirror=mirror, sky_K=sky_K,
+                 fresnel=fresnel if cloak != CLOAK_NONE else 0, backdrop=BACKDROP_PLANE, backdrop_y=PAPER_D,
+                 backdrop_period=period)
+
+
+def paper_camera(width=301, height=251, spp=4, seed=4):
+    """The observer's point camera: at (0, d, 0) looking down, the image's up
+    along +x (across the grooves), 50 deg horizontally and 42 vertically;
+    an odd width puts a column on the vertical centre line (FOV 0)."""
+    return camera(width, height, spp=spp, jitter=spp > 1, seed=seed, eye=(0.0, PAPER_D, 0.0),
+                  target=(0.0, 0.0, 0.0), up=(1.0, 0.0, 0.0), fov_y_deg=42.0, fov_x_deg=50.0)
+
+
+def fov_columns(cam, fov_deg):
+    """Columns [c0, c1) whose centres lie within the horizontal field of view
+    fov_deg about the vertical centre line (0: the centre column)."""
+    W = cam["width"]
+    tx = math.tan(math.radians(0.5 * cam["fov_x_deg"]))
+    lim = math.tan(math.radians(0.5 * fov_deg))
+    cols = [i for i in range(W) if abs((2.0 * (i + 0.5) / W - 1.0) * tx) <= lim + 1e-12]
+    if not cols:
+        cols = [W // 2]
+    return cols[0], cols[-1] + 1
 
 
 def sample_pixels(width, height, count, seed):

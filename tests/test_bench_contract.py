@@ -35,17 +35,23 @@ def test_help_lists_the_workloads():
         assert w in r.stdout
 
 
-def test_traffic_tables_resolve_the_options_the_benchmark_uses():
+def test_traffic_tables_resolve_the_options_the_benchmark_uses(monkeypatch):
     """The measured HBM bytes per launch are found for the options the
     autotuner forms by products (3 x 1e-7, 1e-7 / 3), for every workload
-    whose roofline reports them; an unmeasured setting gives None."""
+    whose roofline reports them, while the in-box kernel's sources are the
+    ones they were measured with; an unmeasured setting, or any change of
+    those sources, gives None."""
     sys.path.insert(0, ROOT)
     import bench
+    monkeypatch.setattr(bench, "MEASURED_SHA", bench._kernel_sha())
     assert bench._measured(bench.TRAFFIC_K_WF_BOX, (3 * 1e-7, 0.5, "dopri5")) is not None
     assert bench._measured(bench.TRAFFIC_K_WF_BOX, (3e-7, 0.5, "rk4")) is None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7 / 3, 0.1)) is not None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.02)) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7 / 3, 0.1, 1e-2)) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.02, 1e-2)) is not None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.02, 0.3)) is None
     assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (1e-7,)) is not None
     assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (3e-7,)) is None
     for table in (bench.TRAFFIC_K_WF_BOX, bench.TRAFFIC_K_WF_BOX_BATCH, bench.TRAFFIC_K_WF_BOX_STRESS):
         assert all(isinstance(k, tuple) and v > 0 for k, v in table.items())
+    monkeypatch.setattr(bench, "MEASURED_SHA", "0" * 16)
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (1e-7,)) is None
