@@ -727,20 +727,6 @@ __device__ inline int plate_walk64(const SceneDev& s, const OptsDev& o, double r
     }
 }
 
-// The walk through air for the pipeline's FP64 kernels: the plate (straight
-// flights) is crossed in place, so that a plate scene never enters the
-// in-box queues; returns as air_walk does.
-__device__ inline int air_walk_plates(const SceneDev& s, const OptsDev& o, double r[3], double p[3], LaneCount& cnt,
-                                      double* min_cos, int* status, cx<double>* w_in)
-{
-    for (;;) {
-        const int ao = air_walk(s, o, r, p, cnt, min_cos, status, w_in);
-        if (ao != AO_ENTERED || s.cloak != CK_PLATE) return ao;
-        const int st = plate_walk64(s, o, r, p, cnt, min_cos);
-        if (st != RS_OK) { *status = st; return AO_FAIL; }
-    }
-}
-
 // Complete path of one ray in FP64.  Returns the status; the exit point and
 // the unit exit direction go to out_org / out_dir.
 __device__ inline int trace_ray64(const SceneDev& s, const OptsDev& o, const double org[3], const double dir[3],

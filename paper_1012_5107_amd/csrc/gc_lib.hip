@@ -185,6 +185,8 @@ struct WfStore {
     QCtr* h_ctr = nullptr;      // pinned host copy of the counters
     int box_blocks[2] = {0, 0}; // persistent grid of k_wf_box<RK4>, <DOPRI5>
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    unsigned long long* acc = nullptr;   // Fresnel: per-sample colour sums (fixed point)
+    size_t acc_bytes = 0;
     // per call
     long long fp64_steps = 0, rounds = 0, tail_rays = 0;
     double hot_ms = 0.0, event_ms = 0.0, tail_ms = 0.0, total_ms = 0.0;
@@ -616,15 +618,15 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
 // ---------------------------------------------------------------------------
 // FP32 pipeline orchestration.
 // ---------------------------------------------------------------------------
-static size_t wf_ray_bytes(long long n) { return (size_t)n * (7 * 8 + 7 * 4 + 14 * 4 + 3 * 4 + 4); }
+static size_t wf_ray_bytes(long long n) { return (size_t)n * (8 * 8 + 10 * 4 + 14 * 4 + 3 * 4 + 4); }
 
 static void wf_carve(void* base, long long n, WfRays& R)
 {
     char* p = (char*)base;
     auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) & ~(size_t)255; return r; };
-    double** d[] = {&R.rx, &R.ry, &R.rz, &R.qx, &R.qy, &R.qz, &R.z0};
+    double** d[] = {&R.rx, &R.ry, &R.rz, &R.qx, &R.qy, &R.qz, &R.z0, &R.wgt};
     for (double** q : d) *q = (double*)take(sizeof(double) * n);
-    int** ip[] = {&R.cell, &R.steps, &R.rej, &R.events, &R.flags, &R.scene, &R.status, &R.fbk};
+    int** ip[] = {&R.cell, &R.steps, &R.rej, &R.events, &R.flags, &R.scene, &R.status, &R.fbk, &R.parent, &R.steps0};
     for (int** q : ip) *q = (int*)take(sizeof(int) * n);
     float** fp[] = {&R.fx, &R.lx, &R.y, &R.ly, &R.px, &R.lpx, &R.py, &R.lpy, &R.pz, &R.Wr, &R.Wi, &R.h, &R.tau,
                     &R.ltau};
@@ -634,7 +636,7 @@ static void wf_carve(void* base, long long n, WfRays& R)
 
 static void wf_free(WfStore& w)
 {
-    void* bufs[] = {w.rays, w.queues, w.tables, w.ctr, w.tot};
+    void* bufs[] = {w.rays, w.queues, w.tables, w.ctr, w.tot, w.acc};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (w.h_ctr) (void)hipHostFree(w.h_ctr);
@@ -775,20 +777,9 @@ static gc_status wf_round(gc_ctx* ctx, WfStore& w, const WfArgs& a, int cur, uns
 
 // Run the pipeline for a filled WfArgs (tables already on the device),
 // round by round, reading the queue lengths back after each.
-static gc_status wf_run(gc_ctx* ctx, WfStore& w, WfArgs& a, hipStream_t stream)
+static gc_status wf_rounds(gc_ctx* ctx, WfStore& w, WfArgs& a, unsigned len, hipStream_t stream)
 {
-    const int integ = a.o.integ;
-    w.fp64_steps = 0;
-    w.rounds = 0;
-    w.tail_rays = 0;
-    w.hot_ms = w.event_ms = w.tail_ms = 0.0;
-    HIP_OK(hipEventRecord(w.ev[0], stream));
-    wf_start(ctx, w, a, stream);
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipStreamSynchronize(stream));
-    unsigned len = w.h_ctr->box_len[0] + w.h_ctr->slow_len[0];
-    const unsigned box_max = wf_box_max(ctx, w, integ);
+    const unsigned box_max = wf_box_max(ctx, w, a.o.integ);
     // one round per visit of the box
     for (int round = 0; len > 0; ++round) {
         const int cur = round & 1;
@@ -805,11 +796,25 @@ static gc_status wf_run(gc_ctx* ctx, WfStore& w, WfArgs& a, hipStream_t stream)
         w.hot_ms += t1;
         w.event_ms += t2;
         w.fp64_steps += w.h_ctr->ev_len;
-        w.rounds = round + 1;
+        w.rounds += 1;
         len = w.h_ctr->box_len[cur ^ 1] + w.h_ctr->slow_len[cur ^ 1];
         if (round > 100000) return fail(GC_EDEVICE, "pipeline did not drain");
     }
     return GC_OK;
+}
+
+static gc_status wf_run(gc_ctx* ctx, WfStore& w, WfArgs& a, hipStream_t stream)
+{
+    w.fp64_steps = 0;
+    w.rounds = 0;
+    w.tail_rays = 0;
+    w.hot_ms = w.event_ms = w.tail_ms = 0.0;
+    HIP_OK(hipEventRecord(w.ev[0], stream));
+    wf_start(ctx, w, a, stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    return wf_rounds(ctx, w, a, w.h_ctr->box_len[0] + w.h_ctr->slow_len[0], stream);
 }
 
 static WfArgs wf_args(const gc_ctx* ctx, const WfStore& w, const OptsDev& o, int ns, long long n_rays)
@@ -869,7 +874,8 @@ static gc_status wf_read_totals(WfStore& w, gc_stats* st, hipStream_t stream)
 // Reserve the store's buffers for n scenes, upload their tables and fill
 // the kernel arguments (render mode).  n_pix: total pixels.
 static gc_status wf_setup(gc_ctx* ctx, WfStore& w, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
-                          float* const* d_rgb, hipStream_t stream, WfArgs* a, long long* n_pix_out)
+                          float* const* d_rgb, hipStream_t stream, WfArgs* a, long long* n_pix_out,
+                          long long extra = 0)
 {
     std::vector<long long> roff(ns + 1), poff(ns + 1);
     roff[0] = poff[0] = 0;
@@ -879,8 +885,8 @@ static gc_status wf_setup(gc_ctx* ctx, WfStore& w, int ns, const SceneDev* sc, c
         roff[i + 1] = roff[i] + npx * cams[i].spp;
     }
     const long long n_rays = roff[ns], n_pix = poff[ns];
-    if (n_rays > (1ll << 31) - 1) return fail(GC_EINVAL, "more than 2^31 - 1 samples in one launch");
-    gc_status r = wf_reserve(ctx, w, n_rays, ns);
+    if (n_rays + extra > (1ll << 31) - 1) return fail(GC_EINVAL, "more than 2^31 - 1 samples (and branches) in one launch");
+    gc_status r = wf_reserve(ctx, w, n_rays + extra, ns);
     if (r != GC_OK) return r;
     // tables: staged in host memory, copied in one go
     const size_t tb = wf_table_bytes(ns);
@@ -908,9 +914,62 @@ static gc_status wf_finish(WfStore& w, const WfArgs& a, int ns, long long n_pix,
     return GC_OK;
 }
 
+// With Fresnel-weighted faces: the primaries' pass appends the reflected
+// branches to a pool after the primaries' slots (4 per sample to start with;
+// a pass that overflows it is run again with room for every branch it
+// asked for); then the branches' pass (the same rounds, no further splits)
+// and the weighted per-sample sums.
+static gc_status wf_render_fresnel(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
+                                   float* const* d_rgb, gc_stats* st, hipStream_t stream)
+{
+    WfStore& w = ctx->wf;
+    long long n_rays = 0;
+    for (int i = 0; i < ns; ++i) n_rays += (long long)cams[i].W * cams[i].H * cams[i].spp;
+    long long cap = 4 * n_rays + 65536;
+    WfArgs a;
+    long long n_pix = 0;
+    unsigned n_seeds = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (n_rays + cap > (1ll << 31) - 1) cap = (1ll << 31) - 1 - n_rays;
+        gc_status r = wf_setup(ctx, w, ns, sc, cams, o, d_rgb, stream, &a, &n_pix, cap);
+        if (r != GC_OK) return r;
+        a.seed_base = n_rays;
+        a.seed_cap = (unsigned)cap;
+        if ((r = wf_run(ctx, w, a, stream)) != GC_OK) return r;
+        n_seeds = w.h_ctr->seed_len;
+        if ((long long)n_seeds <= cap) break;
+        if (attempt > 0 || n_rays + (long long)n_seeds > (1ll << 31) - 1)
+            return fail(GC_ENOMEM, "%u Fresnel branches do not fit one launch", n_seeds);
+        cap = n_seeds;
+    }
+    if (n_seeds > 0) {
+        hipLaunchKernelGGL(k_wf_seed_reset, dim3(1), dim3(64), 0, stream, w.ctr);
+        const unsigned g = (unsigned)std::min<long long>((n_seeds + 255) / 256, 8LL * ctx->n_cu);
+        hipLaunchKernelGGL(k_wf_seed_init, dim3(g), dim3(256), 0, stream, a, n_seeds);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(w.h_ctr, w.ctr, sizeof(QCtr), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        gc_status r = wf_rounds(ctx, w, a, w.h_ctr->box_len[0] + w.h_ctr->slow_len[0], stream);
+        if (r != GC_OK) return r;
+    }
+    gc_status r = grow((void**)&w.acc, &w.acc_bytes, sizeof(unsigned long long) * 3 * (size_t)n_rays,
+                       "Fresnel colour sums");
+    if (r != GC_OK) return r;
+    const unsigned gf = (unsigned)std::min<long long>((n_rays + n_seeds + 255) / 256, kFoldBlocks);
+    hipLaunchKernelGGL(k_fill_u64, dim3(gf), dim3(256), 0, stream, w.acc, 3 * n_rays);
+    hipLaunchKernelGGL(k_wf_fresnel_fold, dim3(gf), dim3(256), 0, stream, a, n_seeds, w.acc, w.tot);
+    hipLaunchKernelGGL(k_wf_fresnel_rgb, dim3(gf), dim3(256), 0, stream, a, (const unsigned long long*)w.acc);
+    HIP_OK(hipGetLastError());
+    w.tail_rays = n_seeds;
+    if ((r = wf_finish(w, a, ns, n_pix, stream)) != GC_OK) return r;
+    return wf_read_totals(w, st, stream);
+}
+
 static gc_status wf_render(gc_ctx* ctx, int ns, const SceneDev* sc, const CamDev* cams, const OptsDev& o,
                            float* const* d_rgb, gc_stats* st, hipStream_t stream)
 {
+    for (int i = 0; i < ns; ++i)
+        if (sc[i].fresnel) return wf_render_fresnel(ctx, ns, sc, cams, o, d_rgb, st, stream);
     WfStore& w = ctx->wf;
     WfArgs a;
     long long n_pix = 0;
@@ -1132,8 +1191,6 @@ static gc_status render_impl(gc_ctx* ctx, const gc_scene* scene, const gc_camera
         hipLaunchKernelGGL(k_render64<true>, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
     else if (opts->prec == GC_F64)
         hipLaunchKernelGGL(k_render64<false>, dim3(nb), dim3(256), 0, stream, s, c, o, d_rgb, ctx->d_cnt);
-    else if (scene->fresnel)
-        return fail(GC_EUNSUPPORTED, "Fresnel-weighted faces are rendered by the FP64 path (prec = GC_F64)");
     else
         return wf_render(ctx, 1, &s, &c, o, &d_rgb, stats, stream);
     HIP_OK(hipGetLastError());
@@ -1164,8 +1221,6 @@ static gc_status render_batch_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene
         if ((r = make_scene(&scenes[i], &sd[i])) != GC_OK) return fail(r, "scene %d: %s", i, g_err.c_str());
         if (scenes[i].mirror == 1 && scenes[i].cloak == GC_CLOAK_NONE)
             return fail(GC_EUNSUPPORTED, "scene %d: flat-mirror scenes are rendered by gc_render", i);
-        if (scenes[i].fresnel)
-            return fail(GC_EUNSUPPORTED, "scene %d: Fresnel-weighted faces are rendered by the FP64 path", i);
         if ((r = make_camera(&cameras[i], &cd[i])) != GC_OK) return fail(r, "camera %d: %s", i, g_err.c_str());
         if (!d_rgb[i]) return fail(GC_EINVAL, "image pointer %d is null", i);
     }

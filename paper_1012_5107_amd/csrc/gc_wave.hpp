@@ -51,6 +51,7 @@ struct QCtr {
     unsigned air_len;               // rays whose walk through air needs the contact search
     unsigned rec_len;               // long first visits recorded (see WfArgs::rec)
     unsigned long long hot_steps;   // accepted steps taken by k_wf_box (all rounds)
+    unsigned seed_len;              // Fresnel branches spawned (slots requested)
 };
 
 // per-ray arrays (structure of arrays)
@@ -61,11 +62,18 @@ struct WfRays {
     float *fx, *lx, *y, *ly, *px, *lpx, *py, *lpy, *pz, *Wr, *Wi, *h, *tau, *ltau;
     int *steps, *rej, *events, *flags, *scene, *status, *fbk;
     float* rgb;   // 3 per ray
+    // Fresnel-weighted faces: the path's weight, and for a reflected branch
+    // (the slots from seed_base on) its sample's primary ray and the steps
+    // it inherited from it
+    double* wgt;
+    int *parent, *steps0;
 };
 
 // WF_FIRST_VISIT: the ray entered the box from k_wf_init (its first visit,
 // in round 0's queues) and has not been handed to the FP64 kernel since
-enum WfFlag { WF_LAST_REJ = 1, WF_FIRST_VISIT = 2 };
+// WF_SEED_INSIDE: a Fresnel branch that starts inside the box (reflected
+// at an exit face)
+enum WfFlag { WF_LAST_REJ = 1, WF_FIRST_VISIT = 2, WF_SEED_INSIDE = 4 };
 
 // Scheduling of the in-box kernel (what is computed does not depend on it).
 struct WfSched {
@@ -106,7 +114,15 @@ struct WfArgs {
     int* rec;
     unsigned rec_cap;
     int rec_min;
+    // Fresnel branches (render mode, scenes with fresnel = 1): a primary ray
+    // that crosses a face appends its reflected part to the slots
+    // [seed_base, seed_base + seed_cap); seed_cap = 0: no branches
+    long long seed_base;
+    unsigned seed_cap;
 };
+
+// A ray is a reflected branch when its slot lies in the branch pool.
+__device__ __forceinline__ bool is_branch(const WfArgs& a, long long q) { return a.seed_cap > 0 && q >= a.seed_base; }
 
 __device__ __forceinline__ int scene_of(const WfArgs& a, long long q)
 {
@@ -277,10 +293,71 @@ __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const S
             // the backdrop plane: where the ray meets it, from the FP64 exit
             backdrop_rgb_image(s, r, p, c3);
         }
+        if (s.fresnel && a.seed_cap > 0) {
+            // the path's share of the sample's light
+            const double w = R.wgt[q];
+            for (int c = 0; c < 3; ++c) c3[c] = (float)(w * (double)c3[c]);
+        }
     }
     R.rgb[3 * q + 0] = c3[0];
     R.rgb[3 * q + 1] = c3[1];
     R.rgb[3 * q + 2] = c3[2];
+}
+
+// Fresnel split at a face crossing of ray q at r (Sec. 3): p1 the momentum
+// on the incoming side, p2 the transmitted one.  A primary ray appends the
+// reflected part (weight w R, on the incoming side: `inside` for an exit)
+// to the branch pool with the counts it has reached; every ray goes on with
+// weight w T.  Branches never split again.
+__device__ __forceinline__ void fresnel_cross(const WfArgs& a, long long q, const double r[3], const double p1[3],
+                                              const double p2[3], int face, bool inside, int steps, int rej,
+                                              int events)
+{
+    const WfRays& R = a.R;
+    double refl[3];
+    const double Rf = crossing_R(face, p1, p2, refl);
+    const double w = R.wgt[q];
+    if (a.seed_cap > 0 && !is_branch(a, q)) {
+        const unsigned k = atomicAdd(&a.ctr->seed_len, 1u);
+        if (k < a.seed_cap) {
+            const long long b = a.seed_base + (long long)k;
+            R.rx[b] = r[0]; R.ry[b] = r[1]; R.rz[b] = r[2];
+            R.qx[b] = refl[0]; R.qy[b] = refl[1]; R.qz[b] = refl[2];
+            R.wgt[b] = w * Rf;
+            R.parent[b] = (int)q;
+            R.scene[b] = R.scene[q];
+            R.steps[b] = steps;
+            R.steps0[b] = steps;
+            R.rej[b] = rej;
+            R.events[b] = events;
+            R.fbk[b] = 0;
+            R.flags[b] = inside ? WF_SEED_INSIDE : 0;
+            R.status[b] = RS_OK;
+        }
+    }
+    R.wgt[q] = w * (1.0 - Rf);
+}
+
+// The pipeline's walk through air from (r, p): a plate is crossed on the
+// way (straight FP64 flights), and with Fresnel every face crossing splits.
+// Returns as air_walk does (a plate scene never returns AO_ENTERED).
+__device__ __forceinline__ int wf_air_walk(const WfArgs& a, long long q, const SceneDev& s, double r[3], double p[3],
+                                           LaneCount& cnt, int* st, cx<double>* W)
+{
+    double mc = 1.0;
+    for (;;) {
+        double pa[3];
+        int face = 0;
+        const int ao = air_walk(s, a.o, r, p, cnt, &mc, st, W, pa, &face);
+        if (ao == AO_ENTERED && s.fresnel && a.seed_cap > 0)
+            fresnel_cross(a, q, r, pa, p, face, false, (int)cnt.steps, (int)cnt.rejected, cnt.events);
+        if (ao != AO_ENTERED || s.cloak != CK_PLATE) return ao;
+        double pin[3];
+        const int ps = plate_walk64(s, a.o, r, p, cnt, &mc, pin, &face);
+        if (ps != RS_OK) { *st = ps; return AO_FAIL; }
+        if (s.fresnel && a.seed_cap > 0)
+            fresnel_cross(a, q, r, pin, p, face, true, (int)cnt.steps, (int)cnt.rejected, cnt.events);
+    }
 }
 
 // Walk through air from (r, p) (a plate is crossed on the way) and either
@@ -289,11 +366,12 @@ __device__ __forceinline__ void finish_ray(const WfArgs& a, long long q, const S
 __device__ __forceinline__ int continue_in_air(const WfArgs& a, long long q, const SceneDev& s, double r[3],
                                                double p[3], LaneCount& cnt)
 {
-    double mc = 1.0;
     int st = RS_OK;
     cx<double> W;
-    int ao = air_walk_plates(s, a.o, r, p, cnt, &mc, &st, &W);
+    int ao = wf_air_walk(a, q, s, r, p, cnt, &st, &W);
     a.R.events[q] = cnt.events;
+    a.R.steps[q] = (int)cnt.steps;
+    a.R.rej[q] = (int)cnt.rejected;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return -1; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return -1; }
     Box64 b = box_entry_state(a.o, r, p, W);
@@ -366,6 +444,7 @@ __device__ __forceinline__ int init_ray(const WfArgs& a, long long q, bool* defe
     a.R.scene[q] = si;
     a.R.flags[q] = 0;
     a.R.fbk[q] = 0;
+    if (a.seed_cap > 0) a.R.wgt[q] = 1.0;
     a.R.steps[q] = 0;
     a.R.rej[q] = 0;
     if (!air_leg_plain(s, r, p)) {
@@ -546,7 +625,9 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                         double nf[3] = {0.0, 0.0, 0.0};
                         const int face = pend - 1;
                         if (face == 0) nf[1] = 1.0; else if (face == 1) nf[0] = 1.0; else nf[0] = -1.0;
+                        const double pin[3] = {p3[0], p3[1], p3[2]};
                         snell(p3, nf, 1.0);
+                        if (sp->fresnel && a.seed_cap > 0) fresnel_cross(a, q, r, pin, p3, face, true, steps, rej, nev);
                         if (air_escapes_now(*sp, r, p3)) {
                             // nothing ahead: the sky, as the air kernel would
                             finish_ray(a, q, *sp, RS_OK, r, p3);
@@ -851,8 +932,10 @@ __device__ __forceinline__ int event_body(const WfArgs& a, long long q, const Sc
     // FP64 steps while the ray stays where FP32 cannot resolve W (with a
     // margin), so that a ray lingering near the branch point does not cost
     // a round per step
+    double pin[3];
+    int face = 0;
     for (int n = 0; n < 256; ++n) {
-        so = box_step64(s, o, b, cnt, &mc, r, p, &st);
+        so = box_step64(s, o, b, cnt, &mc, r, p, &st, pin, &face);
         if (so == SO_INSIDE && cnt.steps >= o.max_steps) { so = SO_FAIL; st = RS_MAX_STEPS; }
         if (so != SO_INSIDE) break;
         const double d2 = (1.0 + b.r1.W.re) * (1.0 + b.r1.W.re) + b.r1.W.im * b.r1.W.im;
@@ -872,6 +955,8 @@ __device__ __forceinline__ int event_body(const WfArgs& a, long long q, const Sc
     }
     a.R.rx[q] = r[0]; a.R.ry[q] = r[1]; a.R.rz[q] = r[2];
     a.R.qx[q] = p[0]; a.R.qy[q] = p[1]; a.R.qz[q] = p[2];
+    if (s.fresnel && a.seed_cap > 0)
+        fresnel_cross(a, q, r, pin, p, face, true, (int)cnt.steps, (int)cnt.rejected, cnt.events);
     return 1;
 }
 
@@ -882,10 +967,9 @@ __device__ __forceinline__ int air_body(const WfArgs& a, long long q, const Scen
     double r[3] = {a.R.rx[q], a.R.ry[q], a.R.rz[q]};
     double p[3] = {a.R.qx[q], a.R.qy[q], a.R.qz[q]};
     LaneCount cnt = {a.R.steps[q], a.R.rej[q], a.R.events[q], 0};
-    double mc = 1.0;
     int st = RS_OK;
     cx<double> W;
-    int ao = air_walk_plates(s, a.o, r, p, cnt, &mc, &st, &W);
+    int ao = wf_air_walk(a, q, s, r, p, cnt, &st, &W);
     a.R.events[q] = cnt.events;
     if (ao == AO_FAIL) { finish_ray(a, q, s, st, r, p); return 2; }
     if (ao == AO_ESCAPED) { finish_ray(a, q, s, RS_OK, r, p); return 2; }
@@ -963,6 +1047,102 @@ __device__ __forceinline__ void add_totals(WfTotals* tot, unsigned long long c_r
         // WfTotals is six consecutive counters in the order of v
         if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(tot) + k, sum);
     }
+}
+
+// ---- Fresnel branches: the seed pass and the weighted sum -------------------
+// Queue counters cleared for the branches' pass (the branch count and the
+// in-box kernel's step total are kept).
+__global__ void __launch_bounds__(64) k_wf_seed_reset(QCtr* c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int k = 0; k < 2; ++k) c->box_len[k] = c->box_head[k] = c->slow_len[k] = c->slow_head[k] = 0;
+        c->ev_len = c->ev_head = c->air_len = 0;
+    }
+}
+
+// Start every branch: one reflected at an exit face goes into the box at
+// the face (a plate: straight on to its next face, then through air); one
+// reflected at an entry walks through air.  The rays that reach the box go
+// to round 0's queues.
+__global__ void __launch_bounds__(256) k_wf_seed_init(WfArgs a, unsigned n_seeds)
+{
+    // the loop bound is uniform over the block, so that the pushes see every lane
+    for (unsigned base = blockIdx.x * blockDim.x; base < n_seeds; base += gridDim.x * blockDim.x) {
+        const unsigned k = base + threadIdx.x;
+        int dest = -1;
+        const long long q = a.seed_base + (long long)k;
+        if (k < n_seeds) {
+            const SceneDev s = a.scenes[a.R.scene[q]];
+            double r[3] = {a.R.rx[q], a.R.ry[q], a.R.rz[q]};
+            double p[3] = {a.R.qx[q], a.R.qy[q], a.R.qz[q]};
+            LaneCount cnt = {a.R.steps[q], a.R.rej[q], a.R.events[q], 0};
+            if (a.R.flags[q] & WF_SEED_INSIDE) {
+                if (s.cloak == CK_PLATE) {
+                    double mc = 1.0, pin[3];
+                    int face = 0;
+                    const int ps = plate_walk64(s, a.o, r, p, cnt, &mc, pin, &face);
+                    a.R.events[q] = cnt.events;
+                    if (ps != RS_OK) {
+                        finish_ray(a, q, s, ps, r, p);
+                    } else {
+                        fresnel_cross(a, q, r, pin, p, face, true, (int)cnt.steps, (int)cnt.rejected, cnt.events);
+                        dest = continue_in_air(a, q, s, r, p, cnt);
+                    }
+                } else {
+                    const cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
+                    const Box64 b = box_entry_state(a.o, r, p, W);
+                    store_box64(a, q, s, b);
+                    a.R.status[q] = RS_OK;
+                    dest = box_dest(a, p);
+                }
+            } else {
+                dest = continue_in_air(a, q, s, r, p, cnt);
+            }
+        }
+        push_box_wave(a, 0, dest, (int)q);
+    }
+}
+
+// Weighted colours summed per sample in fixed point (2^-40): integer
+// additions do not depend on their order, so the sum does not depend on
+// which slot a branch took.  Slots [0, n_rays) are the primaries, the
+// branch pool follows; a branch adds to its primary's sample.  The branches'
+// own accepted steps are added to the totals.
+constexpr double kFixScale = 1099511627776.0;   // 2^40
+
+__global__ void __launch_bounds__(256) k_wf_fresnel_fold(WfArgs a, unsigned n_seeds, unsigned long long* acc,
+                                                         WfTotals* tot)
+{
+    unsigned long long c_steps = 0;
+    const long long n = a.n_rays + (long long)n_seeds;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (long long)gridDim.x * blockDim.x) {
+        const long long q = g < a.n_rays ? g : a.seed_base + (g - a.n_rays);
+        const long long smp = g < a.n_rays ? q : (long long)a.R.parent[q];
+        if (g >= a.n_rays) c_steps += (unsigned)(a.R.steps[q] - a.R.steps0[q]);
+        for (int c = 0; c < 3; ++c) {
+            const float v = a.R.rgb[3 * q + c];
+            if (v > 0.0f) atomicAdd(&acc[3 * smp + c], (unsigned long long)llrint((double)v * kFixScale));
+        }
+    }
+    add_totals(tot, 0, c_steps, 0, 0, 0, 0);
+}
+
+// The sample colours from the sums (a sample whose primary path failed is
+// black, as without the split).
+__global__ void __launch_bounds__(256) k_wf_fresnel_rgb(WfArgs a, const unsigned long long* acc)
+{
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < a.n_rays;
+         q += (long long)gridDim.x * blockDim.x) {
+        const bool ok = a.R.status[q] == RS_OK;
+        for (int c = 0; c < 3; ++c) a.R.rgb[3 * q + c] = ok ? (float)((double)acc[3 * q + c] / kFixScale) : 0.0f;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 // Pixel averages (render mode) and counters (totals in WfTotals).
