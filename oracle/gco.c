@@ -322,6 +322,15 @@ static const double DP_B5[7] = { 35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -21
 static const double DP_B4[7] = { 5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
                                  -92097.0 / 339200, 187.0 / 2100, 1.0 / 40 };
 
+/* The tableau as used above (test access): A[7][6] row-major, then b5[7],
+   then b4[7]. */
+void gco_dp5_tableau(double* out)
+{
+    for (int i = 0; i < 7; ++i)
+        for (int j = 0; j < 6; ++j) out[6 * i + j] = DP_A[i][j];
+    for (int i = 0; i < 7; ++i) { out[42 + i] = DP_B5[i]; out[49 + i] = DP_B4[i]; }
+}
+
 /* One DOPRI5 step of size h from u with k1 = f(u) given.  Writes the 5th
    order result, the 4th order result and k7 = f(result). */
 static void dp5_step(const oscene* s, const st4* u, const st4* k1, double h,

@@ -63,6 +63,7 @@ def lib():
                                               ctypes.c_int, ctypes.c_int, dp, dp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.gco_accel_jac.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.gco_dp5_tableau.argtypes = [dp]
         L.gco_trace_rays_tan.argtypes = [dp, dp, ctypes.c_long, dp, dp, dp, dp,
                                          ctypes.POINTER(ctypes.c_int), u64p, ctypes.c_int]
         L.gco_trace_rays_tan.restype = ctypes.c_int
@@ -158,6 +159,13 @@ def camera_rays(cam):
                 org[q], d[q] = camera_ray(cam, i, j, s)
                 q += 1
     return org, d
+
+
+def dp5_tableau():
+    """The oracle's Dormand-Prince tableau: (A 7 x 6, b5, b4)."""
+    out = np.zeros(56)
+    lib().gco_dp5_tableau(_dp(out))
+    return out[:42].reshape(7, 6), out[42:49], out[49:56]
 
 
 def sky(K, d):

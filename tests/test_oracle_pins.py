@@ -312,6 +312,62 @@ def test_sky_pattern():
         assert np.all(a >= np.minimum(Ca, Cb) - 1e-15) and np.all(a <= np.maximum(Ca, Cb) + 1e-15)
 
 
+@pytest.mark.parametrize("phi,th,c4,s8", [
+    (math.pi / 12, math.pi / 48, 0.5, 0.5),                  # cos(pi/3), sin(pi/6)
+    (math.pi / 16, -math.pi / 32, math.sqrt(0.5), -math.sqrt(0.5)),
+    (math.pi / 8, math.pi / 16, 0.0, 1.0),                   # on a square's edge in azimuth
+    (0.0, math.pi / 80, 1.0, math.sin(math.pi / 10)),
+    (-math.pi / 6, -math.pi / 24, -0.5, -math.sqrt(0.75)),
+])
+@pytest.mark.parametrize("K", [16.0, 2.5])
+def test_sky_smooth_values_at_known_angles(phi, th, c4, s8, K):
+    # finite sharpness: m = 1/2 + 1/2 tanh(K cos 4 phi) tanh(K sin 8 theta) at
+    # directions whose azimuth and elevation make cos 4 phi and sin 8 theta
+    # known numbers (a misplaced K, a wrong harmonic or swapped angles change
+    # the colour)
+    Ca, Cb = np.array([0.95, 0.85, 0.30]), np.array([0.10, 0.20, 0.55])
+    d = np.array([math.sin(phi) * math.cos(th), math.sin(th), -math.cos(phi) * math.cos(th)])
+    m = 0.5 + 0.5 * math.tanh(K * c4) * math.tanh(K * s8)
+    assert np.max(np.abs(O.sky(K, d) - (Cb + m * (Ca - Cb)))) < 1e-14
+
+
+def _rk_order_conditions(A, b, order):
+    """Residuals of the Runge-Kutta order conditions up to `order` (the rooted
+    trees up to order 5) for the tableau with stage matrix A (rows: stages 2
+    on) and weights b; c_i = sum_j a_ij."""
+    s = len(b)
+    a = np.zeros((s, s))
+    a[1:, :A.shape[1]] = A[1:s] if A.shape[0] >= s else A[1:]
+    c = a.sum(axis=1)
+    ac = a @ c
+    res = [b.sum() - 1, b @ c - 1 / 2]
+    if order >= 3:
+        res += [b @ c ** 2 - 1 / 3, b @ ac - 1 / 6]
+    if order >= 4:
+        res += [b @ c ** 3 - 1 / 4, b @ (c * ac) - 1 / 8, b @ (a @ c ** 2) - 1 / 12, b @ (a @ ac) - 1 / 24]
+    if order >= 5:
+        res += [b @ c ** 4 - 1 / 5, b @ (c ** 2 * ac) - 1 / 10, b @ (c * (a @ c ** 2)) - 1 / 15,
+                b @ (c * (a @ ac)) - 1 / 30, b @ ac ** 2 - 1 / 20, b @ (a @ c ** 3) - 1 / 20,
+                b @ (a @ (c * ac)) - 1 / 40, b @ (a @ (a @ c ** 2)) - 1 / 60, b @ (a @ (a @ ac)) - 1 / 120]
+    return np.array(res), c
+
+
+def test_dopri5_tableau_order_conditions():
+    # Dormand & Prince (1980): the propagated weights b satisfy every order
+    # condition up to 5, the embedded b* those up to 4 but not all of order 5
+    # (the difference is the error estimate), FSAL: the last row of A is b;
+    # the nodes are 0, 1/5, 3/10, 4/5, 8/9, 1, 1
+    A, b5, b4 = O.dp5_tableau()
+    r5, c = _rk_order_conditions(A, b5, 5)
+    assert np.max(np.abs(r5)) < 1e-15
+    r4, _ = _rk_order_conditions(A, b4, 4)
+    assert np.max(np.abs(r4)) < 1e-15
+    r45, _ = _rk_order_conditions(A, b4, 5)
+    assert np.max(np.abs(r45)) > 1e-4
+    assert np.allclose(c, [0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1, 1], atol=1e-15)
+    assert np.array_equal(A[6][:6], b5[:6]) and b5[6] == 0.0
+
+
 # --------------------------------------------------------------------------
 # Cross-correlation, eqs. (14), (15) at zero shift
 # --------------------------------------------------------------------------
