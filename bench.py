@@ -106,8 +106,9 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--workload", choices=["batch", "single", "stress", "grad", "paper"], default="batch")
-    p.add_argument("--autotune", choices=["on", "off"], default="on",
-                   help="off: skip the autotuner and use --h-max, --rtol32 (and --sched, single workload)")
+    p.add_argument("--autotune", choices=["recorded", "on", "off"], default="recorded",
+                   help="recorded: the autotuner's recorded choice for the workload (what the tests check); "
+                        "on: rerun the search; off: --h-max, --rtol32 (and --sched, single workload)")
     p.add_argument("--h-max", type=float, default=None, help="FP32 step cap with --autotune off")
     p.add_argument("--w-fallback", type=float, default=None,
                    help="FP64 hand-over threshold |1 + W| of the FP32 path (batch; default: the workload's)")
@@ -200,6 +201,10 @@ def main():
         ta = time.perf_counter() - ta
         print(f"# autotune {ta:.2f} s: rtol {tuned['rtol']} h_max {tuned['h_max']}, tune {rep['tune']}",
               file=sys.stderr, flush=True)
+    elif args.autotune == "recorded":
+        tuned, sched = W.single_timed_opts()
+        ctx.tune(**sched)
+        rep, ta = None, 0.0
     else:
         tuned = dict(op32, h_max=args.h_max if args.h_max is not None else op32["h_max"])
         if args.sched:
@@ -368,7 +373,7 @@ def main_batch(args):
     from paper_1012_5107_amd import workloads as W
 
     scenes, cams = W.batch_64()
-    op32 = W.opts("dopri5", rtol=args.rtol32)
+    op32 = W.batch_timed_opts() if args.autotune == "recorded" else W.opts("dopri5", rtol=args.rtol32)
     if args.autotune == "off" and args.h_max is not None:
         op32["h_max"] = args.h_max
     if args.w_fallback is not None:
@@ -429,7 +434,7 @@ def main_batch(args):
                    "rtol_fp64": op64["rtol"], "h_max_fp64": op64["h_max"], "rays": st["rays"],
                    "ray_steps": st["accepted_steps"]},
         "ray_steps_per_s": st["accepted_steps"] / dt,
-        "autotune": {"seconds": ta, "chosen_rtol": op32["rtol"], "chosen_h_max": op32["h_max"],
+        "autotune": {"mode": args.autotune, "seconds": ta, "chosen_rtol": op32["rtol"], "chosen_h_max": op32["h_max"],
                      "chosen_w_fallback": op32["w_fallback"], "chosen": rep.get("chosen", -1),
                      "passed": bool(rep["candidates"] and rep.get("chosen", -1) >= 0 and
                                     rep["candidates"][rep["chosen"]]["passed"]),
@@ -550,7 +555,43 @@ def main_stress(args):
                         "frac": achieved / PEAK_FP32, "traffic": _measured(TRAFFIC_K_WF_BOX_STRESS, (op32["rtol"],)),
                         "kernel": "k_wf_box<DOPRI5>", "kernel_ms": stg["hot_ms"], "kernel_steps": stg["hot_steps"]},
            "front_rays": stg["tail_rays"], "eager_hot_ms": stk["hot_ms"], "fp32_counters": stk}
+    if not args.no_cpu:
+        out["exit_direction_histogram"] = _stress_histogram(ctx, sc, cam, op32, W)
     print(json.dumps(out), flush=True)
+
+
+def _stress_histogram(ctx, sc, cam, op32, W, n=65536):
+    """Exit directions of n seeded samples of the stress render: the FP32
+    path against the oracle at the same options (the precision split's own
+    error), histogram over log bins 1e-16 .. 1 rad; samples whose status or
+    event count differs are counted apart (the exclusion set)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    rng = np.random.default_rng(20)
+    ii = rng.integers(0, cam["width"], n)
+    jj = rng.integers(0, cam["height"], n)
+    ss = rng.integers(0, cam["spp"], n)
+    org = np.zeros((n, 3))
+    d = np.zeros((n, 3))
+    for k in range(n):
+        org[k], d[k] = O.camera_ray(cam, ii[k], jj[k], ss[k])
+    t = time.perf_counter()
+    orc = O.trace_rays(sc, op32, org, d)
+    tc = time.perf_counter() - t
+    oo, od, st, steps, ev = ctx.trace_rays(sc, op32, torch.from_numpy(org), torch.from_numpy(d), prec="f32")
+    od, st, ev = od.cpu().numpy(), st.cpu().numpy(), ev.cpu().numpy()
+    a, b = od / np.linalg.norm(od, axis=1, keepdims=True), orc["dir"]
+    err = 2 * np.arctan2(np.linalg.norm(a - b, axis=1), np.linalg.norm(a + b, axis=1))
+    excl = (st != orc["status"]) | (ev != orc["events"]) | (orc["status"] != 0)
+    e = err[~excl]
+    edges = 10.0 ** np.arange(-16, 1)
+    h, _ = np.histogram(np.clip(e, 1e-16, 0.99), bins=edges)
+    return {"samples": n, "options": {k: op32[k] for k in ("rtol", "h_max", "w_fallback")},
+            "reference": "oracle (FP64) at the same options", "bin_edges_rad": [float(x) for x in edges],
+            "counts": [int(c) for c in h], "excluded": int(excl.sum()),
+            "p50": float(np.quantile(e, 0.5)), "p99": float(np.quantile(e, 0.99)), "max": float(e.max()),
+            "fraction_within_1e-4": float(np.mean(e <= 1e-4)), "oracle_seconds": tc}
 
 
 def main_grad(args):

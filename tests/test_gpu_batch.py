@@ -1,0 +1,74 @@
+"""The 64-scene batch at the options the benchmark times, against the oracle.
+
+The FP32 pipeline renders all 64 scenes in one launch.  On the 8
+lowest-index scenes (256^2, 512^2 and 1024^2 images, A k from 0.24 to 0.89)
+4096 seeded pixels are rendered by the oracle at the same options: the
+per-pixel colour error measures the FP32 arithmetic (bounds: 99th percentile
+5e-3 -- the 1e-4 rad direction tolerance times the sky's steepest rate of
+about 64 per radian; median 1e-5).  Every scene's zero-shift correlation C0
+(eq. (15)) is compared with the converged FP64 solve (rtol 1e-10).  Run on an
+MI355X (gfx950) only."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_1012_5107_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1012_5107_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def batch(B):
+    scenes, cams = W.batch_64()
+    op = W.batch_timed_opts()
+    ctx = B.context(0)
+    refs = [ctx.render(W.reference_scene(s), c, op, prec="f32")[0] for s, c in zip(scenes, cams)]
+    print(f"[batch] rendering 64 scenes at {op}", flush=True)
+    imgs, c0, st = ctx.render_batch(scenes, cams, op, refs=refs)
+    print(f"[batch] {st}", flush=True)
+    return scenes, cams, op, imgs, c0, refs, st
+
+
+def test_batch_pixels_match_oracle_on_the_lowest_scenes(B, batch):
+    scenes, cams, op, imgs, _, _, st = batch
+    worst = []
+    for i in range(8):
+        cam = cams[i]
+        pix = W.sample_pixels(cam["width"], cam["height"], 4096, seed=100 + i)
+        g_o, cnt = O.render(scenes[i], cam, op, pixels=pix)
+        g = imgs[i].cpu().numpy().reshape(-1, 3)[pix]
+        dpx = np.abs(g - g_o).max(axis=-1)
+        print(f"[batch scene {i}] {cam['width']}^2 Ak={scenes[i]['A'] * 6.283185307179586:.3f}: "
+              f"median {np.median(dpx):.2e} p99 {np.quantile(dpx, 0.99):.2e} max {dpx.max():.2e} "
+              f"oracle failed {cnt['failed']}", flush=True)
+        assert np.median(dpx) <= 1e-5
+        assert np.quantile(dpx, 0.99) <= 5e-3
+        worst.append(dpx.max())
+    assert st["failed"] < 1e-4 * st["rays"]
+
+
+def test_batch_c0_against_converged_fp64(B, batch):
+    scenes, cams, op, imgs, c0, refs, _ = batch
+    ctx = B.context(0)
+    opc = W.opts("dopri5", rtol=1e-10)
+    errs = []
+    for i, (s, c) in enumerate(zip(scenes, cams)):
+        g64, _ = ctx.render(s, c, opc, prec="f64")
+        ref_c0 = ctx.cross_correlate(g64, refs[i])[0]
+        errs.append(abs(c0[i] - ref_c0))
+    errs = np.array(errs)
+    order = np.argsort(-errs)[:5]
+    print("[batch C0] worst scenes: " + ", ".join(
+        f"{int(i)} ({cams[i]['width']}^2, Ak {scenes[i]['A'] * 6.283185307179586:.2f}): {errs[i]:.2e}"
+        for i in order) + f"; mean {errs.mean():.2e}", flush=True)
+    assert np.all(errs <= W.BATCH_C0_BOUND)

@@ -70,20 +70,26 @@ def test_stress_fp64_matches_oracle(B, rays):
     print("[stress fp64 histogram]", _histogram(err[~mask]), flush=True)
 
 
-@pytest.mark.parametrize("w_fallback", [1e-2, 0.15])
-def test_stress_fp32_against_fp64_oracle(B, rays, w_fallback):
-    # Above the grating |1 + W| >= 1 - A k = 0.058 here, so the FP64 fallback
-    # at |1 + W| < 1e-2 only serves stage points inside the metal; a wider
-    # threshold moves the crests' neighbourhood to FP64 as well
+@pytest.mark.parametrize("w_fallback,p99_factor,max_factor", [(1e-2, 30, 5000), (0.3, 1, 5000)])
+def test_stress_fp32_against_oracle(B, rays, w_fallback, p99_factor, max_factor):
+    # FP32 against the oracle at the same options, so that the comparison
+    # measures the precision split (the truncation error of the tolerance is
+    # the same on both sides).  Above the grating |1 + W| >= 1 - A k = 0.058
+    # here, so the FP64 hand-over at |1 + W| < 1e-2 only serves stage points
+    # inside the metal; near the crests FP32 resolves W to ~1e-6 relative,
+    # and over paths of thousands of steps near them the exit directions
+    # drift by up to ~3e-3 rad; a threshold of 0.3 hands the crests'
+    # neighbourhood to FP64 and meets the 1e-4 rad bound
     sc, cam, op, org, d = rays
-    op64 = dict(op, rtol=1e-8, atol=1e-8)
     op32 = dict(op, rtol=1e-7, atol=1e-7, w_fallback=w_fallback)
-    orc = O.trace_rays(sc, op64, org, d)
+    orc = O.trace_rays(sc, op32, org, d)
     od, st, steps, ev = _run(B, sc, op32, org, d, "f32")
-    err, mask, ill = check_directions(O, sc, op64, org, d, orc, od, st, ev, 1e-4, 1e-6,
-                                      f"stress fp32(1e-7, fallback {w_fallback})", max_ill=0.06, p99_factor=50,
-                                      max_factor=5000)
+    err, mask, ill = check_directions(O, sc, op32, org, d, orc, od, st, ev, 1e-4, 1e-6,
+                                      f"stress fp32(1e-7, fallback {w_fallback})", max_ill=0.06,
+                                      p99_factor=p99_factor, max_factor=max_factor)
+    good = ~mask & ~ill
     print(f"[stress fp32 histogram, fallback {w_fallback}]", _histogram(err[~mask]),
-          f"excluded={int(mask.sum())}", flush=True)
+          f"excluded={int(mask.sum())} ill={int(ill.sum())} within 1e-4: {np.mean(err[good] <= 1e-4):.4f}",
+          flush=True)
     _, stats = B.render(sc, dict(cam, width=128, height=128, spp=1), op32, prec="f32")
     print(f"[stress fp32 counters, fallback {w_fallback}]", stats, flush=True)
