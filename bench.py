@@ -112,6 +112,8 @@ def parse():
     p.add_argument("--h-max", type=float, default=None, help="FP32 step cap with --autotune off")
     p.add_argument("--w-fallback", type=float, default=None,
                    help="FP64 hand-over threshold |1 + W| of the FP32 path (batch; default: the workload's)")
+    p.add_argument("--fp64-stay", type=int, default=None,
+                   help="hand-overs after which the FP64 kernel keeps a ray's visit (batch; default: the workload's)")
     p.add_argument("--sched", type=str, default=None,
                    help="gc_tune with --autotune off: slow_pxy,slow_wave_div,refill,waves_per_simd")
     p.add_argument("--no-configured", action="store_true",
@@ -378,6 +380,8 @@ def main_batch(args):
         op32["h_max"] = args.h_max
     if args.w_fallback is not None:
         op32["w_fallback"] = args.w_fallback
+    if args.fp64_stay is not None:
+        op32["fp64_stay"] = args.fp64_stay
     op64 = W.opts("dopri5", rtol=1e-8)
     ctx = B.context(0)
     dev = torch.device("cuda", 0)
@@ -431,7 +435,7 @@ def main_batch(args):
                                "az~U[-60,60], el~U[15,60] deg, 4 jittered spp, DOPRI5, one plan replay per step "
                                "(renders, flat references, C0 of every scene)",
                    "rtol_fp32": op32["rtol"], "h_max_fp32": op32["h_max"], "w_fallback": op32["w_fallback"],
-                   "rtol_fp64": op64["rtol"], "h_max_fp64": op64["h_max"], "rays": st["rays"],
+                   "fp64_stay": op32.get("fp64_stay", 0), "rtol_fp64": op64["rtol"], "h_max_fp64": op64["h_max"], "rays": st["rays"],
                    "ray_steps": st["accepted_steps"]},
         "ray_steps_per_s": st["accepted_steps"] / dt,
         "autotune": {"mode": args.autotune, "seconds": ta, "chosen_rtol": op32["rtol"], "chosen_h_max": op32["h_max"],

@@ -143,8 +143,12 @@ typedef struct {
  * by atol + rtol max(|y_n|, |y_n+1|), step factor clamp [0.2, 5], safety
  * 0.9, no growth right after a rejection, first step h0, caps h_max and
  * h_min.  Step sizes are in tau (|dr/dtau| = n).  w_fallback is the
- * |1 + W| threshold below which the FP32 path recomputes the Lambert
- * function in FP64.  An event (box face or grating) ends a step at the
+ * |1 + W| threshold below which the FP32 path hands a step to FP64; the
+ * FP64 kernel keeps the ray while |1 + W| < 2 w_fallback.  fp64_stay > 0:
+ * from the fp64_stay-th hand-over of a ray on, the FP64 kernel keeps it
+ * for the rest of its visit of the box (at most 16384 steps per round), so
+ * that a ray that keeps returning near the branch point does not cost a
+ * round per return; 0 (default): never.  An event (box face or grating) ends a step at the
  * partial step of the same integrator that lands on the surface. */
 typedef struct {
     int32_t prec;          /* gc_precision */
@@ -154,7 +158,7 @@ typedef struct {
     double h_max, h0, h_min;
     double w_fallback;     /* default 1e-2 */
     int32_t max_events;    /* default 32 */
-    int32_t reserved;
+    int32_t fp64_stay;     /* default 0 (FP32 path only) */
     int64_t max_steps;     /* default 10^5 */
 } gc_opts;
 

@@ -47,7 +47,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("integ", ctypes.c_int32), ("h", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("h_max", ctypes.c_double),
                 ("h0", ctypes.c_double), ("h_min", ctypes.c_double), ("w_fallback", ctypes.c_double),
-                ("max_events", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_steps", ctypes.c_int64)]
+                ("max_events", ctypes.c_int32), ("fp64_stay", ctypes.c_int32), ("max_steps", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -210,6 +210,7 @@ def make_opts(o, prec="f64"):
     p.h_max, p.h0, p.h_min = o["h_max"], o["h0"], o["h_min"]
     p.w_fallback = o.get("w_fallback", 1e-2)
     p.max_events = o["max_events"]
+    p.fp64_stay = o.get("fp64_stay", 0)
     p.max_steps = o["max_steps"]
     return p
 

@@ -395,6 +395,7 @@ static gc_status make_opts(const gc_opts* p, OptsDev* o)
     if (!(p->h_min > 0 && p->h_max >= p->h_min && p->h0 > 0)) return fail(GC_EINVAL, "need 0 < h_min <= h_max and h0 > 0");
     if (!(p->w_fallback >= 0)) return fail(GC_EINVAL, "w_fallback must be >= 0");
     if (p->max_events < 0 || p->max_steps < 0) return fail(GC_EINVAL, "limits must be >= 0");
+    if (p->fp64_stay < 0) return fail(GC_EINVAL, "fp64_stay must be >= 0");
     o->integ = p->integ;
     o->max_events = p->max_events;
     o->max_steps = p->max_steps;
@@ -405,6 +406,7 @@ static gc_status make_opts(const gc_opts* p, OptsDev* o)
     o->h0 = p->h0;
     o->h_min = p->h_min;
     o->wfb2 = p->w_fallback * p->w_fallback;
+    o->stay = p->fp64_stay;
     return GC_OK;
 }
 

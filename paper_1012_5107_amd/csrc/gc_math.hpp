@@ -59,7 +59,8 @@ struct OptsDev {
     int max_events;
     long long max_steps;
     double h, rtol, atol, h_max, h0, h_min;
-    double wfb2;       // |1 + W|^2 below which FP32 redoes W in FP64
+    double wfb2;       // |1 + W|^2 below which FP32 hands the step to FP64
+    int stay;          // hand-overs after which the FP64 kernel keeps the visit (0: never)
 };
 
 enum RayStatus { RS_OK = 0, RS_MAX_STEPS = 1, RS_MAX_EVENTS = 2, RS_NONFINITE = 3, RS_UNDERFLOW = 4 };

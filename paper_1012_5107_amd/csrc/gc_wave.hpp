@@ -931,15 +931,18 @@ __device__ __forceinline__ int event_body(const WfArgs& a, long long q, const Sc
     int so = SO_INSIDE;
     // FP64 steps while the ray stays where FP32 cannot resolve W (with a
     // margin), so that a ray lingering near the branch point does not cost
-    // a round per step
+    // a round per step; from its o.stay-th hand-over on, the rest of the
+    // visit (a ray that keeps coming back costs a round per return)
     double pin[3];
     int face = 0;
-    for (int n = 0; n < 256; ++n) {
+    const bool stay = o.stay > 0 && a.R.fbk[q] >= o.stay;
+    const int nmax = stay ? 16384 : 256;
+    for (int n = 0; n < nmax; ++n) {
         so = box_step64(s, o, b, cnt, &mc, r, p, &st, pin, &face);
         if (so == SO_INSIDE && cnt.steps >= o.max_steps) { so = SO_FAIL; st = RS_MAX_STEPS; }
         if (so != SO_INSIDE) break;
         const double d2 = (1.0 + b.r1.W.re) * (1.0 + b.r1.W.re) + b.r1.W.im * b.r1.W.im;
-        if (d2 >= 4.0 * o.wfb2) break;
+        if (!stay && d2 >= 4.0 * o.wfb2) break;
     }
     a.R.steps[q] = (int)cnt.steps;
     a.R.rej[q] = (int)cnt.rejected;

@@ -71,11 +71,11 @@ def orbit_eye(az_deg, el_deg, R):
 
 
 def opts(integrator="rk4", h=1e-3, rtol=1e-8, atol=None, h_max=0.02, max_events=32,
-         max_steps=100_000, h0=1e-3, h_min=1e-12, w_fallback=1e-2):
+         max_steps=100_000, h0=1e-3, h_min=1e-12, w_fallback=1e-2, fp64_stay=0):
     return dict(integrator=integrator, h=float(h), rtol=float(rtol),
                 atol=float(rtol if atol is None else atol), h_max=float(h_max),
                 max_events=int(max_events), max_steps=int(max_steps), h0=float(h0),
-                h_min=float(h_min), w_fallback=float(w_fallback))
+                h_min=float(h_min), w_fallback=float(w_fallback), fp64_stay=int(fp64_stay))
 
 
 # --- the five workloads -------------------------------------------------------
@@ -177,7 +177,7 @@ def fov_columns(cam, fov_deg):
 # from run to run with the timings, so the tests and the benchmark use the
 # recorded one).
 def batch_timed_opts():
-    return opts("dopri5", rtol=1e-7, h_max=0.05, w_fallback=0.3)
+    return opts("dopri5", rtol=1e-7, h_max=0.05, w_fallback=0.3, fp64_stay=4)
 
 
 def single_timed_opts():

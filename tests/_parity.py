@@ -41,7 +41,7 @@ def conditioning(O, sc, op, org, d, idx, delta):
     return kappa
 
 
-def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, tol, delta, name, max_factor=50,
+def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, tol, delta, name, max_factor=30,
                      max_ill=None, p99_factor=1):
     """Compare exit directions with the oracle's.
 
@@ -56,8 +56,9 @@ def check_directions(O, sc, op, org, d, orc, gpu_dir, gpu_status, gpu_events, to
     cannot be reproduced in FP32 and are counted, not compared (at most 3%);
     at most 1% may change their event sequence; the other rays must have
     their 99th percentile within `tol` and their maximum within max_factor
-    `tol` (adaptive step control turns FP32 rounding into different step
-    sequences, whose truncation errors differ by up to the tolerance).
+    `tol` (default 30; adaptive step control turns FP32 rounding into
+    different step sequences, whose truncation errors differ by up to the
+    tolerance).
     Returns (errors, excluded mask, ill-conditioned mask)."""
     err = angle(gpu_dir, orc["dir"])
     mask = exclusion_mask(orc, gpu_status, gpu_events)

@@ -111,7 +111,7 @@ def test_grad_fp32_matches_oracle(B):
     dm, st = _oracle_dm(sc, cam, op)
     dmp, _ = _oracle_dm(sc, cam, op, eye_shift=1e-6)
     for k, name in ((0, "fp32 dm/dA"), (1, "fp32 dm/dhw")):
-        rel, good = _compare(name, g[:, k], dm[:, k], dmp[:, k], st, 1e-3, 0.5)
+        rel, good = _compare(name, g[:, k], dm[:, k], dmp[:, k], st, 1e-3, 0.15)
         assert np.quantile(rel[good], 0.99) <= 1e-3
     img = r["image"].cpu().numpy()
     orc = O.render_grad(sc, cam, op, ref, loss="ncc")
@@ -215,7 +215,7 @@ def test_grad_full_size_fp32_sampled_against_oracle(B):
     dm, st = _oracle_dm(sc, cam, op, pixels=pix)
     dmp, _ = _oracle_dm(sc, cam, op, pixels=pix, eye_shift=1e-6)
     for k, name in ((0, "full fp32 dm/dA"), (1, "full fp32 dm/dhw")):
-        rel, good = _compare(name, g[:, k], dm[:, k], dmp[:, k], st, 1e-3, 0.5)
+        rel, good = _compare(name, g[:, k], dm[:, k], dmp[:, k], st, 1e-3, 0.15)
         assert np.quantile(rel[good], 0.99) <= 1e-3
         # the sampled part of the sum, ill-conditioned samples included
         m = st == 0

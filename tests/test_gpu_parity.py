@@ -66,8 +66,8 @@ def test_trace_fp64_dopri5_matches_oracle(B):
     check_directions(O, sc, op64, org, d, orc, od, st, ev, 1e-10, 1e-15, "fp64 dopri5 48x48")
 
 
-@pytest.mark.parametrize("rtol32,max_factor", [(1e-5, 100), (1e-7, 50)])
-def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32, max_factor):
+@pytest.mark.parametrize("rtol32", [1e-5, 1e-7])
+def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32):
     # the oracle integrates with the same tolerance, so that the comparison
     # measures the FP32 arithmetic, not the step control; the error against a
     # converged reference is reported by the benchmark
@@ -77,8 +77,7 @@ def test_trace_fp32_dopri5_against_fp64_oracle(B, rtol32, max_factor):
     org, d = _camera_rays(cam)
     orc = O.trace_rays(sc, op, org, d)
     oo, od, st, steps, ev = _gpu_trace(B, sc, op, org, d, "f32")
-    check_directions(O, sc, op, org, d, orc, od, st, ev, 1e-4, 1e-6, f"fp32 dopri5({rtol32}) vs oracle 48x48",
-                     max_factor=max_factor)
+    check_directions(O, sc, op, org, d, orc, od, st, ev, 1e-4, 1e-6, f"fp32 dopri5({rtol32}) vs oracle 48x48")
 
 
 def _air_path_rays(hw, n, seed):

@@ -66,11 +66,11 @@ def test_stress_fp64_matches_oracle(B, rays):
           f"{np.quantile(orc['steps'], 0.99):.0f}/{orc['steps'].max()}", flush=True)
     od, st, steps, ev = _run(B, sc, op, org, d, "f64")
     err, mask, ill = check_directions(O, sc, op, org, d, orc, od, st, ev, 1e-10, 1e-15, "stress fp64",
-                                      max_ill=0.06)
+                                      max_ill=0.04)
     print("[stress fp64 histogram]", _histogram(err[~mask]), flush=True)
 
 
-@pytest.mark.parametrize("w_fallback,p99_factor,max_factor", [(1e-2, 30, 5000), (0.3, 1, 5000)])
+@pytest.mark.parametrize("w_fallback,p99_factor,max_factor", [(1e-2, 30, 1000), (0.3, 1, 30)])
 def test_stress_fp32_against_oracle(B, rays, w_fallback, p99_factor, max_factor):
     # FP32 against the oracle at the same options, so that the comparison
     # measures the precision split (the truncation error of the tolerance is
@@ -78,14 +78,17 @@ def test_stress_fp32_against_oracle(B, rays, w_fallback, p99_factor, max_factor)
     # here, so the FP64 hand-over at |1 + W| < 1e-2 only serves stage points
     # inside the metal; near the crests FP32 resolves W to ~1e-6 relative,
     # and over paths of thousands of steps near them the exit directions
-    # drift by up to ~3e-3 rad; a threshold of 0.3 hands the crests'
-    # neighbourhood to FP64 and meets the 1e-4 rad bound
+    # drift by up to ~3e-3 rad (p99; single rays 5e-2): at the threshold the
+    # configuration names (1e-2) the 1e-4 rad bound is missed, and this case
+    # records the histogram with bounds that only catch a regression.  A
+    # threshold of 0.3 hands the crests' neighbourhood to FP64 and meets the
+    # bound: p99 within 1e-4, every well-conditioned ray within 30 x 1e-4
     sc, cam, op, org, d = rays
     op32 = dict(op, rtol=1e-7, atol=1e-7, w_fallback=w_fallback)
     orc = O.trace_rays(sc, op32, org, d)
     od, st, steps, ev = _run(B, sc, op32, org, d, "f32")
     err, mask, ill = check_directions(O, sc, op32, org, d, orc, od, st, ev, 1e-4, 1e-6,
-                                      f"stress fp32(1e-7, fallback {w_fallback})", max_ill=0.06,
+                                      f"stress fp32(1e-7, fallback {w_fallback})", max_ill=0.04,
                                       p99_factor=p99_factor, max_factor=max_factor)
     good = ~mask & ~ill
     print(f"[stress fp32 histogram, fallback {w_fallback}]", _histogram(err[~mask]),
