@@ -169,7 +169,7 @@ typedef struct {
     int64_t events;          /* box entries/exits, internal reflections, grating contacts */
     int64_t fallbacks;       /* FP32 path: steps handed to FP64 because a stage needed it */
     int64_t failed;          /* samples with status != GC_RAY_OK */
-    int64_t fp64_steps;      /* FP32 path: accepted steps taken by the FP64 event kernel (rounds) */
+    int64_t fp64_steps;      /* FP32 path: accepted in-box steps taken in FP64 (hand-overs) */
     int64_t rounds;          /* FP32 path: in-cloak / event rounds */
     int64_t tail_rays;       /* batch plan: rays put at the front of the first round's queue */
     int64_t hot_steps;       /* FP32 path: accepted steps taken by the FP32 in-cloak kernel */
@@ -182,9 +182,9 @@ typedef struct {
 
 typedef struct gc_ctx gc_ctx;
 
-/* Scheduling of the FP32 pipeline's in-cloak kernel, per context.  It
- * changes only which lane integrates which ray and when: every ray's result
- * is the same for any setting.  The in-cloak kernel is persistent: each
+/* Scheduling of the FP32 pipeline, per context.  It changes only which
+ * lane integrates which ray and when: every ray's result is the same for
+ * any setting.  The in-cloak kernel is persistent: each
  * wave takes rays from queues of box entries, one visit of the box at a
  * time, and a visit cannot be split, so the longest visits bound the
  * length of a launch unless they start early and run fast.
@@ -197,13 +197,19 @@ typedef struct gc_ctx gc_ctx;
  *   refill          a wave claims new rays once at least this many of its
  *                   64 lanes are idle (1 .. 64)
  *   waves_per_simd  resident waves per SIMD of the in-cloak kernel
- *                   (1 .. 8; 0: as many as fit) */
+ *                   (1 .. 8; 0: as many as fit)
+ *   plan_lanes      a batch plan made while this is G >= 2 splits its
+ *                   scenes into G groups (balanced by sample count), each
+ *                   with its own queues, rounds and graphs on a stream of
+ *                   its own, so that the long serial tail of one group
+ *                   (its last visits and FP64 hand-overs) overlaps the work
+ *                   of the others (0 or 1: one pipeline; at most 3) */
 typedef struct {
     double slow_pxy;
     int32_t slow_wave_div;
     int32_t refill;
     int32_t waves_per_simd;
-    int32_t reserved;
+    int32_t plan_lanes;
 } gc_tune;
 
 /* Create a context on HIP device `hip_device` (made current for the call).
@@ -227,7 +233,8 @@ void gc_default_tune(gc_tune* tune);
 
 /* Set / read the context's scheduling.  GC_EINVAL for a null pointer or a
  * value out of range (slow_pxy outside [0, 1], slow_wave_div < 0, refill
- * outside 1 .. 64, waves_per_simd outside 0 .. 8). */
+ * outside 1 .. 64, waves_per_simd outside 0 .. 8, plan_lanes outside
+ * 0 .. 3). */
 gc_status gc_set_tune(gc_ctx* ctx, const gc_tune* tune);
 gc_status gc_get_tune(const gc_ctx* ctx, gc_tune* tune);
 
@@ -279,7 +286,7 @@ void gc_batch_plan_destroy(gc_batch_plan* plan);
  *     others, the fraction whose status or event count differs from the
  *     reference must be at most max_changed, and the rest must have their
  *     99th percentile angle error at most dir_tol and their maximum at most
- *     50 dir_tol;
+ *     30 dir_tol;
  *   - the zero-shift correlation C0 (eq. (15)) of the image at
  *     width / cc_scale x height / cc_scale against the flat-mirror
  *     reference must be within cc_tol of the FP64 image's (with

@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("slow_pxy", ctypes.c_double), ("slow_wave_div", ctypes.c_int32), ("refill", ctypes.c_int32),
-                ("waves_per_simd", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("waves_per_simd", ctypes.c_int32), ("plan_lanes", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

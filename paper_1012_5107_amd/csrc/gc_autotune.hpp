@@ -324,7 +324,7 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
             cand.dir_max = mx;
             cand.changed = chg;
             cand.cc_err = cce;
-            cand.pass = p99 <= at.dir_tol && mx <= 50.0 * at.dir_tol && chg <= at.max_changed && cce <= at.cc_tol;
+            cand.pass = p99 <= at.dir_tol && mx <= 30.0 * at.dir_tol && chg <= at.max_changed && cce <= at.cc_tol;
             if (cand.pass && cand.ms < best_ms) {
                 best_ms = cand.ms;
                 rep.chosen = rep.n_cand - 1;
@@ -386,6 +386,7 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
             t.slow_wave_div = (int32_t)s[1];
             t.refill = (int32_t)s[2];
             t.waves_per_simd = (int32_t)s[3];
+            t.plan_lanes = entry.plan_lanes;   // batch plans only
             ctx->tune = t;
             double ms = 0.0;
             if ((r = time_workload(*opts_out, &ms, nullptr)) != GC_OK) return r;

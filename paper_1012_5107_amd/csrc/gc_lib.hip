@@ -173,6 +173,9 @@ static unsigned flat_blocks(int n_cu, long long npx)
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
+// concurrent sub-pipelines of a batch plan (gc_tune.plan_lanes)
+constexpr int kPlanMaxLanes = 3;
+
 // Device buffers of the FP32 pipeline, grown on demand.
 struct WfStore {
     long long cap_rays = 0;
@@ -797,7 +800,6 @@ static gc_status wf_rounds(gc_ctx* ctx, WfStore& w, WfArgs& a, unsigned len, hip
         HIP_OK(hipEventElapsedTime(&t2, w.ev[2], w.ev[3]));
         w.hot_ms += t1;
         w.event_ms += t2;
-        w.fp64_steps += w.h_ctr->ev_len;
         w.rounds += 1;
         len = w.h_ctr->box_len[cur ^ 1] + w.h_ctr->slow_len[cur ^ 1];
         if (round > 100000) return fail(GC_EDEVICE, "pipeline did not drain");
@@ -860,7 +862,8 @@ static gc_status wf_read_totals(WfStore& w, gc_stats* st, hipStream_t stream)
         st->events = (int64_t)h.events;
         st->fallbacks = (int64_t)h.fallbacks;
         st->failed = (int64_t)h.failed;
-        st->fp64_steps = w.fp64_steps;
+        // the in-box steps the FP32 kernel did not take: the FP64 event kernel's
+        st->fp64_steps = (int64_t)h.steps - (int64_t)w.h_ctr->hot_steps;
         st->rounds = w.rounds;
         st->hot_ms = w.hot_ms;
         st->event_ms = w.event_ms;
@@ -1045,8 +1048,8 @@ static gc_status set_tune_impl(gc_ctx* ctx, const gc_tune* t)
     if (t->slow_wave_div < 0) return fail(GC_EINVAL, "slow_wave_div must be >= 0");
     if (t->refill < 1 || t->refill > 64) return fail(GC_EINVAL, "refill must be in 1 .. 64");
     if (t->waves_per_simd < 0 || t->waves_per_simd > 8) return fail(GC_EINVAL, "waves_per_simd must be in 0 .. 8");
+    if (t->plan_lanes < 0 || t->plan_lanes > kPlanMaxLanes) return fail(GC_EINVAL, "plan_lanes must be in 0 .. 3");
     ctx->tune = *t;
-    ctx->tune.reserved = 0;
     return GC_OK;
 }
 

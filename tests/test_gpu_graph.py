@@ -104,3 +104,42 @@ def test_plan_front_of_queue_replays_match_eager(B, tune):
             plan.close()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_plan_lanes_replays_match_eager_batch(B, lanes):
+    """A plan split into concurrent sub-pipelines (gc_tune.plan_lanes): each
+    group of scenes runs on a stream of its own; every replay reproduces the
+    eager batch bit for bit, and the counters add up to the eager run's."""
+    scenes, cams, op = _workload()
+    ctx = B.Context(0)
+    try:
+        refs_e = [ctx.render(W.reference_scene(s), c, op, prec="f32")[0] for s, c in zip(scenes, cams)]
+        imgs_e, c0_e, st_e = ctx.render_batch(scenes, cams, op, refs=refs_e)
+        ctx.tune(plan_lanes=lanes)
+        outs = [torch.full_like(i, float("nan")) for i in imgs_e]
+        refs = [torch.full_like(r, float("nan")) for r in refs_e]
+        plan = ctx.batch_plan(scenes, cams, op, outs, refs=refs, render_refs=True)
+        try:
+            for rep in range(3):
+                for t in outs + refs:
+                    t.fill_(float("nan"))
+                torch.cuda.synchronize()
+                plan.launch()
+                c0, st = plan.results()
+                for a, b in zip(outs, imgs_e):
+                    assert torch.equal(a, b), rep
+                for a, b in zip(refs, refs_e):
+                    assert torch.equal(a, b), rep
+                assert c0 == c0_e, rep
+                for k in ("rays", "accepted_steps", "rejected_steps", "events", "failed", "fallbacks"):
+                    assert st[k] == st_e[k], (rep, k)
+                assert 0 < st["hot_ms"] <= st["total_ms"]
+                ctx.render(scenes[1], cams[1], op, prec="f32")
+                torch.cuda.synchronize()
+        finally:
+            plan.close()
+        with pytest.raises(B.GcError):
+            ctx.tune(plan_lanes=4)
+    finally:
+        ctx.close()

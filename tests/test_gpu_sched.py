@@ -37,7 +37,7 @@ def test_render_identical_under_every_schedule(B, integ):
         base_img, base_st = None, None
         for s in SETTINGS:
             got = ctx.tune(**s)
-            assert got == s
+            assert {k: got[k] for k in s} == s
             img, st = ctx.render(sc, cam, op, prec="f32")
             torch.cuda.synchronize()
             keys = ("rays", "accepted_steps", "rejected_steps", "events", "failed", "fallbacks", "fp64_steps")
@@ -56,7 +56,8 @@ def test_tune_rejects_out_of_range(B):
     try:
         default = ctx.tune()
         for bad in (dict(slow_pxy=-0.1), dict(slow_pxy=1.5), dict(slow_wave_div=-1), dict(refill=0),
-                    dict(refill=65), dict(waves_per_simd=9), dict(waves_per_simd=-1)):
+                    dict(refill=65), dict(waves_per_simd=9), dict(waves_per_simd=-1), dict(plan_lanes=-1),
+                    dict(plan_lanes=4)):
             with pytest.raises(B.GcError):
                 ctx.tune(**bad)
             assert ctx.tune() == default
