@@ -59,20 +59,19 @@ FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 # every entry stale and the bench reports null instead.
 KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_wave.hpp", "paper_1012_5107_amd/csrc/gc_lane32.hpp",
                   "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp"]
-MEASURED_SHA = "22e0f8705844edca"
+MEASURED_SHA = "5b7cd5643c13161f"
 # 512 x 512 x 4 workload, keyed by (rtol, h_max, integrator)
-# (profiles/k_wf_box_dopri5_512x512x4_tuned.txt)
-TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.04e8, (3e-7, 0.2, "dopri5"): 5.02e8, (3e-7, 0.1, "dopri5"): 4.96e8,
-                    (1e-7, 0.5, "dopri5"): 4.99e8, (1e-7, 0.2, "dopri5"): 4.99e8, (1e-7, 0.1, "dopri5"): 4.95e8}
+TRAFFIC_K_WF_BOX = {}
 # the 64-scene batch, summed over the pipeline rounds of one render, keyed by
 # (rtol, h_max, w_fallback) (profiles/k_wf_box_dopri5_batch64.txt)
-TRAFFIC_K_WF_BOX_BATCH = {(1e-7 / 3, 0.1, 1e-2): 5.83e10, (1e-7, 0.02, 1e-2): 5.61e10}
+TRAFFIC_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): 6.28e10}
 # the 1024 x 1024 x 8 stress render, summed over its rounds, keyed by rtol
-# (profiles/k_wf_box_dopri5_1024x1024x8_stress.txt)
-TRAFFIC_K_WF_BOX_STRESS = {(1e-7,): 3.03e9}
-# SQ_INSTS_VALU_FLOPS_FP32 per launch (wave-level), same keys as the traffic
+TRAFFIC_K_WF_BOX_STRESS = {}
+# SQ_INSTS_VALU_FLOPS_FP32 per render (wave-level: 2 FMA + MUL + ADD + TRANS
+# instructions), same keys as the traffic, and the VALU lane utilisation
+# SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) of the same launches
 VALU_FLOPS_K_WF_BOX = {}
-VALU_FLOPS_K_WF_BOX_BATCH = {}
+VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.645e11, 0.774)}
 
 
 def _kernel_sha():
@@ -105,6 +104,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-converged", action="store_true",
+                   help="batch: skip the converged FP64 reference (rtol 1e-10) the C0 errors are taken against")
     p.add_argument("--workload", choices=["batch", "single", "stress", "grad", "paper"], default="batch")
     p.add_argument("--autotune", choices=["recorded", "on", "off"], default="recorded",
                    help="recorded: the autotuner's recorded choice for the workload (what the tests check); "
@@ -440,8 +441,10 @@ def main_batch(args):
         "ray_steps_per_s": st["accepted_steps"] / dt,
         "autotune": {"mode": args.autotune, "seconds": ta, "chosen_rtol": op32["rtol"], "chosen_h_max": op32["h_max"],
                      "chosen_w_fallback": op32["w_fallback"], "chosen": rep.get("chosen", -1),
-                     "passed": bool(rep["candidates"] and rep.get("chosen", -1) >= 0 and
-                                    rep["candidates"][rep["chosen"]]["passed"]),
+                     # recorded: the search's passing choice (tests/test_gpu_batch.py checks it;
+                     # cc_error_vs_converged_fp64 below measures it again)
+                     "passed": (bool(rep["candidates"][rep["chosen"]]["passed"])
+                                if rep["candidates"] and rep.get("chosen", -1) >= 0 else None),
                      "candidates": [{k: c[k] for k in ("rtol", "h_max", "w_fallback", "ms", "steps", "dir_p99",
                                                        "dir_max", "changed", "cc_err", "passed") if k in c}
                                     for c in rep["candidates"]]},
@@ -450,8 +453,14 @@ def main_batch(args):
                      "traffic": _measured(TRAFFIC_K_WF_BOX_BATCH, key),
                      "kernel": "k_wf_box<DOPRI5>", "kernel_ms": st["hot_ms"], "kernel_steps": st["hot_steps"],
                      "flop_per_step": FLOP_PER_STEP["dopri5"],
+                     # executed FP32 FLOP from the counters (rejected steps, location
+                     # trials and bookkeeping included): wave-level count x 64 lanes x
+                     # the lane utilisation, over the same kernel time
                      "valu_flops_counter": None if vf is None else {
-                         "SQ_INSTS_VALU_FLOPS_FP32": vf, "tflops_full_wave": 64 * vf / (st["hot_ms"] * 1e-3) / 1e12}},
+                         "SQ_INSTS_VALU_FLOPS_FP32": vf[0], "lane_utilisation": vf[1],
+                         "tflops_executed": 64 * vf[0] * vf[1] / (st["hot_ms"] * 1e-3) / 1e12,
+                         "frac_executed": 64 * vf[0] * vf[1] / (st["hot_ms"] * 1e-3) / PEAK_FP32,
+                         "profile": "profiles/k_wf_box_dopri5_batch64.txt"}},
         "fp32_breakdown": dict({k: st[k] for k in ("hot_ms", "event_ms", "total_ms", "rounds")},
                                fp64_steps=stk["fp64_steps"], fallbacks=stk["fallbacks"], failed=stk["failed"],
                                front_rays=st["tail_rays"], eager_pass_hot_ms=stk["hot_ms"]),
@@ -482,20 +491,23 @@ def main_batch(args):
         # paths against it
         opc = W.opts("dopri5", rtol=1e-10)
         for i, (s, c) in enumerate(zip(scenes, cams)):
+            if args.no_converged:
+                break
             gc_, _ = ctx.render(s, c, opc, prec="f64")
             ccc = ctx.cross_correlate(gc_, refs[i])[0]
             per[i].update(c0_converged=ccc, c0_err_vs_converged=abs(c0[i] - ccc),
                           c0_err_fp64_plain_vs_converged=abs(per[i]["c0_fp64"] - ccc))
         errs = [p["c0_err"] for p in per]
-        errc = [p["c0_err_vs_converged"] for p in per]
-        err64 = [p["c0_err_fp64_plain_vs_converged"] for p in per]
+        errc = [p.get("c0_err_vs_converged", float("nan")) for p in per]
+        err64 = [p.get("c0_err_fp64_plain_vs_converged", float("nan")) for p in per]
         out["fp64_plain"] = {"ray_steps_per_s": s64 / t64, "rays_per_s": r64 / t64, "ms": t64 * 1e3,
                              "ray_steps": s64, "note": "one FP64 launch per scene, DOPRI5 rtol 1e-8, h_max 0.02"}
         out["cc_error_fp32_vs_fp64"] = {"max": max(errs), "mean": float(np.mean(errs)),
                                         "scenes_within_1e-4": int(sum(e <= 1e-4 for e in errs)),
                                         "worst_scene": int(np.argmax(errs))}
-        out["cc_error_vs_converged_fp64"] = {
-            "reference": "FP64 DOPRI5 rtol 1e-10, h_max 0.02, per scene",
+        out["cc_error_vs_converged_fp64"] = None if args.no_converged else {
+            "reference": "FP64 DOPRI5 rtol 1e-10, h_max 0.02, per scene", "bound": 1e-4,
+            "bound_met": bool(max(errc) <= W.BATCH_C0_BOUND),
             "fp32_batch": {"max": max(errc), "mean": float(np.mean(errc)),
                            "scenes_within_1e-4": int(sum(e <= 1e-4 for e in errc)), "worst_scene": int(np.argmax(errc))},
             "fp64_plain": {"max": max(err64), "mean": float(np.mean(err64)),
@@ -561,6 +573,9 @@ def main_stress(args):
            "front_rays": stg["tail_rays"], "eager_hot_ms": stk["hot_ms"], "fp32_counters": stk}
     if not args.no_cpu:
         out["exit_direction_histogram"] = _stress_histogram(ctx, sc, cam, op32, W)
+        # the same samples with the FP64 hand-over at |1 + W| < 0.3, the
+        # threshold at which the 1e-4 rad bound is met (untimed)
+        out["exit_direction_histogram_w_fallback_0.3"] = _stress_histogram(ctx, sc, cam, dict(op32, w_fallback=0.3), W)
     print(json.dumps(out), flush=True)
 
 
@@ -585,7 +600,8 @@ def _stress_histogram(ctx, sc, cam, op32, W, n=65536):
     tc = time.perf_counter() - t
     oo, od, st, steps, ev = ctx.trace_rays(sc, op32, torch.from_numpy(org), torch.from_numpy(d), prec="f32")
     od, st, ev = od.cpu().numpy(), st.cpu().numpy(), ev.cpu().numpy()
-    a, b = od / np.linalg.norm(od, axis=1, keepdims=True), orc["dir"]
+    nrm = np.linalg.norm(od, axis=1, keepdims=True)
+    a, b = od / np.where(nrm > 0, nrm, 1.0), orc["dir"]   # failed rays (zero direction) are excluded below
     err = 2 * np.arctan2(np.linalg.norm(a - b, axis=1), np.linalg.norm(a + b, axis=1))
     excl = (st != orc["status"]) | (ev != orc["events"]) | (orc["status"] != 0)
     e = err[~excl]

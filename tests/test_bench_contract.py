@@ -44,14 +44,15 @@ def test_traffic_tables_resolve_the_options_the_benchmark_uses(monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     monkeypatch.setattr(bench, "MEASURED_SHA", bench._kernel_sha())
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX, (3 * 1e-7, 0.5, "dopri5")) is not None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX, (3e-7, 0.5, "rk4")) is None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7 / 3, 0.1, 1e-2)) is not None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.02, 1e-2)) is not None
+    # the batch's recorded options, formed as the autotuner forms them
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (3 * (1e-7 / 3), 0.05, 0.3)) is not None
     assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.02, 0.3)) is None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (1e-7,)) is not None
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (3e-7,)) is None
-    for table in (bench.TRAFFIC_K_WF_BOX, bench.TRAFFIC_K_WF_BOX_BATCH, bench.TRAFFIC_K_WF_BOX_STRESS):
-        assert all(isinstance(k, tuple) and v > 0 for k, v in table.items())
+    assert bench._measured(bench.VALU_FLOPS_K_WF_BOX_BATCH, (1e-7, 0.05, 0.3)) is not None
+    tables = (bench.TRAFFIC_K_WF_BOX, bench.TRAFFIC_K_WF_BOX_BATCH, bench.TRAFFIC_K_WF_BOX_STRESS,
+              bench.VALU_FLOPS_K_WF_BOX, bench.VALU_FLOPS_K_WF_BOX_BATCH)
+    for table in tables:
+        for k, v in table.items():
+            assert isinstance(k, tuple) and bench._measured(table, k) is not None
+            assert (v[0] if isinstance(v, tuple) else v) > 0
     monkeypatch.setattr(bench, "MEASURED_SHA", "0" * 16)
-    assert bench._measured(bench.TRAFFIC_K_WF_BOX_STRESS, (1e-7,)) is None
+    assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.05, 0.3)) is None
