@@ -60,17 +60,19 @@ FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_wave.hpp", "paper_1012_5107_amd/csrc/gc_lane32.hpp",
                   "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp"]
 MEASURED_SHA = "5b7cd5643c13161f"
-# 512 x 512 x 4 workload, keyed by (rtol, h_max, integrator)
-TRAFFIC_K_WF_BOX = {}
+# 512 x 512 x 4 workload, per launch, keyed by (rtol, h_max, integrator)
+# (profiles/k_wf_box_dopri5_512x512x4_tuned.txt)
+TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.03e8}
 # the 64-scene batch, summed over the pipeline rounds of one render, keyed by
 # (rtol, h_max, w_fallback) (profiles/k_wf_box_dopri5_batch64.txt)
 TRAFFIC_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): 6.28e10}
 # the 1024 x 1024 x 8 stress render, summed over its rounds, keyed by rtol
-TRAFFIC_K_WF_BOX_STRESS = {}
+# (profiles/k_wf_box_dopri5_1024x1024x8_stress.txt)
+TRAFFIC_K_WF_BOX_STRESS = {(1e-7,): 3.03e9}
 # SQ_INSTS_VALU_FLOPS_FP32 per render (wave-level: 2 FMA + MUL + ADD + TRANS
 # instructions), same keys as the traffic, and the VALU lane utilisation
 # SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) of the same launches
-VALU_FLOPS_K_WF_BOX = {}
+VALU_FLOPS_K_WF_BOX = {(3e-7, 0.5, "dopri5"): (1.925e9, 0.627)}
 VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.645e11, 0.774)}
 
 
@@ -185,11 +187,18 @@ def main():
 
     def roofline(st, op):
         achieved = st["hot_steps"] * FLOP_PER_STEP[op["integrator"]] / (st["hot_ms"] * 1e-3)
+        key = (op["rtol"], op["h_max"], op["integrator"])
+        vf = _measured(VALU_FLOPS_K_WF_BOX, key)
         return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32,
-                "traffic": _measured(TRAFFIC_K_WF_BOX, (op["rtol"], op["h_max"], op["integrator"])),
+                "traffic": _measured(TRAFFIC_K_WF_BOX, key),
                 "kernel": "k_wf_box<DOPRI5>" if op["integrator"] == "dopri5" else "k_wf_box<RK4>",
-                "kernel_ms": st["hot_ms"], "kernel_steps": st["hot_steps"]}
+                "kernel_ms": st["hot_ms"], "kernel_steps": st["hot_steps"],
+                "valu_flops_counter": None if vf is None else {
+                    "SQ_INSTS_VALU_FLOPS_FP32": vf[0], "lane_utilisation": vf[1],
+                    "tflops_executed": 64 * vf[0] * vf[1] / (st["hot_ms"] * 1e-3) / 1e12,
+                    "frac_executed": 64 * vf[0] * vf[1] / (st["hot_ms"] * 1e-3) / PEAK_FP32,
+                    "profile": "profiles/k_wf_box_dopri5_512x512x4_tuned.txt"}}
 
     # the configured step control with the default scheduling
     ctx.tune(**B.default_tune())

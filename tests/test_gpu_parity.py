@@ -286,3 +286,35 @@ def test_render_batch_errors(B):
     with pytest.raises(B.GcError) as e:
         B.context(0).render_batch([dict(scenes[0], A=0.5), scenes[1]], cams, op)
     assert e.value.status == B.GC_EDOMAIN
+
+
+@pytest.mark.parametrize("A", [0.02, 0.1])
+def test_fp32_grating_contacts_against_oracle(B, A):
+    """The FP32 in-box kernel locates grating contacts in FP32 (regula falsi
+    on the partial step, to 2e-7 of the step) and reflects about the normal
+    (-Im W, 1 + Re W) from the FP32 W; the FP64 path and the oracle locate
+    them in FP64.  A camera above a wide box sees only contacts inside the
+    box; with a weak cloak (A = 0.02) the integration error between contacts
+    is small, so the exit direction of a ray with one contact measures the
+    contact's own error.  FP32 against the oracle at the same options, by
+    number of contacts: every group's 99th percentile within 1e-5 rad (a
+    tenth of the FP32 tolerance)."""
+    sc = W.scene(A=A, half_width=4.0)
+    cam = W.camera(96, 96, spp=1, jitter=True, seed=7, eye=(0.3, 3.0, 1.2), fov_y_deg=30.0)
+    op = W.opts("dopri5", rtol=1e-7, h_max=0.05)
+    org, d = _camera_rays(cam)
+    orc = O.trace_rays(sc, op, org, d)
+    oo, od, st, steps, ev = _gpu_trace(B, sc, op, org, d, "f32")
+    err = angle(od, orc["dir"])
+    same = (st == 0) & (orc["status"] == 0) & (ev == orc["events"])
+    # paths that stay in the box: in through the top, its contacts, out through the top
+    inside = (orc["events"] == orc["contacts"] + 2) & (np.abs(orc["org"][:, 0]) < 4.0 - 1e-9)
+    for k in (1, 2, 3):
+        g = same & inside & ((orc["contacts"] == k) if k < 3 else (orc["contacts"] >= k))
+        if g.sum() < 50:
+            continue
+        e = err[g]
+        print(f"[fp32 contacts A={A}] {'>=' if k == 3 else ''}{k} contact(s): n={int(g.sum())} "
+              f"median {np.median(e):.2e} p99 {np.quantile(e, 0.99):.2e} max {e.max():.2e}", flush=True)
+        assert np.quantile(e, 0.99) <= 1e-5
+    assert (~same).sum() <= 0.01 * same.size
