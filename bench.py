@@ -715,7 +715,7 @@ def main_grad(args):
 
 
 # Table 1 of the paper (Sec. 5): C(0, 0) in % for FOV 0/10/25/50 deg, the
-# grating rows (the Gaussian-cloak rows need a map this build does not have).
+# grating rows (the Gaussian-cloak rows need an implicit coordinate map that is not implemented here).
 # Measured there on the photograph of Fig. 2 (a): context, not a target.
 PAPER_TABLE1 = {("3a", "3b"): (-20, -1, 7, 6), ("3a", "3c"): (99, 91, 73, 51), ("5a", "5b"): (17, 2, 8, 8),
                 ("5a", "5c"): (97, 91, 76, 55), ("3a", "5c"): (74, 60, 40, 28), ("6a", "6b"): (25, 4, 10, 9),
