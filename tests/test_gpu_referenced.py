@@ -183,3 +183,35 @@ def test_unsupported_combinations(B):
     with pytest.raises(B.GcError) as e:
         B.render(dict(W.paper_scene("flat"), backdrop_period=0.0), cam, OP64)
     assert e.value.status == B.GC_EINVAL
+
+
+def test_paper_table1_trends(B):
+    """The trends of Table 1 (Sec. 5) on the paper's scene at full size (FP32, Fresnel faces, the
+    procedural backdrop plane in place of the photograph, so only the trends are compared):
+    the cloak's image against the flat mirror (3a/3c) correlates nearly perfectly in the centre
+    strip and less with every wider field of view, and far better than the bare grating's
+    (3a/3b) at every field of view; the same holds for the referenced cloak of height 1.1
+    against its reference, the plate on the mirror (5a/5c), versus the plate on the grating
+    (5a/5b)."""
+    cam = W.paper_camera()
+    op = W.opts("dopri5", rtol=1e-7, h_max=0.02)
+    names = {"3a": W.paper_scene("flat"), "3b": W.paper_scene("grating"), "3c": W.paper_scene("cloak", 1.1),
+             "5a": W.paper_scene("plate", 1.1), "5b": W.paper_scene("plate_grating", 1.1),
+             "5c": W.paper_scene("referenced", 1.1)}
+    img = {n: B.render(s, cam, op, prec="f32")[0] for n, s in names.items()}
+
+    def c00(f, g):
+        out = []
+        for fov in W.PAPER_FOVS:
+            c0, c1 = W.fov_columns(cam, fov)
+            m, _, _, _ = B.cross_correlate_map(img[g], img[f], 0, 0, cols=(c0, c1))
+            out.append(float(m[0, 0]))
+        return np.array(out)
+
+    for ref, good, bare in (("3a", "3c", "3b"), ("5a", "5c", "5b")):
+        cg, cb = c00(ref, good), c00(ref, bare)
+        print(f"[table 1] {ref}/{good} {np.round(100 * cg, 1)}  {ref}/{bare} {np.round(100 * cb, 1)} "
+              f"(FOV {W.PAPER_FOVS} deg)", flush=True)
+        assert cg[0] >= 0.95
+        assert np.all(np.diff(cg) <= 0.0)
+        assert np.all(cg > cb + 0.2)
