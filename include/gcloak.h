@@ -293,9 +293,9 @@ void gc_batch_plan_destroy(gc_batch_plan* plan);
  *     cc_scale = 1 the timed full-size renders are the ones checked).
  * Candidates (DOPRI5): rtol x {3, 1, 1/3} times h_max x {1, 2.5, 5,
  * 10, 25} (RK4 keeps its step: one candidate), at FP64 hand-over
- * thresholds w_fallback in {the given one, 0.1, 0.3}: the larger levels
- * are tried, in that order, only while no candidate has passed (at most 45
- * candidates).  Of the candidates that pass, the one with the shortest FP32 render of the whole workload is
+ * thresholds w_fallback in {the given one, 0.1, 0.3}: after the given
+ * one, the levels of 0.1 and 0.3 that exceed it are tried, in increasing
+ * order, only while no candidate has passed (at most 45 candidates).  Of the candidates that pass, the one with the shortest FP32 render of the whole workload is
  * chosen (best of `reps`); if none passes, the fastest that is nowhere less
  * accurate than the options as given (see `chosen`); then, if tune_sched, a fixed set of gc_tune
  * settings is timed the same way and the fastest is installed in the

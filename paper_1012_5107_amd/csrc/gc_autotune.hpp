@@ -262,18 +262,18 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
     // the third lever: near the crests of a high-amplitude grating FP32
     // cannot resolve W (the Halley residual W - Z e^-W loses its leading
     // digits as |1 + W| shrinks), so a larger threshold hands more steps to
-    // FP64.  Threshold levels are tried in order (the given one first) and
-    // the search stops after the first level at which a candidate passes.
+    // FP64.  The given threshold is tried first, then those of 0.1 and 0.3
+    // that exceed it, in increasing order; the search stops after the first
+    // level at which a candidate passes.
     static const double kTolFactor[] = {3.0, 1.0, 1.0 / 3.0};
     static const double kCapFactor[] = {1.0, 2.5, 5.0, 10.0, 25.0};
     const double kWfb[3] = {opts->w_fallback, 0.1, 0.3};
     const bool dp = opts->integ == GC_DOPRI5;
     const int n_tol = dp ? 3 : 1, n_cap = dp ? 5 : 1;
     double best_ms = HUGE_VAL;
-    int n_levels = 0;
     for (int wi = 0; wi < 3; ++wi) {
-        if (wi > 0 && (rep.chosen >= 0 || !(kWfb[wi] > opts->w_fallback))) break;
-        ++n_levels;
+        if (wi > 0 && rep.chosen >= 0) break;
+        if (wi > 0 && !(kWfb[wi] > opts->w_fallback)) continue;
         for (int ti = 0; ti < n_tol; ++ti)
         for (int ci = 0; ci < n_cap; ++ci) {
             gc_autotune_cand& cand = rep.cand[rep.n_cand++];
@@ -358,7 +358,6 @@ static gc_status autotune_impl(gc_ctx* ctx, int32_t n_scenes, const gc_scene* sc
             opts_out->w_fallback = c.w_fallback;
         }
     }
-    (void)n_levels;
 
     // ---- scheduling ---------------------------------------------------------
     const gc_tune entry = ctx->tune;

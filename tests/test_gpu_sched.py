@@ -65,21 +65,22 @@ def test_tune_rejects_out_of_range(B):
         ctx.close()
 
 
-def test_autotune_fallback_when_nothing_passes(B):
-    """With bounds no candidate can meet, the autotuner tries every FP64
-    hand-over level and returns the fastest candidate whose every measured
-    error is at most that of the options as given (flagged as not passing),
-    or the options themselves."""
+@pytest.mark.parametrize("w_given,levels", [(1e-2, [1e-2, 0.1, 0.3]), (0.2, [0.2, 0.3]), (0.5, [0.5])])
+def test_autotune_fallback_when_nothing_passes(B, w_given, levels):
+    """With bounds no candidate can meet, the autotuner tries the given FP64
+    hand-over level and every level of 0.1 and 0.3 above it, and returns the
+    fastest candidate whose every measured error is at most that of the
+    options as given (flagged as not passing), or the options themselves."""
     sc = W.scene(A=0.1, half_width=3.0)
     cam = W.camera(64, 48, spp=1, jitter=True, seed=9)
-    op = W.opts("dopri5", rtol=1e-7)
+    op = W.opts("dopri5", rtol=1e-7, w_fallback=w_given)
     ctx = B.Context(0)
     try:
         tuned, rep = ctx.autotune(sc, cam, op, dir_scale=2, reps=1, tune_sched=0, dir_tol=1e-12, cc_tol=1e-12)
         cands = rep["candidates"]
         assert not any(c["passed"] for c in cands)
-        assert len(cands) == 45
-        assert sorted({c["w_fallback"] for c in cands}) == pytest.approx([op["w_fallback"], 0.1, 0.3])
+        assert len(cands) == 15 * len(levels)
+        assert [c["w_fallback"] for c in cands] == pytest.approx([w for w in levels for _ in range(15)])
         base = [i for i, c in enumerate(cands) if c["rtol"] == pytest.approx(op["rtol"])
                 and c["h_max"] == pytest.approx(op["h_max"]) and c["w_fallback"] == op["w_fallback"]]
         assert len(base) == 1
