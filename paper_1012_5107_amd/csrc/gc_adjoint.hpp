@@ -357,6 +357,108 @@ __device__ inline void rk4_vjp(const SceneDev& s, const AS<T>& u, const cx<T> Ws
     lA += la;
 }
 
+// The transposed map of one FP64 RK4 step applied to four adjoint vectors
+// at once (the rows of L, with their dL/dA in lA): the stage values and the
+// field Jacobians are formed once for all four.
+__device__ inline void rk4_vjp4(const SceneDev& s, const AS<double>& u, const cx<double> Wst[4], double h,
+                                double L[4][4], double lA[4])
+{
+    const double c[4] = {0.0, 0.5 * h, 0.5 * h, h};
+    const double w[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0};
+    double PX[4], PY[4], AX[4], AY[4];
+    SJ<double> J[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double X, Y;
+        if (i == 0) {
+            X = u.x; Y = u.y; PX[0] = u.px; PY[0] = u.py;
+        } else {
+            X = u.x + c[i] * PX[i - 1];
+            Y = u.y + c[i] * PY[i - 1];
+            PX[i] = u.px + c[i] * AX[i - 1];
+            PY[i] = u.py + c[i] * AY[i - 1];
+        }
+        double d2;
+        cx<double> dW;
+        accel_from_w<double>(s, Wst[i], AX[i], AY[i], dW, d2);
+        J[i] = stage_jac<double>(s, X, Y, Wst[i]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double* l = L[k];
+        double lu[4] = {l[0], l[1], l[2], l[3]};
+        double cr[4] = {0.0, 0.0, 0.0, 0.0};
+        double la = 0.0;
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+            const double kx = w[i] * l[0] + cr[0], ky = w[i] * l[1] + cr[1];
+            const cx<double> La = {w[i] * l[2] + cr[2], w[i] * l[3] + cr[3]};
+            const double mx = rcm(J[i].Gx, La), my = rcm(J[i].Gy, La);
+            la += rcm(J[i].GA, La);
+            lu[0] += mx;
+            lu[1] += my;
+            lu[2] += kx;
+            lu[3] += ky;
+            cr[0] = c[i] * mx;
+            cr[1] = c[i] * my;
+            cr[2] = c[i] * kx;
+            cr[3] = c[i] * ky;
+        }
+        l[0] = lu[0]; l[1] = lu[1]; l[2] = lu[2]; l[3] = lu[3];
+        lA[k] += la;
+    }
+}
+
+// Values per tape record of a segment map (below).
+constexpr int kMapFields = 20;
+
+// The transposed map of the in-cloak steps from tape record i (a RUN or
+// CKPT record) to the next record (the following checkpoint or the run's
+// event): the adjoint l of the state at the segment's end becomes
+// sum_k l[k] map[4k .. 4k+3] at its start, and dL/dA gains
+// sum_k l[k] map[16 + k].  The segment is recomputed from its record (the
+// same steps the forward pass took) and reversed once for the four unit
+// seeds.  Returns false if the tape is inconsistent.
+__device__ inline bool adj_segment_map(const SceneDev& s, double wfb2, int C, double h, const AdjTape& tp, int i,
+                                       const AdjSeg<double>& sg, double* map)
+{
+    const long long tag = (long long)*tp.at(i, 7), tag1 = (long long)*tp.at(i + 1, 7);
+    const int kind = (int)(tag & 7), kind1 = (int)(tag1 & 7);
+    const long long base = kind == AK_RUN ? 0 : (tag >> 7);
+    const long long nseg = (tag1 >> 7) - base;
+    if ((kind != AK_RUN && kind != AK_CKPT) || (kind1 != AK_CKPT && kind1 != AK_EVENT) || nseg < 0 || nseg > C)
+        return false;
+    AS<double> u = as_make<double>(*tp.at(i, 0), *tp.at(i, 1), *tp.at(i, 2), *tp.at(i, 3),
+                                   {*tp.at(i, 4), *tp.at(i, 5)});
+    for (int q = 0; q < (int)nseg; ++q) {
+        cx<double> Wst[4];
+        AS<double> ue;
+        adj_rk4<double>(s, wfb2, u, h, ue, Wst);
+        *sg.at(q, 0) = u.x; *sg.at(q, 1) = u.y; *sg.at(q, 2) = u.px; *sg.at(q, 3) = u.py;
+        *sg.at(q, 4) = u.W.re; *sg.at(q, 5) = u.W.im;
+        *sg.at(q, 6) = Wst[1].re; *sg.at(q, 7) = Wst[1].im;
+        *sg.at(q, 8) = Wst[2].re; *sg.at(q, 9) = Wst[2].im;
+        *sg.at(q, 10) = Wst[3].re; *sg.at(q, 11) = Wst[3].im;
+        u = ue;
+    }
+    double L[4][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0, 1.0, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}, {0.0, 0.0, 0.0, 1.0}};
+    double lA[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = (int)nseg - 1; q >= 0; --q) {
+        const AS<double> uq = {*sg.at(q, 0), *sg.at(q, 1), *sg.at(q, 2), *sg.at(q, 3), {*sg.at(q, 4), *sg.at(q, 5)},
+                               0.0, 0.0, 0.0, 0.0};
+        const cx<double> Wst[4] = {uq.W, {*sg.at(q, 6), *sg.at(q, 7)}, {*sg.at(q, 8), *sg.at(q, 9)},
+                                   {*sg.at(q, 10), *sg.at(q, 11)}};
+        rk4_vjp4(s, uq, Wst, h, L, lA);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) map[4 * k + r] = L[k][r];
+        map[16 + k] = lA[k];
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Event functions inside the cloak (>= 0 inside): 0 top, 1 right, 2 left,
 // 3 grating (virtual coordinate v = y + Re W / k, zero on the trochoid).
@@ -661,7 +763,7 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
 template <typename T>
 __device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T wfb2, int C, const AdjTape& tp, int nrec,
                                          const AdjSeg<T>& sg, const double out_dir[3], double lm,
-                                         double& lA, double& lhw, int& bad, double& sens)
+                                         double& lA, double& lhw, int& bad, double& sens, const double* maps)
 {
     const T h = (T)o.h;
     double lr[2] = {0.0, 0.0}, lp[3];
@@ -782,6 +884,25 @@ __device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T 
                 return;
             }
             const int nseg = (int)(j - base);
+            if (maps) {
+                // the segment's map, formed beforehand (adj_segment_map)
+                const double* m = maps + (long long)kMapFields * i;
+                if (!(m[0] == m[0])) {
+                    bad = 1;
+                    return;
+                }
+                double ln[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double lk = (double)l[k];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ln[r] += lk * m[4 * k + r];
+                    lA += lk * m[16 + k];
+                }
+                l[0] = (T)ln[0]; l[1] = (T)ln[1]; l[2] = (T)ln[2]; l[3] = (T)ln[3];
+                j = base;
+                continue;
+            }
             AS<T> u = as_make<T>(*tp.at(i, 0), *tp.at(i, 1), *tp.at(i, 2), *tp.at(i, 3),
                                  {(T)*tp.at(i, 4), (T)*tp.at(i, 5)});
             for (int q = 0; q < nseg; ++q) {
@@ -822,6 +943,14 @@ struct AdjCC {
     double c0, ncc;
 };
 
+// A long trace of the second pass whose reverse sweep runs after its
+// segment maps are formed: its tape is in the pool from record `off` on.
+struct AdjLong {
+    long long sidx, off;
+    int nrec;
+    double od[3];                 // its exit direction (the sky's argument)
+};
+
 struct AdjIo {
     long long n;                  // samples to process (list length when list is set)
     const long long* list;        // sample indices of the second pass (null: 0 .. n-1)
@@ -844,6 +973,15 @@ struct AdjIo {
     // per radian (FP32 rounding would be amplified)
     long long rerun_steps;
     double rerun_sens;
+    // second pass: traces of at least pool_min records copy their tape to
+    // the pool (while it has room) and leave their reverse sweep to
+    // k_adj_maps and k_adj_chain; null pool: every trace reverses here
+    double* pool;
+    long long pool_cap;           // records the pool holds
+    unsigned long long* pool_used;
+    int pool_min;
+    AdjLong* longs;
+    unsigned long long* n_long;
 };
 
 __device__ __forceinline__ unsigned long long adj_wave_sum(unsigned long long v)
@@ -905,10 +1043,27 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         bool hand_over = stopped;
         if (st == RS_OK) {
             hand_over = nrec > io.cap || steps > io.rerun_steps;
+            if (!hand_over && io.pool && nrec >= io.pool_min) {
+                const unsigned long long off = atomicAdd(io.pool_used, (unsigned long long)nrec);
+                if (off + (unsigned long long)nrec <= (unsigned long long)io.pool_cap) {
+                    double* dst = io.pool + (long long)off * kTapeFields;
+                    for (int r = 0; r < nrec; ++r)
+#pragma unroll
+                        for (int f = 0; f < kTapeFields; ++f) dst[r * kTapeFields + f] = *tp.at(r, f);
+                    const unsigned long long k = atomicAdd(io.n_long, 1ull);
+                    AdjLong e;
+                    e.sidx = sidx;
+                    e.off = (long long)off;
+                    e.nrec = nrec;
+                    e.od[0] = od[0]; e.od[1] = od[1]; e.od[2] = od[2];
+                    io.longs[k] = e;
+                    continue;   // its dm/dA and dm/dhw come from k_adj_chain
+                }
+            }
             if (!hand_over) {
                 int bad = 0;
                 double sens = 0.0;
-                adj_reverse<T>(s, o, wfb2, C, tp, nrec, sg, od, 1.0, gA, ghw, bad, sens);
+                adj_reverse<T>(s, o, wfb2, C, tp, nrec, sg, od, 1.0, gA, ghw, bad, sens, nullptr);
                 if (!io.list) c_rev += (unsigned long long)steps;
                 if (bad) {
                     atomicAdd(&io.cnt[4], 1ull);
@@ -952,6 +1107,54 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         atomicAdd(&io.cnt[3], c_fail);
         atomicAdd(&io.cnt[5], c_rev);
         atomicAdd(&io.cnt[6], c_fwd);
+    }
+}
+
+// Segment maps of the pooled tapes, one RUN or CKPT record per task, all
+// records of all pooled traces in parallel (grid-stride).  A record whose
+// map cannot be formed gets a NaN marker, which k_adj_chain counts as an
+// inconsistent tape.
+__global__ void __launch_bounds__(256) k_adj_maps(SceneDev s, OptsDev o, double wfb2, int C, double* pool,
+                                                  const unsigned long long* pool_used, long long pool_cap,
+                                                  double* maps, double* seg)
+{
+    const long long lane = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const AdjSeg<double> sg = {seg, stride, lane};
+    const long long taken = (long long)*pool_used;
+    const long long used = taken < pool_cap ? taken : pool_cap;
+    const AdjTape tp = {pool, 1, 0, (int)used};
+    for (long long g = lane; g < used; g += stride) {
+        const int kind = (int)((long long)pool[g * kTapeFields + 7] & 7);
+        if (kind != AK_RUN && kind != AK_CKPT) continue;
+        double* m = maps + g * kMapFields;
+        if (g + 1 >= used || !adj_segment_map(s, wfb2, C, o.h, tp, (int)g, sg, m)) m[0] = __builtin_nan("");
+    }
+}
+
+// Reverse sweeps of the pooled traces, one per lane, through their segment
+// maps; writes their dm/dA and dm/dhw.
+__global__ void __launch_bounds__(256) k_adj_chain(SceneDev s, OptsDev o, double wfb2, int C, const double* pool,
+                                                   const double* maps, const AdjLong* longs,
+                                                   const unsigned long long* n_long, double* seg, double* sgrad,
+                                                   unsigned long long* cnt)
+{
+    const long long lane = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const AdjSeg<double> sg = {seg, stride, lane};
+    const long long n = (long long)*n_long;
+    for (long long k = lane; k < n; k += stride) {
+        const AdjLong e = longs[k];
+        const AdjTape tp = {const_cast<double*>(pool) + e.off * kTapeFields, 1, 0, e.nrec};
+        double gA = 0.0, ghw = 0.0, sens = 0.0;
+        int bad = 0;
+        adj_reverse<double>(s, o, wfb2, C, tp, e.nrec, sg, e.od, 1.0, gA, ghw, bad, sens, maps + e.off * kMapFields);
+        if (bad) {
+            atomicAdd(&cnt[4], 1ull);
+            gA = ghw = 0.0;
+        }
+        sgrad[2 * e.sidx] = gA;
+        sgrad[2 * e.sidx + 1] = ghw;
     }
 }
 

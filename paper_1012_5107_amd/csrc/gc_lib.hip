@@ -213,6 +213,12 @@ struct AdjStore {
     unsigned long long* h_ctr = nullptr; // pinned: ctr, then red and the correlation sums
     int blocks[2] = {0, 0};              // resident blocks of k_adj<double>, k_adj<float>
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // second pass: tapes of the long traces, their segment maps, one entry each
+    double* pool = nullptr;
+    double* maps = nullptr;
+    AdjLong* longs = nullptr;
+    long long pool_cap = 0;
+    size_t longs_bytes = 0;
 };
 
 struct gc_ctx {
@@ -437,14 +443,24 @@ constexpr int kAdjMaxC = 256;
 // Counters of the adjoint (unsigned long long, device): claims of the two
 // passes, hand-overs of the first pass (front, back of the list), overflows
 // of the second, then rays, steps, events, failed, inconsistent tapes,
-// steps reversed in the first pass and forward steps it took.
-enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_N = 13 };
+// steps reversed in the first pass and forward steps it took; then the
+// second pass's pooled records and pooled traces.
+enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_POOL = 13, AC_N = 15 };
 // FP32 samples handed to the FP64 second pass: paths of more steps, or
 // colours more sensitive to the initial direction (per unit seed) than this
 constexpr long long kAdjRerunSteps = 20000;
 // hand-overs of more steps than this are queued first in the second pass
 constexpr long long kAdjLongSteps = 8000;
 constexpr double kAdjRerunSens = 60.0;
+// Second-pass traces of at least this many tape records (C steps each, or
+// events) are reversed through segment maps formed in parallel
+// (k_adj_maps, k_adj_chain) after the pass, instead of one record after the
+// other on their lane.  Only the longest traces pay for that: a shorter
+// trace's reverse sweep on its lane ends while the longest forward traces
+// still run.  The pool holds at most kAdjPoolRecords records (about
+// 0.9 GB); traces that do not fit reverse on their lane.
+constexpr int kAdjPoolMin = 512;
+constexpr long long kAdjPoolRecords = 1LL << 22;
 
 static gc_status grow(void** p, size_t* have, size_t need, const char* what)
 {
@@ -504,7 +520,7 @@ static gc_status adj_reserve(gc_ctx* ctx, long long n, long long npix)
 template <typename T>
 static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const OptsDev& o, int C, long long n,
                           const long long* list, long long* out_list, int cap, bool rerun, double* sgrad, int pass,
-                          hipStream_t stream)
+                          bool pooled, hipStream_t stream, long long* lanes_out = nullptr)
 {
     AdjStore& a = ctx->adj;
     const int prec = sizeof(T) == 8 ? 0 : 1;
@@ -535,9 +551,16 @@ static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const
     io.cnt = a.ctr + AC_CNT;
     io.rerun_steps = rerun ? kAdjRerunSteps : (1LL << 62);
     io.rerun_sens = rerun ? kAdjRerunSens : HUGE_VAL;
+    io.pool = pooled ? a.pool : nullptr;
+    io.pool_cap = a.pool_cap;
+    io.pool_used = a.ctr + AC_POOL;
+    io.pool_min = kAdjPoolMin;
+    io.longs = a.longs;
+    io.n_long = a.ctr + AC_POOL + 1;
     const T wfb2 = (T)o.wfb2;
     hipLaunchKernelGGL(k_adj<T>, dim3((unsigned)(lanes / 256)), dim3(256), 0, stream, s, c, o, wfb2, C, io);
     HIP_OK(hipGetLastError());
+    if (lanes_out) *lanes_out = lanes;
     return GC_OK;
 }
 
@@ -556,7 +579,8 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
     HIP_OK(hipEventRecord(a.ev[0], stream));
     const long long nbm = std::min<long long>(kCCBlocks, (npix + 255) / 256);
     HIP_OK(hipMemsetAsync(a.ctr, 0, sizeof(unsigned long long) * AC_N, stream));
-    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, a.ovf, kAdjCap, sizeof(T) == 4, sgrad, 0, stream)) != GC_OK)
+    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, a.ovf, kAdjCap, sizeof(T) == 4, sgrad, 0, false, stream)) !=
+        GC_OK)
         return r;
     HIP_OK(hipEventRecord(a.ev[1], stream));
     HIP_OK(hipMemcpyAsync(a.h_ctr, a.ctr, sizeof(unsigned long long) * AC_N, hipMemcpyDeviceToHost, stream));
@@ -571,9 +595,29 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
         // every record a trace can write: one per C steps, three per event
         const long long cap2 = o.max_steps / C + 3LL * (o.max_events + 1) + 8;
         if (cap2 > (1LL << 30)) return fail(GC_EUNSUPPORTED, "max_steps / checkpoint_every too large for the tape");
-        if ((r = adj_pass<double>(ctx, s, c, o, C, handed, a.ovf, nullptr, (int)cap2, false, sgrad, 1, stream)) !=
+        // the pool for the long traces, and one entry per handed-over sample
+        if (!a.pool) {
+            if (hipMalloc((void**)&a.pool, sizeof(double) * kTapeFields * (size_t)kAdjPoolRecords) != hipSuccess ||
+                hipMalloc((void**)&a.maps, sizeof(double) * kMapFields * (size_t)kAdjPoolRecords) != hipSuccess)
+                return fail(GC_ENOMEM, "adjoint tape pool: allocation failed");
+            a.pool_cap = kAdjPoolRecords;
+        }
+        if ((r = grow((void**)&a.longs, &a.longs_bytes, sizeof(AdjLong) * (size_t)handed, "adjoint pool list")) !=
             GC_OK)
             return r;
+        long long lanes = 0;
+        if ((r = adj_pass<double>(ctx, s, c, o, C, handed, a.ovf, nullptr, (int)cap2, false, sgrad, 1, true, stream,
+                                  &lanes)) != GC_OK)
+            return r;
+        // the pooled traces: segment maps over all their records, then one
+        // reverse sweep per trace (the per-lane segment buffers of the
+        // second pass serve both)
+        hipLaunchKernelGGL(k_adj_maps, dim3((unsigned)(lanes / 256)), dim3(256), 0, stream, s, o, o.wfb2, C, a.pool,
+                           (const unsigned long long*)(a.ctr + AC_POOL), a.pool_cap, a.maps, (double*)a.seg);
+        hipLaunchKernelGGL(k_adj_chain, dim3((unsigned)(lanes / 256)), dim3(256), 0, stream, s, o, o.wfb2, C,
+                           (const double*)a.pool, (const double*)a.maps, (const AdjLong*)a.longs,
+                           (const unsigned long long*)(a.ctr + AC_POOL + 1), (double*)a.seg, sgrad, a.ctr + AC_CNT);
+        HIP_OK(hipGetLastError());
     }
     HIP_OK(hipEventRecord(a.ev[2], stream));
     hipLaunchKernelGGL(k_adj_image, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, a.srgb, npix, c.spp,
@@ -1130,7 +1174,7 @@ void gc_destroy(gc_ctx* c)
     if (c->d_peak) (void)hipFree(c->d_peak);
     wf_free(c->wf);
     AdjStore& a = c->adj;
-    void* bufs[] = {a.tape, a.seg, a.srgb, a.sgrad, a.ovf, a.img, a.cs, a.ctr, a.red};
+    void* bufs[] = {a.tape, a.seg, a.srgb, a.sgrad, a.ovf, a.img, a.cs, a.ctr, a.red, a.pool, a.maps, a.longs};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (a.h_ctr) (void)hipHostFree(a.h_ctr);

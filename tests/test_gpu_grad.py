@@ -128,8 +128,9 @@ def test_grad_checkpoint_interval_does_not_change_result(B):
     """Recomputing segments from checkpoints reproduces the forward states
     (up to the compiler's contraction of the same expressions in the forward
     and the recomputation), so the interval -- and the long-tape pass that
-    C = 1 forces for every sample with more than 256 steps -- leaves each
-    sample's result unchanged up to rounding."""
+    C = 1 forces for every sample with more than 256 steps, where the traces
+    of 512 or more records are reversed through segment maps formed in
+    parallel -- leaves each sample's result unchanged up to rounding."""
     sc, cam, op = W.grad_256()
     cam = dict(cam, width=16, height=12, spp=1)
     ref = torch.from_numpy(_ref(sc, cam, op))
