@@ -401,7 +401,7 @@ typedef enum {
  * adjoint of the RK4 tracer (opts->integ must be GC_RK4).  opts->prec
  * selects FP64 or FP32 in-cloak arithmetic; surface maps, sky and sums are
  * FP64.  In FP32 the samples whose derivative FP32 cannot resolve -- paths
- * of more than 20000 steps, or a sky parameter m more sensitive than 60 per
+ * of more than 8000 steps, or a sky parameter m more sensitive than 60 per
  * radian to the initial direction -- are traced and differentiated again
  * in FP64 (colour included).
  * Each sample is traced forward with its state recorded every
@@ -424,7 +424,7 @@ typedef enum {
  * samples differentiated again in FP64 with tapes long enough for any
  * trace the options allow -- tapes longer than 256 records, and in FP32 the
  * long or sensitive traces; the first pass stops a trace once its tape has
- * overflowed or, in FP32, once it has passed 20000 steps, and the counters
+ * overflowed or, in FP32, once it has passed 8000 steps, and the counters
  * of such a sample come from the FP64 pass; rounds = the hand-overs of more
  * than 8000 steps, which
  * start first; hot_steps = steps reversed by the first pass;

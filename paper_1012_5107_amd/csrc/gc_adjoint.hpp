@@ -418,8 +418,10 @@ constexpr int kMapFields = 20;
 // sum_k l[k] map[4k .. 4k+3] at its start, and dL/dA gains
 // sum_k l[k] map[16 + k].  The segment is recomputed from its record (the
 // same steps the forward pass took) and reversed once for the four unit
-// seeds.  Returns false if the tape is inconsistent.
-__device__ inline bool adj_segment_map(const SceneDev& s, double wfb2, int C, double h, const AdjTape& tp, int i,
+// seeds.  Returns false if the tape is inconsistent.  Not inlined: its
+// callers (k_adj_maps, and adj_reverse for a trace the pool had no room
+// for) then run the same compiled arithmetic.
+__device__ __noinline__ bool adj_segment_map(const SceneDev& s, double wfb2, int C, double h, const AdjTape& tp, int i,
                                        const AdjSeg<double>& sg, double* map)
 {
     const long long tag = (long long)*tp.at(i, 7), tag1 = (long long)*tp.at(i + 1, 7);
@@ -763,7 +765,8 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
 template <typename T>
 __device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T wfb2, int C, const AdjTape& tp, int nrec,
                                          const AdjSeg<T>& sg, const double out_dir[3], double lm,
-                                         double& lA, double& lhw, int& bad, double& sens, const double* maps)
+                                         double& lA, double& lhw, int& bad, double& sens, const double* maps,
+                                         bool fly = false)
 {
     const T h = (T)o.h;
     double lr[2] = {0.0, 0.0}, lp[3];
@@ -884,9 +887,25 @@ __device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T 
                 return;
             }
             const int nseg = (int)(j - base);
-            if (maps) {
-                // the segment's map, formed beforehand (adj_segment_map)
-                const double* m = maps + (long long)kMapFields * i;
+            if (maps || fly) {
+                // the segment's map: formed beforehand (k_adj_maps), or here
+                // by the same function (a trace the pool had no room for), so
+                // that both give the same result; a segment ends at the next
+                // record
+                if (i + 1 >= nrec) {
+                    bad = 1;
+                    return;
+                }
+                const double* m = maps ? maps + (long long)kMapFields * i : nullptr;
+                double mf[kMapFields];
+                if (!maps) {
+                    if constexpr (sizeof(T) == 8) {
+                        if (!adj_segment_map(s, (double)wfb2, C, o.h, tp, i, sg, mf)) mf[0] = __builtin_nan("");
+                    } else {
+                        mf[0] = __builtin_nan("");
+                    }
+                    m = mf;
+                }
                 if (!(m[0] == m[0])) {
                     bad = 1;
                     return;
@@ -953,7 +972,9 @@ struct AdjLong {
 
 struct AdjIo {
     long long n;                  // samples to process (list length when list is set)
-    const long long* list;        // sample indices of the second pass (null: 0 .. n-1)
+    const long long* list;        // sample indices of the second pass (null: 0 .. n-1): list_front
+                                  // entries from its start, the rest from its end (list_cap entries)
+    long long list_front, list_cap;
     unsigned long long* claim;    // work counter (64 samples per claim)
     double* tape;
     int cap;                      // tape slots per lane
@@ -1011,7 +1032,9 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         if (q >= (unsigned long long)io.n) continue;
         // a second pass's entry ~sidx: a sample the first pass stopped early,
         // whose counters are taken here
-        const long long raw = io.list ? io.list[q] : (long long)q;
+        const long long qq = (long long)q;
+        const long long raw = !io.list ? qq
+                              : qq < io.list_front ? io.list[qq] : io.list[io.list_cap - 1 - (qq - io.list_front)];
         const bool redo = raw < 0;
         const long long sidx = redo ? ~raw : raw;
         const long long pix = sidx / cam.spp;
@@ -1043,7 +1066,11 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         bool hand_over = stopped;
         if (st == RS_OK) {
             hand_over = nrec > io.cap || steps > io.rerun_steps;
-            if (!hand_over && io.pool && nrec >= io.pool_min) {
+            // a long trace of the second pass reverses through segment maps:
+            // formed in parallel after the pass if its tape fits in the pool,
+            // else here, one after the other (the same arithmetic either way)
+            const bool by_maps = !hand_over && io.pool && nrec >= io.pool_min;
+            if (by_maps) {
                 const unsigned long long off = atomicAdd(io.pool_used, (unsigned long long)nrec);
                 if (off + (unsigned long long)nrec <= (unsigned long long)io.pool_cap) {
                     double* dst = io.pool + (long long)off * kTapeFields;
@@ -1063,7 +1090,7 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
             if (!hand_over) {
                 int bad = 0;
                 double sens = 0.0;
-                adj_reverse<T>(s, o, wfb2, C, tp, nrec, sg, od, 1.0, gA, ghw, bad, sens, nullptr);
+                adj_reverse<T>(s, o, wfb2, C, tp, nrec, sg, od, 1.0, gA, ghw, bad, sens, nullptr, by_maps);
                 if (!io.list) c_rev += (unsigned long long)steps;
                 if (bad) {
                     atomicAdd(&io.cnt[4], 1ull);

@@ -448,7 +448,7 @@ constexpr int kAdjMaxC = 256;
 enum { AC_CLAIM = 0, AC_OVF = 3, AC_CNT = 6, AC_POOL = 13, AC_N = 15 };
 // FP32 samples handed to the FP64 second pass: paths of more steps, or
 // colours more sensitive to the initial direction (per unit seed) than this
-constexpr long long kAdjRerunSteps = 20000;
+constexpr long long kAdjRerunSteps = 8000;
 // hand-overs of more steps than this are queued first in the second pass
 constexpr long long kAdjLongSteps = 8000;
 constexpr double kAdjRerunSens = 60.0;
@@ -519,8 +519,8 @@ static gc_status adj_reserve(gc_ctx* ctx, long long n, long long npix)
 // are only counted).  `rerun`: apply the FP32 hand-over criteria.
 template <typename T>
 static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const OptsDev& o, int C, long long n,
-                          const long long* list, long long* out_list, int cap, bool rerun, double* sgrad, int pass,
-                          bool pooled, hipStream_t stream, long long* lanes_out = nullptr)
+                          const long long* list, long long list_front, long long* out_list, int cap, bool rerun,
+                          double* sgrad, int pass, bool pooled, hipStream_t stream, long long* lanes_out = nullptr)
 {
     AdjStore& a = ctx->adj;
     const int prec = sizeof(T) == 8 ? 0 : 1;
@@ -538,6 +538,8 @@ static gc_status adj_pass(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const
     AdjIo io;
     io.n = n;
     io.list = list;
+    io.list_front = list_front;
+    io.list_cap = a.cap_samples;
     io.claim = a.ctr + AC_CLAIM + pass;
     io.tape = a.tape;
     io.cap = cap;
@@ -579,7 +581,7 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
     HIP_OK(hipEventRecord(a.ev[0], stream));
     const long long nbm = std::min<long long>(kCCBlocks, (npix + 255) / 256);
     HIP_OK(hipMemsetAsync(a.ctr, 0, sizeof(unsigned long long) * AC_N, stream));
-    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, a.ovf, kAdjCap, sizeof(T) == 4, sgrad, 0, false, stream)) !=
+    if ((r = adj_pass<T>(ctx, s, c, o, C, n, nullptr, 0, a.ovf, kAdjCap, sizeof(T) == 4, sgrad, 0, false, stream)) !=
         GC_OK)
         return r;
     HIP_OK(hipEventRecord(a.ev[1], stream));
@@ -588,10 +590,8 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
     const long long n_front = (long long)a.h_ctr[AC_OVF + 0], n_back = (long long)a.h_ctr[AC_OVF + 1];
     const long long handed = n_front + n_back;
     if (handed > 0) {
-        // make the list contiguous: the back part follows the front part
-        if (n_back > 0 && a.cap_samples - n_back != n_front)
-            HIP_OK(hipMemcpyAsync(a.ovf + n_front, a.ovf + (a.cap_samples - n_back), sizeof(long long) * n_back,
-                                  hipMemcpyDeviceToDevice, stream));
+        // the second pass reads the list's front part from its start and the
+        // rest from its end, where the first pass wrote them
         // every record a trace can write: one per C steps, three per event
         const long long cap2 = o.max_steps / C + 3LL * (o.max_events + 1) + 8;
         if (cap2 > (1LL << 30)) return fail(GC_EUNSUPPORTED, "max_steps / checkpoint_every too large for the tape");
@@ -606,8 +606,8 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
             GC_OK)
             return r;
         long long lanes = 0;
-        if ((r = adj_pass<double>(ctx, s, c, o, C, handed, a.ovf, nullptr, (int)cap2, false, sgrad, 1, true, stream,
-                                  &lanes)) != GC_OK)
+        if ((r = adj_pass<double>(ctx, s, c, o, C, handed, a.ovf, n_front, nullptr, (int)cap2, false, sgrad, 1, true,
+                                  stream, &lanes)) != GC_OK)
             return r;
         // the pooled traces: segment maps over all their records, then one
         // reverse sweep per trace (the per-lane segment buffers of the

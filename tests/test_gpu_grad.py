@@ -224,3 +224,27 @@ def test_grad_full_size_fp32_sampled_against_oracle(B):
     # the loss against the oracle's on the image the library rendered
     img = r["image"].cpu().numpy()
     assert abs(r["loss"] - O.loss_weights(ref, img, "ncc")[0]) < 1e-9
+
+
+def test_grad_most_samples_handed_over_is_deterministic(B):
+    """With short tapes (checkpoints every 8 steps, so that most samples
+    outgrow the first pass's 256 records) most samples go to the FP64 pass:
+    its list, written from both ends by the first pass, is read in place.
+    Two calls agree bit for bit, and each sample agrees with the usual
+    checkpoint interval up to rounding."""
+    sc, cam, op = W.grad_256()
+    cam = dict(cam, width=128, height=128)
+    ref = torch.from_numpy(_ref(sc, cam, op))
+    ctx = B.context()
+    a = ctx.render_grad(sc, cam, op, ref, prec="f64", checkpoint_every=8, sample_dm=True)
+    b = ctx.render_grad(sc, cam, op, ref, prec="f64", checkpoint_every=8, sample_dm=True)
+    n = cam["width"] * cam["height"] * cam["spp"]
+    print(f"[handed over] {a['stats']['tail_rays']} of {n}", flush=True)
+    assert a["stats"]["tail_rays"] > n // 2
+    ga, gb = a["sample_dm"].cpu().numpy(), b["sample_dm"].cpu().numpy()
+    assert np.array_equal(ga, gb) and a["loss"] == b["loss"] and a["dA"] == b["dA"]
+    c = ctx.render_grad(sc, cam, op, ref, prec="f64", checkpoint_every=64, sample_dm=True)
+    g0 = c["sample_dm"].cpu().numpy()
+    rel = np.abs(ga - g0) / (np.abs(g0) + 1e-6 * np.abs(g0).max(axis=0))
+    print(f"[handed over] C=8 against C=64: max rel {rel.max():.3e} p99 {np.quantile(rel, 0.99):.3e}", flush=True)
+    assert np.quantile(rel, 0.99) <= 1e-12 and rel.max() <= 1e-6
