@@ -74,22 +74,30 @@ TRAFFIC_K_WF_BOX_STRESS = {(1e-7,): 3.03e9}
 # SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) of the same launches
 VALU_FLOPS_K_WF_BOX = {(3e-7, 0.5, "dopri5"): (1.925e9, 0.627)}
 VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.645e11, 0.774)}
+# The gradient's first pass k_adj<float> (profiles/k_adj_rk4_256x256x4_grad.txt),
+# per launch, keyed by (RK4 step, checkpoint interval); these hold for the
+# adjoint's sources (its kernels, shared device code and orchestration).
+ADJ_KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_adjoint.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp",
+                      "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_lib.hip"]
+ADJ_MEASURED_SHA = "09322c696aef1e11"
+TRAFFIC_K_ADJ = {(1e-3, 64): 1.39e11}
+VALU_FLOPS_K_ADJ = {(1e-3, 64): (3.848e10, 0.756)}
 
 
-def _kernel_sha():
+def _kernel_sha(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if sources is None else sources):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _measured(table, key):
+def _measured(table, key, sources=None, sha=None):
     """Table entry for options that equal the key's up to rounding (the
     autotuner forms its candidates by products such as 3 x 1e-7); None when
     absent or when the kernel sources changed since the tables were taken."""
-    if key is None or _kernel_sha() != MEASURED_SHA:
+    if key is None or _kernel_sha(sources) != (MEASURED_SHA if sha is None else sha):
         return None
     for k, v in table.items():
         if all(a == b if isinstance(a, str) else math.isclose(a, b, rel_tol=1e-9) for a, b in zip(k, key)):
@@ -656,6 +664,8 @@ def main_grad(args):
     # stops and hands over included) and the steps it reversed
     fwd, fwd1, rev = st["accepted_steps"], st["first_pass_steps"], st["hot_steps"]
     achieved = (fwd1 * FLOP_PER_STEP["rk4"] + rev * FLOP_PER_REVERSED_STEP) / (st["hot_ms"] * 1e-3)
+    akey = (op["h"], 64)
+    avf = _measured(VALU_FLOPS_K_ADJ, akey, ADJ_KERNEL_SOURCES, ADJ_MEASURED_SHA)
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
         "value": fwd / dt, "unit": "ray-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -667,8 +677,15 @@ def main_grad(args):
         "rays_per_s": st["rays"] / dt,
         "loss": r["loss"], "dL_dA": r["dA"], "dL_dhw": r["dhw"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None, "kernel": "k_adj<float>",
-                     "kernel_ms": st["hot_ms"], "forward_steps": fwd1, "reversed_steps": rev},
+                     "frac": achieved / PEAK_FP32,
+                     "traffic": _measured(TRAFFIC_K_ADJ, akey, ADJ_KERNEL_SOURCES, ADJ_MEASURED_SHA),
+                     "kernel": "k_adj<float>", "kernel_ms": st["hot_ms"], "forward_steps": fwd1,
+                     "reversed_steps": rev,
+                     "valu_flops_counter": None if avf is None else {
+                         "SQ_INSTS_VALU_FLOPS_FP32": avf[0], "lane_utilisation": avf[1],
+                         "tflops_executed": 64 * avf[0] * avf[1] / (st["hot_ms"] * 1e-3) / 1e12,
+                         "frac_executed": 64 * avf[0] * avf[1] / (st["hot_ms"] * 1e-3) / PEAK_FP32,
+                         "profile": "profiles/k_adj_rk4_256x256x4_grad.txt"}},
         "adjoint_breakdown": {"fp32_pass_ms": st["hot_ms"], "fp64_passes_ms": st["tail_ms"],
                               "total_ms": st["total_ms"], "fp64_samples": st["tail_rays"],
                               "long_tape_samples": st["rounds"], "failed": st["failed"]},

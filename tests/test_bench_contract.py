@@ -56,3 +56,17 @@ def test_traffic_tables_resolve_the_options_the_benchmark_uses(monkeypatch):
             assert (v[0] if isinstance(v, tuple) else v) > 0
     monkeypatch.setattr(bench, "MEASURED_SHA", "0" * 16)
     assert bench._measured(bench.TRAFFIC_K_WF_BOX_BATCH, (1e-7, 0.05, 0.3)) is None
+
+
+def test_adjoint_measured_tables(monkeypatch):
+    """The gradient's recorded counter and traffic figures are returned for
+    its own step and checkpoint interval while the adjoint's sources are the
+    ones they were measured with, and None otherwise."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src, sha = bench.ADJ_KERNEL_SOURCES, bench._kernel_sha(bench.ADJ_KERNEL_SOURCES)
+    monkeypatch.setattr(bench, "ADJ_MEASURED_SHA", sha)
+    for table in (bench.TRAFFIC_K_ADJ, bench.VALU_FLOPS_K_ADJ):
+        assert bench._measured(table, (1e-3, 64), src, sha) is not None
+        assert bench._measured(table, (1e-3, 32), src, sha) is None
+        assert bench._measured(table, (1e-3, 64), src, "0" * 16) is None
