@@ -79,7 +79,7 @@ VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.645e11, 0.774)}
 # adjoint's sources (its kernels, shared device code and orchestration).
 ADJ_KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_adjoint.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp",
                       "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_lib.hip"]
-ADJ_MEASURED_SHA = "09322c696aef1e11"
+ADJ_MEASURED_SHA = "6b85677bef57adcf"
 TRAFFIC_K_ADJ = {(1e-3, 64): 1.39e11}
 VALU_FLOPS_K_ADJ = {(1e-3, 64): (3.848e10, 0.756)}
 

@@ -596,10 +596,18 @@ static gc_status adj_run(gc_ctx* ctx, const SceneDev& s, const CamDev& c, const 
         const long long cap2 = o.max_steps / C + 3LL * (o.max_events + 1) + 8;
         if (cap2 > (1LL << 30)) return fail(GC_EUNSUPPORTED, "max_steps / checkpoint_every too large for the tape");
         // the pool for the long traces, and one entry per handed-over sample
-        if (!a.pool) {
+        if (!a.pool || !a.maps) {
+            if (a.pool) (void)hipFree(a.pool);
+            if (a.maps) (void)hipFree(a.maps);
+            a.pool = a.maps = nullptr;
             if (hipMalloc((void**)&a.pool, sizeof(double) * kTapeFields * (size_t)kAdjPoolRecords) != hipSuccess ||
-                hipMalloc((void**)&a.maps, sizeof(double) * kMapFields * (size_t)kAdjPoolRecords) != hipSuccess)
+                hipMalloc((void**)&a.maps, sizeof(double) * kMapFields * (size_t)kAdjPoolRecords) != hipSuccess) {
+                if (a.pool) (void)hipFree(a.pool);
+                if (a.maps) (void)hipFree(a.maps);
+                a.pool = a.maps = nullptr;
+                a.pool_cap = 0;
                 return fail(GC_ENOMEM, "adjoint tape pool: allocation failed");
+            }
             a.pool_cap = kAdjPoolRecords;
         }
         if ((r = grow((void**)&a.longs, &a.longs_bytes, sizeof(AdjLong) * (size_t)handed, "adjoint pool list")) !=
