@@ -59,10 +59,10 @@ FLOP_PER_REVERSED_STEP = 354.0 + 4 * (113.0 + 33.0 + 30.0)
 # every entry stale and the bench reports null instead.
 KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_wave.hpp", "paper_1012_5107_amd/csrc/gc_lane32.hpp",
                   "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp"]
-MEASURED_SHA = "5b7cd5643c13161f"
+MEASURED_SHA = "673032bf72973b76"
 # 512 x 512 x 4 workload, per launch, keyed by (rtol, h_max, integrator)
 # (profiles/k_wf_box_dopri5_512x512x4_tuned.txt)
-TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.03e8}
+TRAFFIC_K_WF_BOX = {(3e-7, 0.5, "dopri5"): 5.02e8}
 # the 64-scene batch, summed over the pipeline rounds of one render, keyed by
 # (rtol, h_max, w_fallback) (profiles/k_wf_box_dopri5_batch64.txt)
 TRAFFIC_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): 6.28e10}
@@ -72,8 +72,8 @@ TRAFFIC_K_WF_BOX_STRESS = {(1e-7,): 3.03e9}
 # SQ_INSTS_VALU_FLOPS_FP32 per render (wave-level: 2 FMA + MUL + ADD + TRANS
 # instructions), same keys as the traffic, and the VALU lane utilisation
 # SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) of the same launches
-VALU_FLOPS_K_WF_BOX = {(3e-7, 0.5, "dopri5"): (1.925e9, 0.627)}
-VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.645e11, 0.774)}
+VALU_FLOPS_K_WF_BOX = {(3e-7, 0.5, "dopri5"): (1.927e9, 0.635)}
+VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.653e11, 0.783)}
 # The gradient's first pass k_adj<float> (profiles/k_adj_rk4_256x256x4_grad.txt),
 # per launch, keyed by (RK4 step, checkpoint interval); these hold for the
 # adjoint's sources (its kernels, shared device code and orchestration).

@@ -752,6 +752,8 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                 ev_values32(c, ue, re, ytop, xh, xl, mirror, e);
                 bool apply = false;
                 int evc = -1;
+                bool take = false;
+                float hnew = 0.0f;
                 if (!loc) {
                     float hnext = h;
                     bool accepted = true;
@@ -777,11 +779,8 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                                 (e[3] < 0.0f ? 8 : 0);
                         if (!emask) {
                             comp_add(tau, ltau, h);
-                            u = ue;
-                            r1 = re;
-                            h = hnext;
-                            xhi = xh;
-                            xlo = xl;
+                            take = true;
+                            hnew = hnext;
                         } else {
                             // the step crossed an event: locate it on the
                             // partial steps of the next iterations
@@ -847,14 +846,21 @@ __global__ void __launch_bounds__(256) k_wf_box(WfArgs a, int cur)
                     }
                 }
                 if (apply) {
-                    // the event at the trial state ue (theta = th)
                     comp_add(tau, ltau, th * hacc);
+                    take = true;
+                    hnew = hnx;
+                    loc = false;
+                }
+                if (take) {
+                    // the step (or the located event's partial step) is taken
                     u = ue;
                     r1 = re;
+                    h = hnew;
                     xhi = xh;
                     xlo = xl;
-                    h = hnx;
-                    loc = false;
+                }
+                if (apply) {
+                    // the event at the trial state ue (theta = th)
                     if (++nev > max_ev) {
                         fin = RS_MAX_EVENTS;
                     } else {
