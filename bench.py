@@ -74,6 +74,12 @@ TRAFFIC_K_WF_BOX_STRESS = {(1e-7,): 3.03e9}
 # SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) of the same launches
 VALU_FLOPS_K_WF_BOX = {(3e-7, 0.5, "dopri5"): (1.927e9, 0.635)}
 VALU_FLOPS_K_WF_BOX_BATCH = {(1e-7, 0.05, 0.3): (2.653e11, 0.783)}
+# The batch's autotuner search at the recorded options' kernels (python bench.py
+# --autotune on; profiles/autotune_batch64.txt): the choice recorded as
+# workloads.batch_timed_opts, the candidate's index, the candidates tried and
+# whether the choice met every bound.
+AUTOTUNE_BATCH = {(1e-7, 0.05, 0.3): {"chosen": 36, "candidates": 45, "passed": True, "seconds": 84.0,
+                                      "record": "profiles/autotune_batch64.txt"}}
 # The gradient's first pass k_adj<float> (profiles/k_adj_rk4_256x256x4_grad.txt),
 # per launch, keyed by (RK4 step, checkpoint interval); these hold for the
 # adjoint's sources (its kernels, shared device code and orchestration).
@@ -396,7 +402,10 @@ def main_batch(args):
     from paper_1012_5107_amd import workloads as W
 
     scenes, cams = W.batch_64(jitter_seed=args.jitter_seed)
-    op32 = W.batch_timed_opts() if args.autotune == "recorded" else W.opts("dopri5", rtol=args.rtol32)
+    # the search's levers are the step control and the FP64 hand-over
+    # threshold; the workload's other options (fp64_stay) stay as recorded
+    op32 = W.batch_timed_opts() if args.autotune == "recorded" else W.opts(
+        "dopri5", rtol=args.rtol32, fp64_stay=W.batch_timed_opts()["fp64_stay"])
     if args.autotune == "off" and args.h_max is not None:
         op32["h_max"] = args.h_max
     if args.w_fallback is not None:
@@ -448,6 +457,7 @@ def main_batch(args):
     # the recorded counter and traffic figures belong to the workload's own samples
     key = (op32["rtol"], op32["h_max"], op32["w_fallback"]) if args.jitter_seed == 1 else None
     vf = _measured(VALU_FLOPS_K_WF_BOX_BATCH, key)
+    searched = _measured(AUTOTUNE_BATCH, key) if args.autotune == "recorded" else None
     out = {
         "metric": "ray-steps/s and rays/s (FP32 batched vs FP64 plain) at CC error ≤1e-4",
         "value": st["rays"] / dt, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -462,10 +472,13 @@ def main_batch(args):
         "ray_steps_per_s": st["accepted_steps"] / dt,
         "autotune": {"mode": args.autotune, "seconds": ta, "chosen_rtol": op32["rtol"], "chosen_h_max": op32["h_max"],
                      "chosen_w_fallback": op32["w_fallback"], "chosen": rep.get("chosen", -1),
-                     # recorded: the search's passing choice (tests/test_gpu_batch.py checks it;
-                     # cc_error_vs_converged_fp64 below measures it again)
+                     # on: this run's search; recorded: the search that chose these options,
+                     # while the kernel sources are those it ran with (tests/test_gpu_batch.py
+                     # checks the choice; cc_error_vs_converged_fp64 below measures it again)
                      "passed": (bool(rep["candidates"][rep["chosen"]]["passed"])
-                                if rep["candidates"] and rep.get("chosen", -1) >= 0 else None),
+                                if rep["candidates"] and rep.get("chosen", -1) >= 0
+                                else searched["passed"] if searched else None),
+                     "recorded_search": searched,
                      "candidates": [{k: c[k] for k in ("rtol", "h_max", "w_fallback", "ms", "steps", "dir_p99",
                                                        "dir_max", "changed", "cc_err", "passed") if k in c}
                                     for c in rep["candidates"]]},

@@ -70,3 +70,21 @@ def test_adjoint_measured_tables(monkeypatch):
         assert bench._measured(table, (1e-3, 64), src, sha) is not None
         assert bench._measured(table, (1e-3, 32), src, sha) is None
         assert bench._measured(table, (1e-3, 64), src, "0" * 16) is None
+
+
+def test_recorded_batch_search_is_the_timed_choice(monkeypatch):
+    """The batch's recorded autotuner search is keyed on the options the
+    benchmark times by default (workloads.batch_timed_opts): it passed, its
+    choice is one of its candidates, and its record is committed; with other
+    kernel sources it is not reported."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1012_5107_amd import workloads as W
+    op = W.batch_timed_opts()
+    key = (op["rtol"], op["h_max"], op["w_fallback"])
+    monkeypatch.setattr(bench, "MEASURED_SHA", bench._kernel_sha())
+    rec = bench._measured(bench.AUTOTUNE_BATCH, key)
+    assert rec is not None and rec["passed"] is True and 0 <= rec["chosen"] < rec["candidates"]
+    assert os.path.isfile(os.path.join(ROOT, rec["record"]))
+    monkeypatch.setattr(bench, "MEASURED_SHA", "0" * 16)
+    assert bench._measured(bench.AUTOTUNE_BATCH, key) is None
