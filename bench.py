@@ -85,9 +85,9 @@ AUTOTUNE_BATCH = {(1e-7, 0.05, 0.3): {"chosen": 36, "candidates": 45, "passed": 
 # adjoint's sources (its kernels, shared device code and orchestration).
 ADJ_KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_adjoint.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp",
                       "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_lib.hip"]
-ADJ_MEASURED_SHA = "6b85677bef57adcf"
-TRAFFIC_K_ADJ = {(1e-3, 64): 1.39e11}
-VALU_FLOPS_K_ADJ = {(1e-3, 64): (3.848e10, 0.756)}
+ADJ_MEASURED_SHA = "3555d2c9023e87ea"
+TRAFFIC_K_ADJ = {(1e-3, 64): 1.25e11}
+VALU_FLOPS_K_ADJ = {(1e-3, 64): (3.845e10, 0.753)}
 
 
 def _kernel_sha(sources=None):

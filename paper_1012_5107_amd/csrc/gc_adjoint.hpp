@@ -421,9 +421,14 @@ constexpr int kMapFields = 20;
 // seeds.  Returns false if the tape is inconsistent.  Not inlined: its
 // callers (k_adj_maps, and adj_reverse for a trace the pool had no room
 // for) then run the same compiled arithmetic.
-__device__ __noinline__ bool adj_segment_map(const SceneDev& s, double wfb2, int C, double h, const AdjTape& tp, int i,
-                                       const AdjSeg<double>& sg, double* map)
+__device__ __noinline__ bool adj_segment_map(const SceneDev& s_in, double wfb2, int C, double h, const AdjTape& tp_in,
+                                       int i, const AdjSeg<double>& sg_in, double* map)
 {
+    // the scene and the buffers' descriptors in registers (read through the
+    // references, they would be loaded again after every store)
+    const SceneDev s = s_in;
+    const AdjTape tp = tp_in;
+    const AdjSeg<double> sg = sg_in;
     const long long tag = (long long)*tp.at(i, 7), tag1 = (long long)*tp.at(i + 1, 7);
     const int kind = (int)(tag & 7), kind1 = (int)(tag1 & 7);
     const long long base = kind == AK_RUN ? 0 : (tag >> 7);
@@ -647,10 +652,18 @@ __device__ inline void sky_vjp(double K, const double d[3], double lm, double lp
 constexpr int kAdjStopped = 16;   // not a ray status
 
 template <typename T>
-__device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T wfb2, int C, const double org[3],
-                                        const double dir[3], const AdjTape& tp, int& nrec, double out_dir[3],
-                                        long long& steps, int& events, bool stop, long long stop_steps)
+__device__ __forceinline__ int adj_forward_body(const SceneDev& s, const OptsDev& o, T wfb2, int C,
+                                                const double org[3], const double dir[3], const AdjTape& tp,
+                                                int& nrec, double out_dir[3], long long& steps, int& events,
+                                                bool stop, long long stop_steps)
 {
+    // the scene, options and tape in registers for the step loop: read
+    // through the caller's references they would be loaded again every
+    // step, since the tape's stores might alias them
+    const SceneDev sl = s;
+    const long long max_steps = o.max_steps;
+    const int max_events = o.max_events;
+    const AdjTape tl = tp;
     double r[3] = {org[0], org[1], org[2]};
     const double nd = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
     double p[3] = {dir[0] / nd, dir[1] / nd, dir[2] / nd};
@@ -671,10 +684,10 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
                 out_dir[0] = p[0]; out_dir[1] = p[1]; out_dir[2] = p[2];
                 return RS_OK;
             }
-            if (++events > o.max_events) return RS_MAX_EVENTS;
+            if (++events > max_events) return RS_MAX_EVENTS;
             if (tg <= tb) {
                 if (s.A == 0.0) xi = r[0] + tg * p[0];
-                tape_put(tp, nrec, r[0], r[1], p[0], p[1], p[2], xi, tg, AK_CONTACT);
+                tape_put(tl, nrec, r[0], r[1], p[0], p[1], p[2], xi, tg, AK_CONTACT);
                 for (int i = 0; i < 3; ++i) r[i] += tg * p[i];
                 double sn, cs;
                 sincos(s.k * xi, &sn, &cs);
@@ -692,28 +705,28 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
             const cx<double> W = w0_cold(zarg64(s, r[0], r[1]));
             const double n2 = 1.0 / sqrt(norm2(mk(1.0 + W.re, W.im)));
             const bool thr = snell(p, nf, n2);
-            tape_put(tp, nrec, r0[0], r0[1], p0[0], p0[1], p0[2], 0.0, tb, AK_ENTRY + 8 * face + (thr ? 64 : 0));
+            tape_put(tl, nrec, r0[0], r0[1], p0[0], p0[1], p0[2], 0.0, tb, AK_ENTRY + 8 * face + (thr ? 64 : 0));
             if (thr) break;
         }
         // --- cloak ---
         AS<T> u = as_make<T>(r[0], r[1], p[0], p[1], cvt<T>(w0_cold(zarg64(s, r[0], r[1]))));
         const double pz = p[2];
-        tape_put(tp, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re, u.W.im,
+        tape_put(tl, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re, u.W.im,
                  pz, AK_RUN);
         long long run = 0;
         for (;;) {
-            if (stop && (nrec > tp.cap || steps > stop_steps)) return kAdjStopped;
-            if (steps >= o.max_steps) return RS_MAX_STEPS;
+            if (stop && (nrec > tl.cap || steps > stop_steps)) return kAdjStopped;
+            if (steps >= max_steps) return RS_MAX_STEPS;
             if (run > 0 && run % C == 0)
-                tape_put(tp, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re,
+                tape_put(tl, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re,
                          u.W.im, 0.0, AK_CKPT + 128 * run);
             AS<T> ue;
-            adj_rk4<T>(s, wfb2, u, h, ue, nullptr);
+            adj_rk4<T>(sl, wfb2, u, h, ue, nullptr);
             ++steps;
             if (!(isfinite(ue.x) && isfinite(ue.y) && isfinite(ue.px) && isfinite(ue.py))) return RS_NONFINITE;
             T f1[4];
 #pragma unroll
-            for (int ev = 0; ev < 4; ++ev) f1[ev] = adj_event<T>(s, ev, ue);
+            for (int ev = 0; ev < 4; ++ev) f1[ev] = adj_event<T>(sl, ev, ue);
             if (!(f1[0] < (T)0 || f1[1] < (T)0 || f1[2] < (T)0 || f1[3] < (T)0)) {
                 u = ue;
                 ++run;
@@ -724,11 +737,14 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
             AS<T> uc = ue;
             for (int ev = 0; ev < 4; ++ev) {
                 if (!(f1[ev] < (T)0)) continue;
+                // copies for the call, so that the step loop's own state is
+                // never addressed and stays in registers
+                const AS<T> ua = u, ub = ue;
                 AS<T> uh;
-                const T th = adj_locate<T>(s, wfb2, ev, u, h, fmax(adj_event<T>(s, ev, u), (T)0), f1[ev], ue, uh);
+                const T th = adj_locate<T>(s, wfb2, ev, ua, h, fmax(adj_event<T>(sl, ev, u), (T)0), f1[ev], ub, uh);
                 if (th < best) { best = th; hit = ev; uc = uh; }
             }
-            if (++events > o.max_events) return RS_MAX_EVENTS;
+            if (++events > max_events) return RS_MAX_EVENTS;
             double pp[3] = {join(uc.px, uc.pxl), join(uc.py, uc.pyl), pz};
             bool thr = false;
             if (hit == 3) {
@@ -740,7 +756,7 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
                 if (hit == 0) nf[1] = 1.0; else if (hit == 1) nf[0] = 1.0; else nf[0] = -1.0;
                 thr = snell(pp, nf, 1.0);
             }
-            tape_put(tp, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re, u.W.im,
+            tape_put(tl, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re, u.W.im,
                      (double)best, AK_EVENT + 8 * hit + (thr ? 64 : 0) + 128 * run);
             if (thr) {
                 r[0] = join(uc.x, uc.xl);
@@ -752,10 +768,27 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
             split(pp[0], u.px, u.pxl);
             split(pp[1], u.py, u.pyl);
             run = 0;
-            tape_put(tp, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re, u.W.im,
+            tape_put(tl, nrec, join(u.x, u.xl), join(u.y, u.yl), join(u.px, u.pxl), join(u.py, u.pyl), u.W.re, u.W.im,
                      pz, AK_RUN);
         }
     }
+}
+
+// The forward trace as one compiled function (the first and second passes
+// share it); its counters live in registers and are written back at the end.
+template <typename T>
+__device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T wfb2, int C, const double org[3],
+                                        const double dir[3], const AdjTape& tp, int& nrec, double out_dir[3],
+                                        long long& steps, int& events, bool stop, long long stop_steps)
+{
+    int nrec_l = 0, events_l = 0;
+    long long steps_l = 0;
+    const int st = adj_forward_body<T>(s, o, wfb2, C, org, dir, tp, nrec_l, out_dir, steps_l, events_l, stop,
+                                       stop_steps);
+    nrec = nrec_l;
+    steps = steps_l;
+    events = events_l;
+    return st;
 }
 
 // ---------------------------------------------------------------------------
@@ -763,11 +796,17 @@ __device__ __noinline__ int adj_forward(const SceneDev& s, const OptsDev& o, T w
 // Accumulates dL/dA and dL/dhw of this sample.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T wfb2, int C, const AdjTape& tp, int nrec,
-                                         const AdjSeg<T>& sg, const double out_dir[3], double lm,
-                                         double& lA, double& lhw, int& bad, double& sens, const double* maps,
-                                         bool fly = false)
+__device__ __forceinline__ void adj_reverse_body(const SceneDev& s_in, const OptsDev& o_in, T wfb2, int C,
+                                                 const AdjTape& tp_in, int nrec, const AdjSeg<T>& sg_in,
+                                                 const double out_dir[3], double lm, double& lA, double& lhw,
+                                                 int& bad, double& sens, const double* maps, bool fly)
 {
+    // the scene, options and buffers' descriptors in registers (read through
+    // the references, they would be loaded again after every store)
+    const SceneDev s = s_in;
+    const OptsDev o = o_in;
+    const AdjTape tp = tp_in;
+    const AdjSeg<T> sg = sg_in;
     const T h = (T)o.h;
     double lr[2] = {0.0, 0.0}, lp[3];
     sky_vjp(s.K, out_dir, lm, lp);
@@ -900,7 +939,7 @@ __device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T 
                 double mf[kMapFields];
                 if (!maps) {
                     if constexpr (sizeof(T) == 8) {
-                        if (!adj_segment_map(s, (double)wfb2, C, o.h, tp, i, sg, mf)) mf[0] = __builtin_nan("");
+                        if (!adj_segment_map(s_in, (double)wfb2, C, o.h, tp_in, i, sg_in, mf)) mf[0] = __builtin_nan("");
                     } else {
                         mf[0] = __builtin_nan("");
                     }
@@ -949,6 +988,23 @@ __device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T 
     // sensitivity of the colour to the initial direction (the adjoint of
     // the camera ray's momentum): how much rounding in the trace is amplified
     sens = sqrt(lp[0] * lp[0] + lp[1] * lp[1] + lp[2] * lp[2]);
+}
+
+// The reverse sweep as one compiled function (the in-lane and pooled paths
+// share it); its sums live in registers and are written back at the end.
+template <typename T>
+__device__ __noinline__ void adj_reverse(const SceneDev& s, const OptsDev& o, T wfb2, int C, const AdjTape& tp, int nrec,
+                                         const AdjSeg<T>& sg, const double out_dir[3], double lm,
+                                         double& lA, double& lhw, int& bad, double& sens, const double* maps,
+                                         bool fly = false)
+{
+    double lA_l = lA, lhw_l = lhw, sens_l = sens;
+    int bad_l = bad;
+    adj_reverse_body<T>(s, o, wfb2, C, tp, nrec, sg, out_dir, lm, lA_l, lhw_l, bad_l, sens_l, maps, fly);
+    lA = lA_l;
+    lhw = lhw_l;
+    bad = bad_l;
+    sens = sens_l;
 }
 
 // ---------------------------------------------------------------------------
