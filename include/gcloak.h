@@ -411,7 +411,7 @@ typedef enum {
  * checkpoint and the transposed step Jacobians applied, including the
  * derivative of every event time (partial steps ending on a face or on the
  * grating, straight flights ending on the grating or the box).  The
- * longest FP64 traces (512 or more records) apply each segment's transposed
+ * longest FP64 traces (256 or more records) apply each segment's transposed
  * map instead, formed for all their segments in parallel; the result is
  * the same up to rounding order and does not depend on scheduling.  The result
  * is the derivative of the discrete image, sample by sample; a sample

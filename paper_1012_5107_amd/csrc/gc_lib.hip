@@ -455,12 +455,14 @@ constexpr double kAdjRerunSens = 60.0;
 // Second-pass traces of at least this many tape records (C steps each, or
 // events) are reversed through segment maps formed in parallel
 // (k_adj_maps, k_adj_chain) after the pass, instead of one record after the
-// other on their lane.  Only the longest traces pay for that: a shorter
-// trace's reverse sweep on its lane ends while the longest forward traces
-// still run.  The pool holds at most kAdjPoolRecords records (about
-// 0.9 GB); traces that do not fit reverse on their lane.
-constexpr int kAdjPoolMin = 512;
-constexpr long long kAdjPoolRecords = 1LL << 22;
+// other on their lane.  Only the longer traces pay for that: a shorter
+// trace's reverse sweep on its lane (about three times its forward trace)
+// ends while the longest forward traces still run; below 256 records the
+// maps formed after the pass cost more than they save.  The pool holds at
+// most kAdjPoolRecords records (about 1.9 GB); traces that do not fit
+// reverse on their lane.
+constexpr int kAdjPoolMin = 256;
+constexpr long long kAdjPoolRecords = 1LL << 23;
 
 static gc_status grow(void** p, size_t* have, size_t need, const char* what)
 {
