@@ -433,8 +433,9 @@ typedef enum {
  * start first; hot_steps = steps reversed by the first pass;
  * first_pass_steps = forward steps the first pass took;
  * hot_ms / tail_ms / total_ms the device time of the first pass, of the
- * FP64 passes and of the call).  Device scratch
- * (tapes of up to 8 GiB) is owned by the context.  Synchronises the
+ * FP64 passes and of the call).  Device scratch (tapes of up to 8 GiB per
+ * pass, and once a sample is handed over a pool of 1.9 GB for the longest
+ * traces' tapes and segment maps) is owned by the context.  Synchronises the
  * stream.  GC_EUNSUPPORTED for DOPRI5, flat-mirror scenes or sky_K = inf;
  * GC_EINVAL for a constant reference (or, for NCC, a constant image). */
 gc_status gc_render_grad(gc_ctx* ctx, const gc_scene* scene, const gc_camera* camera, const gc_opts* opts,
