@@ -248,3 +248,21 @@ def test_grad_most_samples_handed_over_is_deterministic(B):
     rel = np.abs(ga - g0) / (np.abs(g0) + 1e-6 * np.abs(g0).max(axis=0))
     print(f"[handed over] C=8 against C=64: max rel {rel.max():.3e} p99 {np.quantile(rel, 0.99):.3e}", flush=True)
     assert np.quantile(rel, 0.99) <= 1e-12 and rel.max() <= 1e-6
+
+
+def test_grad_fp32_two_calls_agree_bit_for_bit(B):
+    """The FP32 gradient with its FP64 hand-over pass (the long traces
+    reversed through segment maps, pooled as lanes reach them) is the same,
+    sample by sample, on two calls: no result depends on which lane took a
+    sample or on the order in which traces reached the pool."""
+    sc, cam, op = W.grad_256()
+    cam = dict(cam, width=128, height=128)
+    ref = torch.from_numpy(_ref(sc, cam, op))
+    ctx = B.context()
+    a = ctx.render_grad(sc, cam, op, ref, prec="f32", sample_dm=True)
+    b = ctx.render_grad(sc, cam, op, ref, prec="f32", sample_dm=True)
+    st = a["stats"]
+    print(f"[fp32 twice] handed over {st['tail_rays']}, of them long {st['rounds']}", flush=True)
+    assert st["tail_rays"] > 0 and st["rounds"] > 0
+    assert np.array_equal(a["sample_dm"].cpu().numpy(), b["sample_dm"].cpu().numpy())
+    assert (a["loss"], a["dA"], a["dhw"]) == (b["loss"], b["dA"], b["dhw"])
