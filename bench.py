@@ -85,9 +85,9 @@ AUTOTUNE_BATCH = {(1e-7, 0.05, 0.3): {"chosen": 36, "candidates": 45, "passed": 
 # adjoint's sources (its kernels, shared device code and orchestration).
 ADJ_KERNEL_SOURCES = ["paper_1012_5107_amd/csrc/gc_adjoint.hpp", "paper_1012_5107_amd/csrc/gc_math.hpp",
                       "paper_1012_5107_amd/csrc/gc_lane64.hpp", "paper_1012_5107_amd/csrc/gc_lib.hip"]
-ADJ_MEASURED_SHA = "a5cf40ee1ab10182"
-TRAFFIC_K_ADJ = {(1e-3, 64): 1.25e11}
-VALU_FLOPS_K_ADJ = {(1e-3, 64): (3.845e10, 0.753)}
+ADJ_MEASURED_SHA = "308b892dd882260b"
+TRAFFIC_K_ADJ = {(1e-3, 64): 1.37e11}
+VALU_FLOPS_K_ADJ = {(1e-3, 64): (3.845e10, 0.751)}
 
 
 def _kernel_sha(sources=None):

@@ -1071,7 +1071,8 @@ __device__ __forceinline__ unsigned long long adj_wave_sum(unsigned long long v)
 // Persistent: each wave claims 64 consecutive samples (neighbouring pixels
 // follow similar paths), traces them forward with tapes and reverses them.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, T wfb2, int C, AdjIo io)
+__device__ __forceinline__ void k_adj_body(const SceneDev& s, const CamDev& cam, const OptsDev& o, T wfb2, int C,
+                                           const AdjIo& io)
 {
     const long long lane = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -1191,6 +1192,23 @@ __global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, 
         atomicAdd(&io.cnt[5], c_rev);
         atomicAdd(&io.cnt[6], c_fwd);
     }
+}
+
+// The adjoint kernel: the FP64 pass (and the FP64 gradient) at one wave
+// per SIMD; the FP32 first pass at two, which its registers allow with
+// some of them spilled (its instruction stream, and so its results, are the
+// same): the pass waits on latency, and the second wave hides part of it.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj(SceneDev s, CamDev cam, OptsDev o, T wfb2, int C, AdjIo io)
+{
+    k_adj_body<T>(s, cam, o, wfb2, C, io);
+}
+
+template <>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_adj<float>(SceneDev s, CamDev cam, OptsDev o, float wfb2, int C, AdjIo io)
+{
+    k_adj_body<float>(s, cam, o, wfb2, C, io);
 }
 
 // Segment maps of the pooled tapes, one RUN or CKPT record per task, all
